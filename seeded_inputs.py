@@ -1,0 +1,83 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+Holds none of the integrand's arithmetic: only numpy random draws of points in
+the unit hypercube and of generic test momenta, so that the HIP path and the
+oracle can be fed identical inputs.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BASE_SEED = 2105105290
+
+
+def ndim(n_final_gluons: int) -> int:
+    """Integration dimensions for g g -> t t~ + n gluons: 3 n_final - 2."""
+    return 3 * (n_final_gluons + 2) - 2
+
+
+def unit_points(n: int, d: int, seed: int = BASE_SEED, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """n points uniformly in (lo, hi)^d, float64, row-major [n][d]."""
+    rng = np.random.default_rng(seed)
+    return lo + (hi - lo) * rng.random((n, d))
+
+
+def points_above_threshold(n: int, d: int, sqrt_s: float, m_t: float, seed: int = BASE_SEED,
+                           margin: float = 1.05) -> np.ndarray:
+    """Points whose x1 x2 S exceeds (margin * 2 m_t)^2, so that every event has kinematics."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((0, d))
+    tau_min = (margin * 2 * m_t / sqrt_s) ** 2
+    while out.shape[0] < n:
+        x = rng.random((2 * n, d))
+        x = x[x[:, 0] * x[:, 1] > tau_min]
+        out = np.concatenate([out, x])
+    return np.ascontiguousarray(out[:n])
+
+
+def edge_points(d: int) -> np.ndarray:
+    """Uniforms at the extremes of (0, 1): the smallest and largest values a Philox draw can give."""
+    lo = 0.5 * 2.0**-53
+    hi = 1.0 - 0.5 * 2.0**-53
+    rows = [np.full(d, 0.5), np.full(d, lo), np.full(d, hi)]
+    mix = np.full(d, 0.5)
+    mix[0] = mix[1] = hi
+    mix[2:] = lo
+    rows.append(mix)
+    mix2 = np.full(d, hi)
+    mix2[2:] = 0.5
+    rows.append(mix2)
+    return np.array(rows)
+
+
+def random_grid(d: int, nb: int = 50, seed: int = BASE_SEED, spread: float = 0.9) -> np.ndarray:
+    """A strictly increasing random VEGAS grid on [0, 1] per dimension, shape [d][nb+1]."""
+    rng = np.random.default_rng(seed)
+    w = 1.0 - spread + spread * rng.random((d, nb)) * 2
+    e = np.concatenate([np.zeros((d, 1)), np.cumsum(w, axis=1)], axis=1)
+    e /= e[:, -1:]
+    e[:, -1] = 1.0
+    return e
+
+
+def boost_matrix(beta: np.ndarray) -> np.ndarray:
+    """4x4 Lorentz boost with velocity vector beta (|beta| < 1)."""
+    b2 = float(beta @ beta)
+    g = 1.0 / np.sqrt(1.0 - b2)
+    L = np.eye(4)
+    L[0, 0] = g
+    L[0, 1:] = L[1:, 0] = g * beta
+    L[1:, 1:] += (g - 1.0) * np.outer(beta, beta) / b2
+    return L
+
+
+def rotation_matrix(seed: int = BASE_SEED) -> np.ndarray:
+    """A random 4x4 spatial rotation."""
+    rng = np.random.default_rng(seed)
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q *= np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    L = np.eye(4)
+    L[1:, 1:] = q
+    return L
