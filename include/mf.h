@@ -1,0 +1,182 @@
+/*
+ * mf.h -- C ABI of the MI355X (gfx950) per-event LO integrand library.
+ *
+ * The library evaluates, entirely in HIP kernels, the event pipeline of a
+ * parton-level Monte Carlo described in arXiv:2105.10529, Sec. 2.1 (random
+ * numbers -> phase-space kinematics with fiducial cuts -> PDFs -> matrix
+ * element -> histogram accumulation for the VEGAS grid), with the helicity
+ * loop and the aggregation of colour-ordered amplitudes of Sec. 2.2.
+ * Processes: g g -> t t~ + 0..3 gluons and q q~ -> t t~ (q = u, d).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns mf_status; MF_OK is 0.  On error a description is
+ *    available from mf_last_error() (thread-local, valid until the next call
+ *    on the same thread).  No C++ exception crosses this interface.
+ *  - Pointers documented as "device" are HIP device pointers (for example
+ *    torch.Tensor.data_ptr() of a cuda tensor); "host" pointers are ordinary
+ *    host memory.  The caller owns every buffer it passes.  The library
+ *    allocates device memory only inside an mf_process handle (tables, the
+ *    VEGAS grid, reduction partials) and frees it in mf_process_destroy.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  Calls taking a stream are asynchronous with respect to the
+ *    host unless stated otherwise.
+ *  - For fixed inputs (seed, event count, configuration) results are
+ *    bitwise reproducible: reductions run in a fixed order.
+ *  - Units: GeV for energies and masses, pb for cross sections.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MF_OK = 0,
+  MF_EINVAL = 1,   /* invalid argument or non-physical configuration */
+  MF_ERANGE = 2,   /* value outside a supported range (grid order, PDF range) */
+  MF_ENOMEM = 3,   /* device allocation failed */
+  MF_EDEVICE = 4,  /* HIP runtime error (launch, copy, synchronisation) */
+  MF_ENOTSUP = 5   /* combination not supported by this build */
+} mf_status;
+
+typedef enum {
+  MF_GG_TTX = 0,     /* g g -> t t~                         (4 dims)  */
+  MF_UUX_TTX = 1,    /* u u~ -> t t~, both beam assignments  (4 dims)  */
+  MF_DDX_TTX = 2,    /* d d~ -> t t~, both beam assignments  (4 dims)  */
+  MF_GG_TTXG = 3,    /* g g -> t t~ g                        (7 dims)  */
+  MF_GG_TTXGG = 4,   /* g g -> t t~ g g                      (10 dims) */
+  MF_GG_TTXGGG = 5   /* g g -> t t~ g g g                    (13 dims) */
+} mf_process_id;
+
+typedef enum {
+  MF_PREC_FP64 = 0,     /* every step in FP64 */
+  MF_PREC_FP32_AMP = 1  /* amplitudes in FP32; kinematics, PDFs, weights
+                           and all accumulations in FP64 */
+} mf_precision;
+
+/* Configuration of one integrand (create-time; immutable afterwards). */
+typedef struct {
+  int32_t process;         /* mf_process_id */
+  int32_t precision;       /* mf_precision */
+  double sqrt_s;           /* hadronic centre-of-mass energy, > 2 m_t */
+  double m_t;              /* top mass, > 0 */
+  double mu;               /* factorisation scale; <= 0 selects mu = m_t */
+  double alpha_s;          /* fixed strong coupling, > 0 */
+  double pt_min;           /* gluon cut pT > pt_min (GeV) */
+  double eta_max;          /* gluon cut |eta| < eta_max (lab frame) */
+  double dr_min;           /* gluon-gluon cut dR > dr_min; <= 0 disables */
+  double pdf_params[20];   /* (A, a, b, c, d) of x f = A x^(a+bL) (1-x)^(c+dL),
+                              L = ln(Q/1.65 GeV), for g, u, d, u~ (d~ = u~) */
+  int32_t n_bins;          /* VEGAS bins per dimension, 1..64 */
+  double alpha;            /* VEGAS refinement damping exponent, > 0 */
+  uint64_t seed;           /* Philox key word 0 for in-library sampling */
+} mf_config;
+
+typedef struct mf_process mf_process;
+
+/* Create an integrand on the current HIP device: validates cfg, tabulates
+ * the PDF grid (196 points uniform in ln x over [1e-9, 1] x 50 points
+ * uniform in ln Q over [1.65, 1e5] GeV) and collapses it at the fixed scale,
+ * allocates the VEGAS grid (uniform).  *out receives the handle.
+ * MF_EINVAL for sqrt_s <= 2 m_t, non-positive masses/couplings, a scale
+ * outside the Q grid or an unknown process; MF_ENOTSUP for a precision the
+ * process does not provide; MF_ENOMEM / MF_EDEVICE on HIP failures. */
+mf_status mf_process_create(const mf_config* cfg, mf_process** out);
+
+/* Release every device allocation of the handle (NULL is accepted). */
+void mf_process_destroy(mf_process* p);
+
+/* Number of integration dimensions: 4, 7, 10 or 13 (3 n_final - 2). */
+int mf_process_ndim(const mf_process* p);
+
+/* Thread-local description of the last error ("" if none). */
+const char* mf_last_error(void);
+
+/* The integrand at caller-supplied points (the phase-space, PDF and matrix
+ * element part of the event pipeline, Sec. 2.1, without the VEGAS map):
+ *   u: device, [ndim][n] FP64 structure of arrays, each value in (0,1):
+ *      u[0], u[1] are the momentum fractions x1, x2; then the n_final-2
+ *      intermediate-mass uniforms; then (cos theta, phi) uniforms per two-body
+ *      split, the t t~ split last.
+ *   w: device, [n] FP64 output: d sigma in pb per unit hypercube volume.
+ *      Zero below threshold or outside the cuts; a non-finite value is
+ *      never written (such events give 0).
+ * n = 0 is accepted and does nothing.  MF_EINVAL for n < 0 or NULL pointers
+ * with n > 0. */
+mf_status mf_integrand(mf_process* p, const double* u, int64_t n, double* w, void* stream);
+
+/* The same integrand and its derivatives (forward mode) at the same points:
+ *   dw: device, [9][n] FP64: d w / d m_t, then d w / d theta_k for
+ *       theta = (A_g, a_g, b_g, c_g, d_g, A_u, A_d, A_u~), i.e. pdf_params
+ *       entries 0..4, 5, 10, 15.  m_t enters the top momenta, the phase-space
+ *       weight, spinors, propagators and (if mu <= 0) the PDF scale.
+ * w may be NULL. */
+mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w, double* dw, void* stream);
+
+/* One VEGAS grid refinement (Lepage 1978) per dimension, on the device:
+ * 3-point smoothing of the bin sums of w^2, damped importance
+ * r_k = [(1 - d_k/D) / ln(D/d_k)]^alpha, new edges holding equal shares of
+ * sum r, linear inside old bins.
+ *   edges: device, [ndim][nbins+1] FP64, in/out, strictly increasing.
+ *   hist:  device, [ndim][nbins] FP64 sums of w^2 per bin (>= 0).
+ * A dimension whose histogram is all zero is left unchanged.  MF_ERANGE if
+ * the result is not strictly increasing (the input grid is then unchanged
+ * for that dimension).  ndim in 1..13, nbins in 1..64.  Takes a 4-byte
+ * status word from the stream-ordered allocator and synchronises `stream`
+ * before returning. */
+mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins, double alpha, void* stream);
+
+typedef struct {
+  int32_t n_iter;                 /* iterations, >= 1 */
+  int64_t n_events;               /* events per iteration, >= 2 */
+  double target_rel_err;          /* stop once error/integral <= this; 0 = off */
+  int32_t warmup_iters_discarded; /* leading iterations left out of the mean */
+  int32_t adapt;                  /* 1: refine the grid after each iteration */
+  uint64_t iter_offset;           /* Philox iteration word of the first iteration */
+  const double* edges_in;         /* device [ndim][nbins+1] start grid, or NULL = current grid */
+  double* edges_out;              /* device [ndim][nbins+1] final grid, or NULL */
+  void* stream;                   /* hipStream_t or NULL */
+} mf_integrate_opts;
+
+typedef struct {
+  double integral;          /* inverse-variance weighted mean (pb) */
+  double error;             /* its standard error */
+  double chi2_dof;          /* chi^2 per degree of freedom of the iterations */
+  int32_t n_iter_done;
+  int64_t n_events_total;
+  int64_t n_nonzero;        /* events with w != 0 */
+  int64_t n_nonfinite;      /* events whose weight was not finite (dropped) */
+  double seconds;           /* wall time of the call */
+  double time_to_target;    /* seconds until error/integral <= target, -1 if never */
+  double kernel_seconds;    /* summed device time of the fused per-event kernel,
+                               from HIP events recorded around each launch on
+                               the call's stream */
+  double* iter_integral;    /* host, length >= n_iter, or NULL */
+  double* iter_error;       /* host, length >= n_iter, or NULL */
+} mf_result;
+
+/* VEGAS integration (Lepage 1978) of the integrand: per iteration, events
+ * e = 0..n_events-1 draw ndim uniforms from Philox4x64-10 with counter
+ * (e, iter_offset + it, call, 0) and key (cfg.seed, 0); the uniforms go
+ * through the grid, the weights w = f * Jacobian are reduced (compensated
+ * FP64 sums of w and w^2) and binned (w^2 per dimension and bin); the grid
+ * is refined on the device.  The handle keeps the final grid.  Blocks until
+ * the result is on the host. */
+mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r);
+
+/* Pathwise Monte Carlo estimate of sigma and its parameter derivatives with
+ * a frozen grid (the current grid of the handle, or o->edges_in): events as
+ * in mf_integrate with iteration word o->iter_offset, o->n_events events.
+ *   out:  host [10]: sigma, d sigma/d m_t, d sigma / d theta_k (k = 0..7)
+ *   err:  host [10]: their Monte Carlo standard errors
+ * Only n_events, iter_offset, edges_in and stream of o are used. */
+mf_status mf_grad(mf_process* p, const mf_integrate_opts* o, double* out, double* err);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_H */

@@ -46,6 +46,7 @@ def lib():
         d, i, i64, u64 = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
         P = ctypes.c_void_p
         L.or_philox4x64_10.argtypes = [P, P, P]
+        L.or_max_threads.restype = ctypes.c_int
         L.or_event_uniforms.argtypes = [u64, u64, u64, u64, u64, i, P]
         L.or_vegas_map.argtypes = [P, i, i, P, P, P]
         L.or_vegas_map.restype = d
@@ -260,6 +261,10 @@ def vegas_refine(edges: np.ndarray, hist: np.ndarray, alpha: float = 1.5) -> np.
     d, nb1 = e.shape
     lib().or_vegas_refine(_ptr(e), _ptr(h), d, nb1 - 1, alpha)
     return e
+
+
+def max_threads() -> int:
+    return lib().or_max_threads()
 
 
 def uniform_edges(d: int, nb: int = 50) -> np.ndarray:

@@ -865,6 +865,14 @@ extern "C" {
 
 int or_version(void) { return 1; }
 
+int or_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 void or_philox4x64_10(const uint64_t* ctr, const uint64_t* key, uint64_t* out) { philox4x64_10(ctr, key, out); }
 
 void or_event_uniforms(uint64_t n, uint64_t ev0, uint64_t it, uint64_t seed, uint64_t purpose, int d, double* u) {

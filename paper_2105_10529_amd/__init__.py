@@ -1,0 +1,271 @@
+"""MI355X (gfx950) per-event LO integrand: thin Python binding of ``libmf.so``.
+
+Argument marshalling only: every step of the event pipeline runs in the HIP
+kernels of the library (``include/mf.h`` documents each entry point).  torch
+supplies device memory and streams.  The library must have been built
+(``python -m paper_2105_10529_amd.build_lib`` or ``__graft_entry__.build()``);
+there is no fallback of any kind when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmf.so")
+
+MF_OK, MF_EINVAL, MF_ERANGE, MF_ENOMEM, MF_EDEVICE, MF_ENOTSUP = range(6)
+PROCESSES = {"gg>ttx": 0, "uux>ttx": 1, "ddx>ttx": 2, "gg>ttxg": 3, "gg>ttxgg": 4, "gg>ttxggg": 5}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+DEFAULT_PDF = (1.6, -0.2, -0.05, 5.0, 0.3,   # g
+               2.2, 0.5, -0.02, 3.0, 0.2,    # u
+               1.1, 0.5, -0.02, 4.0, 0.2,    # d
+               0.2, -0.2, -0.05, 7.0, 0.3)   # u~ (= d~)
+
+
+class MFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"mf status {status}: {msg}")
+        self.status = status
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [
+        ("process", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("sqrt_s", ctypes.c_double),
+        ("m_t", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("alpha_s", ctypes.c_double),
+        ("pt_min", ctypes.c_double),
+        ("eta_max", ctypes.c_double),
+        ("dr_min", ctypes.c_double),
+        ("pdf_params", ctypes.c_double * 20),
+        ("n_bins", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class _IntegrateOpts(ctypes.Structure):
+    _fields_ = [
+        ("n_iter", ctypes.c_int32),
+        ("n_events", ctypes.c_int64),
+        ("target_rel_err", ctypes.c_double),
+        ("warmup_iters_discarded", ctypes.c_int32),
+        ("adapt", ctypes.c_int32),
+        ("iter_offset", ctypes.c_uint64),
+        ("edges_in", ctypes.c_void_p),
+        ("edges_out", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [
+        ("integral", ctypes.c_double),
+        ("error", ctypes.c_double),
+        ("chi2_dof", ctypes.c_double),
+        ("n_iter_done", ctypes.c_int32),
+        ("n_events_total", ctypes.c_int64),
+        ("n_nonzero", ctypes.c_int64),
+        ("n_nonfinite", ctypes.c_int64),
+        ("seconds", ctypes.c_double),
+        ("time_to_target", ctypes.c_double),
+        ("kernel_seconds", ctypes.c_double),
+        ("iter_integral", ctypes.c_void_p),
+        ("iter_error", ctypes.c_void_p),
+    ]
+
+
+EXPORTS = ("mf_process_create", "mf_process_destroy", "mf_process_ndim", "mf_last_error", "mf_integrand",
+           "mf_integrand_grad", "mf_vegas_refine", "mf_integrate", "mf_grad")
+
+_lib = None
+
+
+def lib():
+    """Load libmf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.mf_process_create.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(P)]
+        L.mf_process_create.restype = i32
+        L.mf_process_destroy.argtypes = [P]
+        L.mf_process_destroy.restype = None
+        L.mf_process_ndim.argtypes = [P]
+        L.mf_process_ndim.restype = ctypes.c_int
+        L.mf_last_error.argtypes = []
+        L.mf_last_error.restype = ctypes.c_char_p
+        L.mf_integrand.argtypes = [P, P, i64, P, P]
+        L.mf_integrand.restype = i32
+        L.mf_integrand_grad.argtypes = [P, P, i64, P, P, P]
+        L.mf_integrand_grad.restype = i32
+        L.mf_vegas_refine.argtypes = [P, P, ctypes.c_int, ctypes.c_int, d, P]
+        L.mf_vegas_refine.restype = i32
+        L.mf_integrate.argtypes = [P, ctypes.POINTER(_IntegrateOpts), ctypes.POINTER(_Result)]
+        L.mf_integrate.restype = i32
+        L.mf_grad.argtypes = [P, ctypes.POINTER(_IntegrateOpts), P, P]
+        L.mf_grad.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != MF_OK:
+        raise MFError(status, lib().mf_last_error().decode())
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev_ptr(t, dtype_name="float64") -> int:
+    import torch
+
+    assert t.is_cuda, "device tensor expected"
+    assert t.dtype == getattr(torch, dtype_name), f"{dtype_name} tensor expected"
+    assert t.is_contiguous(), "contiguous tensor expected"
+    return t.data_ptr()
+
+
+@dataclass
+class Config:
+    process: str = "gg>ttx"
+    precision: str = "fp64"
+    sqrt_s: float = 13000.0
+    m_t: float = 173.0
+    mu: float = -1.0
+    alpha_s: float = 0.118
+    pt_min: float = 20.0
+    eta_max: float = 2.5
+    dr_min: float = 0.0
+    pdf_params: tuple = DEFAULT_PDF
+    n_bins: int = 50
+    alpha: float = 1.5
+    seed: int = 2105105290
+
+    def _c(self) -> _Config:
+        c = _Config()
+        c.process = PROCESSES[self.process]
+        c.precision = PRECISIONS[self.precision]
+        c.sqrt_s, c.m_t, c.mu, c.alpha_s = self.sqrt_s, self.m_t, self.mu, self.alpha_s
+        c.pt_min, c.eta_max, c.dr_min = self.pt_min, self.eta_max, self.dr_min
+        for k in range(20):
+            c.pdf_params[k] = float(self.pdf_params[k])
+        c.n_bins, c.alpha, c.seed = self.n_bins, self.alpha, self.seed
+        return c
+
+
+@dataclass
+class IntegrationResult:
+    integral: float
+    error: float
+    chi2_dof: float
+    n_iter_done: int
+    n_events_total: int
+    n_nonzero: int
+    n_nonfinite: int
+    seconds: float
+    time_to_target: float
+    kernel_seconds: float
+    iter_integral: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    iter_error: np.ndarray = field(default_factory=lambda: np.zeros(0))
+
+
+class Process:
+    """An integrand on the current HIP device (mf_process_create)."""
+
+    def __init__(self, cfg: Config | None = None, **kw):
+        self.cfg = cfg if cfg is not None else Config(**kw)
+        h = ctypes.c_void_p()
+        c = self.cfg._c()
+        _check(lib().mf_process_create(ctypes.byref(c), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().mf_process_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ndim(self) -> int:
+        return lib().mf_process_ndim(self._h)
+
+    @property
+    def nbins(self) -> int:
+        return self.cfg.n_bins
+
+    def integrand(self, u, w=None, stream=None):
+        """w[n] = integrand at u ([ndim][n] float64 cuda tensor, SoA) -- mf_integrand."""
+        import torch
+
+        n = u.shape[1] if u.dim() == 2 else 0
+        assert u.dim() == 2 and u.shape[0] == self.ndim
+        if w is None:
+            w = torch.empty(n, dtype=torch.float64, device=u.device)
+        _check(lib().mf_integrand(self._h, _dev_ptr(u), n, _dev_ptr(w), _stream_ptr(stream)))
+        return w
+
+    def integrand_grad(self, u, stream=None):
+        """(w[n], dw[9][n]) -- mf_integrand_grad."""
+        import torch
+
+        n = u.shape[1]
+        w = torch.empty(n, dtype=torch.float64, device=u.device)
+        dw = torch.empty((9, n), dtype=torch.float64, device=u.device)
+        _check(lib().mf_integrand_grad(self._h, _dev_ptr(u), n, _dev_ptr(w), _dev_ptr(dw), _stream_ptr(stream)))
+        return w, dw
+
+    def integrate(self, n_iter: int, n_events: int, target_rel_err: float = 0.0, warmup: int = 0, adapt: bool = True,
+                  iter_offset: int = 0, edges_in=None, edges_out=None, stream=None) -> IntegrationResult:
+        """VEGAS integration entirely on the device -- mf_integrate."""
+        o = _IntegrateOpts()
+        o.n_iter, o.n_events, o.target_rel_err = n_iter, n_events, target_rel_err
+        o.warmup_iters_discarded, o.adapt, o.iter_offset = warmup, int(adapt), iter_offset
+        o.edges_in = _dev_ptr(edges_in) if edges_in is not None else None
+        o.edges_out = _dev_ptr(edges_out) if edges_out is not None else None
+        o.stream = _stream_ptr(stream)
+        r = _Result()
+        Ii = np.zeros(n_iter)
+        Ie = np.zeros(n_iter)
+        r.iter_integral = Ii.ctypes.data
+        r.iter_error = Ie.ctypes.data
+        _check(lib().mf_integrate(self._h, ctypes.byref(o), ctypes.byref(r)))
+        k = r.n_iter_done
+        return IntegrationResult(r.integral, r.error, r.chi2_dof, k, r.n_events_total, r.n_nonzero, r.n_nonfinite,
+                                 r.seconds, r.time_to_target, r.kernel_seconds, Ii[:k].copy(), Ie[:k].copy())
+
+    def grad(self, n_events: int, iter_offset: int = 0, edges_in=None, stream=None):
+        """(values[10], errors[10]): sigma, d sigma/d m_t, d sigma/d theta_0..7 -- mf_grad."""
+        o = _IntegrateOpts()
+        o.n_iter, o.n_events, o.iter_offset = 1, n_events, iter_offset
+        o.edges_in = _dev_ptr(edges_in) if edges_in is not None else None
+        o.stream = _stream_ptr(stream)
+        out = np.zeros(10)
+        err = np.zeros(10)
+        _check(lib().mf_grad(self._h, ctypes.byref(o), out.ctypes.data, err.ctypes.data))
+        return out, err
+
+
+def vegas_refine(edges, hist, alpha: float = 1.5, stream=None):
+    """In-place refinement of a device grid [ndim][nbins+1] from a device histogram -- mf_vegas_refine."""
+    d, nb1 = edges.shape
+    _check(lib().mf_vegas_refine(_dev_ptr(edges), _dev_ptr(hist), d, nb1 - 1, alpha, _stream_ptr(stream)))
+    return edges

@@ -1,0 +1,262 @@
+// Templated per-event kernels of the integrand library (HIP, gfx950),
+// instantiated per process and amplitude precision in the inst_*.hip units
+// and reached from the C ABI through the launcher table of launch.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+#include "pipeline.h"
+
+namespace mf {
+namespace {
+
+// -------------------------------------------------------------- integrand
+template <int NG, int CH, class RA>
+__global__ void __launch_bounds__(BLOCK) k_integrand(DevCfg c, const double* __restrict__ u, int64_t n,
+                                                     double* __restrict__ w) {
+  for (int64_t e = blockIdx.x * (int64_t)BLOCK + threadIdx.x; e < n; e += (int64_t)gridDim.x * BLOCK) {
+    double x[MAXD];
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j)
+      if (j < c.ndim) x[j] = u[(int64_t)j * n + e];
+    EventOut<double> r = event_weight<NG, CH, RA, double>(c, x, c.mt, c.pdfc);
+    w[e] = isfinite(r.w) ? r.w : 0.0;
+  }
+}
+
+// Derivatives of the event weight: m_t by a dual number through phase space
+// and amplitudes, plus the scale derivative of the PDFs when mu = m_t; PDF
+// parameters through the collapsed derivative tables.
+template <int NG, int CH, class RA>
+__device__ __forceinline__ void grad_event(const DevCfg& c, const double* x, double& w, double* dw) {
+  EventOut<Dual<double>> r = event_weight<NG, CH, RA, Dual<double>>(c, x, Dual<double>(c.mt, 1.0), c.pdfc);
+  w = r.w.v;
+  for (int k = 0; k < 9; ++k) dw[k] = 0.0;
+  if (!r.pass) return;
+  dw[0] = r.w.d;
+  if constexpr (CH == 0) {
+    double f1 = hermite_x(c.pdfc, r.t1), f2 = hermite_x(c.pdfc, r.t2);
+    if (c.mu_is_mt) dw[0] += r.r1.v * (hermite_x(c.pdfd, r.t1) * f2 + f1 * hermite_x(c.pdfd, r.t2));
+    for (int k = 0; k < 5; ++k) {
+      const double* T = c.pdft + k * NXK;
+      dw[1 + k] = r.r1.v * (hermite_x(T, r.t1) * f2 + f1 * hermite_x(T, r.t2));
+    }
+  } else {
+    const int fq = CH == 1 ? 1 : 2;
+    const double* Q = c.pdfc + fq * NXK;
+    const double* A = c.pdfc + 3 * NXK;
+    double q1 = hermite_x(Q, r.t1), a2 = hermite_x(A, r.t2), a1 = hermite_x(A, r.t1), q2 = hermite_x(Q, r.t2);
+    if (c.mu_is_mt) {
+      const double* dQ = c.pdfd + fq * NXK;
+      const double* dA = c.pdfd + 3 * NXK;
+      dw[0] += r.r1.v * (hermite_x(dQ, r.t1) * a2 + q1 * hermite_x(dA, r.t2)) +
+               r.r2.v * (hermite_x(dA, r.t1) * q2 + a1 * hermite_x(dQ, r.t2));
+    }
+    const double* TQ = c.pdft + (CH == 1 ? 5 : 6) * NXK;
+    const double* TA = c.pdft + 7 * NXK;
+    dw[CH == 1 ? 6 : 7] = r.r1.v * (hermite_x(TQ, r.t1) * a2) + r.r2.v * (a1 * hermite_x(TQ, r.t2));
+    dw[8] = r.r1.v * (q1 * hermite_x(TA, r.t2)) + r.r2.v * (hermite_x(TA, r.t1) * q2);
+  }
+}
+
+template <int NG, int CH, class RA>
+__global__ void __launch_bounds__(BLOCK) k_integrand_grad(DevCfg c, const double* __restrict__ u, int64_t n,
+                                                          double* __restrict__ w, double* __restrict__ dw) {
+  for (int64_t e = blockIdx.x * (int64_t)BLOCK + threadIdx.x; e < n; e += (int64_t)gridDim.x * BLOCK) {
+    double x[MAXD];
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j)
+      if (j < c.ndim) x[j] = u[(int64_t)j * n + e];
+    double ww, d[9];
+    grad_event<NG, CH, RA>(c, x, ww, d);
+    bool ok = isfinite(ww);
+    for (int k = 0; k < 9; ++k) ok = ok && isfinite(d[k]);
+    if (w) w[e] = ok ? ww : 0.0;
+    for (int k = 0; k < 9; ++k) dw[(int64_t)k * n + e] = ok ? d[k] : 0.0;
+  }
+}
+
+// ----------------------------------------------------- fused VEGAS iteration
+template <int NG, int CH, class RA>
+__global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restrict__ edges_g, uint64_t iter,
+                                                 int64_t N, uint64_t seed, double* __restrict__ partials,
+                                                 int pstride) {
+  extern __shared__ double lds[];
+  const int d = c.ndim, nb = c.nb;
+  double* edges = lds;                             // d*(nb+1)
+  double* pdf = edges + d * (nb + 1);              // 4*196
+  double* hist = pdf + 4 * NXK;                    // WAVES*d*nb
+  double* w2s = hist + WAVES * d * nb;             // BLOCK
+  unsigned char* bins_s = (unsigned char*)(w2s + BLOCK);  // d*BLOCK
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < d * (nb + 1); i += BLOCK) edges[i] = edges_g[i];
+  for (int i = tid; i < 4 * NXK; i += BLOCK) pdf[i] = c.pdfc[i];
+  for (int i = tid; i < WAVES * d * nb; i += BLOCK) hist[i] = 0.0;
+  __syncthreads();
+  DevCfg cl = c;
+  cl.pdfc = pdf;
+  KSum s1{0.0, 0.0}, s2{0.0, 0.0};
+  int nnz = 0, nbad = 0;
+  double* my_hist = hist + wave * d * nb;
+  for (int64_t base = (int64_t)blockIdx.x * BLOCK + wave * 64; base < N; base += (int64_t)gridDim.x * BLOCK) {
+    int64_t e = base + lane;
+    double w = 0.0;
+    int bins[MAXD];
+    if (e < N) {
+      double y[MAXD], x[MAXD];
+      event_uniforms((uint64_t)e, iter, seed, 0, d, y);
+      double jac = 1.0;
+#pragma unroll
+      for (int j = 0; j < MAXD; ++j)
+        if (j < d) x[j] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], bins[j], jac);
+      EventOut<double> r = event_weight<NG, CH, RA, double>(cl, x, c.mt, pdf);
+      w = r.w * jac;
+      if (!isfinite(w)) {
+        w = 0.0;
+        ++nbad;
+      }
+      nnz += (w != 0.0);
+      kadd(s1, w);
+      kadd(s2, w * w);
+    } else {
+#pragma unroll
+      for (int j = 0; j < MAXD; ++j) bins[j] = 0;
+    }
+    // stage this wave's 64 events, then d lanes bin them in event order
+    w2s[tid] = w * w;
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j)
+      if (j < d) bins_s[j * BLOCK + tid] = (unsigned char)bins[j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < d) {
+      const unsigned char* bj = bins_s + lane * BLOCK + wave * 64;
+      const double* ws = w2s + wave * 64;
+      double* hj = my_hist + lane * nb;
+      for (int k = 0; k < 64; ++k) hj[bj[k]] += ws[k];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();
+  // combine the wave histograms in wave order, then the compensated sums in
+  // thread order (a fixed order: the partials are bitwise reproducible)
+  double* p = partials + (int64_t)blockIdx.x * pstride;
+  for (int i = tid; i < d * nb; i += BLOCK) {
+    double h = 0.0;
+    for (int v = 0; v < WAVES; ++v) h += hist[v * d * nb + i];
+    p[PART_HEAD + i] = h;
+  }
+  __syncthreads();
+  double vals[4] = {s1.s, -s1.c, s2.s, -s2.c};
+  double acc_hi[2] = {0.0, 0.0}, acc_lo[2] = {0.0, 0.0};
+  for (int q = 0; q < 4; ++q) {
+    w2s[tid] = vals[q];
+    __syncthreads();
+    if (tid == 0) {
+      int slot = q >> 1;
+      for (int t = 0; t < BLOCK; ++t) dd_add(acc_hi[slot], acc_lo[slot], w2s[t]);
+    }
+    __syncthreads();
+  }
+  // counts
+  int* ci = (int*)w2s;
+  ci[tid] = nnz;
+  ci[BLOCK + tid] = nbad;
+  __syncthreads();
+  if (tid == 0) {
+    long long tn = 0, tb = 0;
+    for (int t = 0; t < BLOCK; ++t) {
+      tn += ci[t];
+      tb += ci[BLOCK + t];
+    }
+    p[0] = acc_hi[0];
+    p[1] = acc_lo[0];
+    p[2] = acc_hi[1];
+    p[3] = acc_lo[1];
+    p[4] = (double)tn;
+    p[5] = (double)tb;
+  }
+}
+
+// ------------------------------------------------- gradient estimator
+template <int NG, int CH, class RA>
+__global__ void __launch_bounds__(BLOCK) k_grad_vegas(DevCfg c, const double* __restrict__ edges_g, uint64_t iter,
+                                                      int64_t N, uint64_t seed, double* __restrict__ partials) {
+  extern __shared__ double lds[];
+  const int d = c.ndim, nb = c.nb;
+  double* edges = lds;
+  for (int i = threadIdx.x; i < d * (nb + 1); i += BLOCK) edges[i] = edges_g[i];
+  __syncthreads();
+  KSum s[GV];
+  double sq[GV];
+  for (int k = 0; k < GV; ++k) {
+    s[k] = KSum{0.0, 0.0};
+    sq[k] = 0.0;
+  }
+  for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < N; e += (int64_t)gridDim.x * BLOCK) {
+    double y[MAXD], x[MAXD];
+    int bins[MAXD];
+    event_uniforms((uint64_t)e, iter, seed, 0, d, y);
+    double jac = 1.0;
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j)
+      if (j < d) x[j] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], bins[j], jac);
+    double v[GV];
+    grad_event<NG, CH, RA>(c, x, v[0], v + 1);
+    bool ok = true;
+    for (int k = 0; k < GV; ++k) ok = ok && isfinite(v[k]);
+    for (int k = 0; k < GV; ++k) {
+      double t = ok ? v[k] * jac : 0.0;
+      kadd(s[k], t);
+      sq[k] += t * t;
+    }
+  }
+  __shared__ double red[BLOCK];
+  double* p = partials + (int64_t)blockIdx.x * (3 * GV);
+  for (int k = 0; k < GV; ++k) {
+    for (int q = 0; q < 3; ++q) {
+      red[threadIdx.x] = q == 0 ? s[k].s : (q == 1 ? -s[k].c : sq[k]);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double hi = 0.0, lo = 0.0;
+        for (int t = 0; t < BLOCK; ++t) dd_add(hi, lo, red[t]);
+        p[3 * k + q] = hi + lo;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace
+
+// Launcher table of one (final gluons, channel, amplitude type) instance;
+// GRAD = 0 leaves the derivative kernels out.
+template <int NG, int CH, class RA, class RD, int GRAD>
+Launchers make_launchers() {
+  Launchers L;
+  L.integrand = [](const DevCfg& c, const double* u, int64_t n, double* w, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL((k_integrand<NG, CH, RA>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w);
+  };
+  L.vegas = [](const DevCfg& c, const double* edges, uint64_t iter, int64_t N, uint64_t seed, double* part,
+               int pstride, int nblk, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((k_vegas<NG, CH, RA>), dim3(nblk), dim3(BLOCK), lds, s, c, edges, iter, N, seed, part, pstride);
+  };
+  L.integrand_grad = nullptr;
+  L.grad_vegas = nullptr;
+  if constexpr (GRAD != 0) {
+    L.integrand_grad = [](const DevCfg& c, const double* u, int64_t n, double* w, double* dw, int nblk,
+                          hipStream_t s) {
+      hipLaunchKernelGGL((k_integrand_grad<NG, CH, RD>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w, dw);
+    };
+    L.grad_vegas = [](const DevCfg& c, const double* edges, uint64_t iter, int64_t N, uint64_t seed, double* part,
+                      int nblk, size_t lds, hipStream_t s) {
+      hipLaunchKernelGGL((k_grad_vegas<NG, CH, RD>), dim3(nblk), dim3(BLOCK), lds, s, c, edges, iter, N, seed, part);
+    };
+  }
+  return L;
+}
+
+}  // namespace mf

@@ -1,0 +1,60 @@
+// Launcher table: the C ABI reaches the templated kernels of one process
+// instance through these function pointers (one translation unit per
+// instance keeps compilation parallel).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pipeline.h"
+
+namespace mf {
+
+constexpr int BLOCK = 256;
+constexpr int WAVES = BLOCK / 64;
+constexpr int MAX_BLOCKS = 2048;
+constexpr int PART_HEAD = 8;  // S1 hi, S1 lo, S2 hi, S2 lo, nonzero, nonfinite, pad, pad
+constexpr int GV = 10;        // w, dw/dm_t, dw/dtheta_0..7
+
+// ---------------------------------------------------- compensated sums
+struct KSum {
+  double s, c;  // Kahan: the exact sum is approximately s - c
+};
+__device__ __forceinline__ void kadd(KSum& k, double v) {
+  double y = v - k.c;
+  double t = k.s + y;
+  k.c = (t - k.s) - y;
+  k.s = t;
+}
+// Error-free two-sum: a + b = s + e exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+// Double-double accumulate (hi, lo) += v.
+__device__ __forceinline__ void dd_add(double& hi, double& lo, double v) {
+  double s, e;
+  two_sum(hi, v, s, e);
+  lo += e;
+  two_sum(s, lo, hi, lo);
+}
+
+struct Launchers {
+  void (*integrand)(const DevCfg&, const double*, int64_t, double*, int, hipStream_t);
+  void (*integrand_grad)(const DevCfg&, const double*, int64_t, double*, double*, int, hipStream_t);
+  void (*vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, int, size_t, hipStream_t);
+  void (*grad_vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, size_t, hipStream_t);
+};
+
+// One per built instance: g g -> t t~ + ng g in FP64 / FP32 amplitudes, and
+// the quark channels in FP64.
+Launchers launchers_gg0_f64();
+Launchers launchers_gg0_f32();
+Launchers launchers_gg1_f64();
+Launchers launchers_gg1_f32();
+Launchers launchers_gg2_f64();
+Launchers launchers_gg2_f32();
+Launchers launchers_uu_f64();
+Launchers launchers_dd_f64();
+
+}  // namespace mf

@@ -1,0 +1,564 @@
+// Kernels and the C ABI of the per-event LO integrand library (gfx950).
+//
+// Kernels (one event per lane):
+//   k_pdf_setup      tabulate the synthetic PDFs on the 196 x-knots and collapse
+//                    the Q direction at the fixed scale (value, d/dmu, d/dtheta)
+//   k_integrand      the integrand at caller-supplied points
+//   k_integrand_grad the integrand and its forward-mode derivatives
+//   k_vegas          one fused VEGAS iteration: Philox -> map -> phase space ->
+//                    cuts -> PDFs -> |M|^2 -> weight -> compensated sums and
+//                    per-wave grid histograms -> per-block partials
+//   k_finalize       ordered reduction of the partials, iteration estimate,
+//                    on-device grid refinement
+//   k_refine         grid refinement alone
+//   k_grad_vegas / k_grad_finalize   pathwise derivative estimates
+// Sec. 2.1 of arXiv:2105.10529 describes the pipeline; Sec. 3.1 notes that
+// everything stays in GPU memory, which is also the design here: one VEGAS
+// iteration moves a few KB between host and device.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mf.h"
+#include "launch.h"
+#include "pipeline.h"
+
+using namespace mf;
+
+namespace {
+
+thread_local std::string g_err;
+
+mf_status fail(mf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(MF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int REC = 8;        // per-iteration record: I, sigma, S1, S2, nonzero, nonfinite, status, pad
+
+struct PdfParams {
+  double p[20];
+};
+
+// ------------------------------------------------------------ PDF tables
+__device__ double pdf_formula(const double* p5, double x, double L, int dpar) {
+  if (!(x < 1.0)) return 0.0;
+  double lx = log(x), l1x = log1p(-x);
+  double v = p5[0] * exp((p5[1] + p5[2] * L) * lx + (p5[3] + p5[4] * L) * l1x);
+  switch (dpar) {
+    case 0: return v / p5[0];
+    case 1: return v * lx;
+    case 2: return v * L * lx;
+    case 3: return v * l1x;
+    case 4: return v * L * l1x;
+    default: return v;
+  }
+}
+
+// One thread per (flavour, x knot): Hermite in ln Q at mu of the tabulated
+// values (and of the parameter derivatives), with its mu derivative.
+__global__ void k_pdf_setup(PdfParams P, double mu, double* pdfc, double* pdfd, double* pdft) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * NXK) return;
+  int f = t / NXK, i = t % NXK;
+  double x = pow(10.0, -9.0 + 9.0 * i / 195.0);
+  double hq = (log(PDF_QMAX) - log(PDF_Q0)) / (NQK - 1);
+  double tq = (log(mu) - log(PDF_Q0)) / hq;
+  int j = (int)floor(tq);
+  j = j < 0 ? 0 : (j > NQK - 2 ? NQK - 2 : j);
+  double u = tq - j;
+  double u2 = u * u, u3 = u2 * u;
+  double h00 = 2 * u3 - 3 * u2 + 1, h10 = u3 - 2 * u2 + u, h01 = -2 * u3 + 3 * u2, h11 = u3 - u2;
+  double d00 = 6 * u2 - 6 * u, d10 = 3 * u2 - 4 * u + 1, d01 = -6 * u2 + 6 * u, d11 = 3 * u2 - 2 * u;
+  // theta_k -> (flavour, parameter): A_g a_g b_g c_g d_g A_u A_d A_u~
+  const int tf[8] = {0, 0, 0, 0, 0, 1, 2, 3}, tp[8] = {0, 1, 2, 3, 4, 0, 0, 0};
+  for (int which = -1; which < 8; ++which) {
+    if (which >= 0 && tf[which] != f) continue;
+    int dpar = which < 0 ? -1 : tp[which];
+    double F[4];
+    for (int r = 0; r < 4; ++r) {
+      int jj = j - 1 + r;
+      jj = jj < 0 ? 0 : (jj > NQK - 1 ? NQK - 1 : jj);
+      double Q = PDF_Q0 * pow(PDF_QMAX / PDF_Q0, jj / 49.0);
+      F[r] = pdf_formula(P.p + 5 * f, x, log(Q / PDF_Q0), dpar);
+    }
+    // F[1] = row j, F[2] = row j+1
+    double s0 = (j == 0) ? F[2] - F[1] : 0.5 * (F[2] - F[0]);
+    double s1 = (j + 1 == NQK - 1) ? F[2] - F[1] : 0.5 * (F[3] - F[1]);
+    double v = h00 * F[1] + h10 * s0 + h01 * F[2] + h11 * s1;
+    if (which < 0) {
+      pdfc[f * NXK + i] = v;
+      pdfd[f * NXK + i] = (d00 * F[1] + d10 * s0 + d01 * F[2] + d11 * s1) / (hq * mu);
+    } else {
+      pdft[which * NXK + i] = v;
+    }
+  }
+}
+
+__global__ void k_fill_uniform(double* edges, int d, int nb) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d * (nb + 1)) return;
+  int k = t % (nb + 1);
+  edges[t] = (double)k / nb;
+}
+
+// -------------------------------------------------------- refinement
+// Lepage's refinement of one dimension, serial over bins (50-ish), FP64.
+// Returns false (and leaves e unchanged) if the new edges are not strictly
+// increasing.
+__device__ bool refine_dim(double* e, const double* h, int nb, double alpha, double* scratch) {
+  double* dsm = scratch;       // nb
+  double* r = scratch + nb;    // nb
+  double* ne = scratch + 2 * nb;  // nb+1
+  if (nb == 1) dsm[0] = h[0];
+  else {
+    dsm[0] = 0.5 * (h[0] + h[1]);
+    dsm[nb - 1] = 0.5 * (h[nb - 2] + h[nb - 1]);
+    for (int k = 1; k < nb - 1; ++k) dsm[k] = (h[k - 1] + h[k] + h[k + 1]) / 3.0;
+  }
+  double D = 0.0;
+  for (int k = 0; k < nb; ++k) D += dsm[k];
+  if (!(D > 0.0)) return true;
+  double Rs = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    double rk = 0.0;
+    if (dsm[k] > 0.0) {
+      double q = dsm[k] / D;
+      rk = (q < 1.0) ? pow((1.0 - q) / log(1.0 / q), alpha) : 0.0;
+    }
+    r[k] = rk;
+    Rs += rk;
+  }
+  if (!(Rs > 0.0)) return true;
+  double per = Rs / nb;
+  ne[0] = e[0];
+  ne[nb] = e[nb];
+  int k = 0;
+  double acc = 0.0;
+  for (int i = 1; i < nb; ++i) {
+    double target = per * i;
+    while (k < nb && acc + r[k] < target) {
+      acc += r[k];
+      ++k;
+    }
+    ne[i] = (k >= nb) ? e[nb] : e[k] + (target - acc) / r[k] * (e[k + 1] - e[k]);
+  }
+  for (int i = 0; i < nb; ++i)
+    if (!(ne[i + 1] > ne[i])) return false;
+  for (int i = 0; i <= nb; ++i) e[i] = ne[i];
+  return true;
+}
+
+__global__ void k_refine(double* edges, const double* hist, int d, int nb, double alpha, int* status) {
+  __shared__ double scratch[3 * MAX_BINS + 1];
+  int j = blockIdx.x;
+  if (threadIdx.x == 0 && j < d) {
+    bool ok = refine_dim(edges + j * (nb + 1), hist + j * nb, nb, alpha, scratch);
+    if (!ok) status[0] = 1;
+  }
+}
+
+// Ordered reduction of the block partials of one iteration; writes the
+// iteration record and (if adapt) refines the grid in place.
+__global__ void k_finalize(const double* partials, int nblk, int pstride, int d, int nb, int64_t N, double alpha,
+                           int adapt, double* edges, double* rec, double* hist_out) {
+  __shared__ double hsum[MAXD * MAX_BINS];
+  __shared__ double scratch[MAXD][3 * MAX_BINS + 1];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < d * nb; i += blockDim.x) {
+    double h = 0.0;
+    for (int b = 0; b < nblk; ++b) h += partials[(int64_t)b * pstride + PART_HEAD + i];
+    hsum[i] = h;
+    if (hist_out) hist_out[i] = h;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double h1 = 0.0, l1 = 0.0, h2 = 0.0, l2 = 0.0, nz = 0.0, bad = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      const double* p = partials + (int64_t)b * pstride;
+      dd_add(h1, l1, p[0]);
+      dd_add(h1, l1, p[1]);
+      dd_add(h2, l2, p[2]);
+      dd_add(h2, l2, p[3]);
+      nz += p[4];
+      bad += p[5];
+    }
+    double S1 = h1 + l1, S2 = h2 + l2;
+    double I = S1 / (double)N;
+    double var = (S2 / (double)N - I * I) / (double)(N - 1);
+    rec[0] = I;
+    rec[1] = sqrt(var > 0.0 ? var : 0.0);
+    rec[2] = S1;
+    rec[3] = S2;
+    rec[4] = nz;
+    rec[5] = bad;
+    rec[6] = 0.0;
+  }
+  __syncthreads();
+  if (adapt && tid < d) {
+    bool ok = refine_dim(edges + tid * (nb + 1), hsum + tid * nb, nb, alpha, scratch[tid]);
+    if (!ok) rec[6] = 1.0;
+  }
+}
+
+__global__ void k_grad_finalize(const double* partials, int nblk, int64_t N, double* out) {
+  int k = threadIdx.x;
+  if (k >= GV) return;
+  double hi = 0.0, lo = 0.0, q = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    dd_add(hi, lo, partials[(int64_t)b * 3 * GV + 3 * k]);
+    dd_add(hi, lo, partials[(int64_t)b * 3 * GV + 3 * k + 1]);
+    q += partials[(int64_t)b * 3 * GV + 3 * k + 2];
+  }
+  double mean = (hi + lo) / (double)N;
+  double var = (q / (double)N - mean * mean) / (double)(N - 1);
+  out[k] = mean;
+  out[GV + k] = sqrt(var > 0.0 ? var : 0.0);
+}
+
+}  // namespace
+
+// ============================================================== host side
+struct mf_process {
+  mf_config cfg;
+  DevCfg dc;
+  int device;
+  int ndim, nb;
+  double* d_pdf = nullptr;      // pdfc | pdfd | pdft
+  double* d_edges = nullptr;    // ndim*(nb+1)
+  double* d_part = nullptr;     // MAX_BLOCKS * pstride
+  double* d_rec = nullptr;      // per-iteration records
+  double* d_hist = nullptr;     // last histogram
+  double* d_out = nullptr;      // small outputs
+  int* d_status = nullptr;
+  int pstride;
+  int rec_cap;
+  Launchers L;
+};
+
+namespace {
+
+int n_final_gluons(int proc) {
+  switch (proc) {
+    case MF_GG_TTXG: return 1;
+    case MF_GG_TTXGG: return 2;
+    case MF_GG_TTXGGG: return 3;
+    default: return 0;
+  }
+}
+int channel_of(int proc) { return proc == MF_UUX_TTX ? 1 : (proc == MF_DDX_TTX ? 2 : 0); }
+
+double factorial(int n) {
+  double f = 1;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+int blocks_for(int64_t n) {
+  int64_t b = (n + BLOCK - 1) / BLOCK;
+  if (b < 1) b = 1;
+  if (b > MAX_BLOCKS) b = MAX_BLOCKS;
+  return (int)b;
+}
+
+size_t vegas_lds_bytes(int d, int nb) {
+  return sizeof(double) * (size_t)(d * (nb + 1) + 4 * NXK + WAVES * d * nb + BLOCK) + (size_t)d * BLOCK;
+}
+
+Launchers pick_launchers(int ng, int ch, int prec) {
+  const bool f32 = prec == MF_PREC_FP32_AMP;
+  if (ch == 1) return launchers_uu_f64();
+  if (ch == 2) return launchers_dd_f64();
+  if (ng == 0) return f32 ? launchers_gg0_f32() : launchers_gg0_f64();
+  if (ng == 1) return f32 ? launchers_gg1_f32() : launchers_gg1_f64();
+  return f32 ? launchers_gg2_f32() : launchers_gg2_f64();
+}
+
+mf_status check_stream_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MF_EDEVICE, "%s launch: %s", what, hipGetErrorString(e));
+  return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mf_last_error(void) { return g_err.c_str(); }
+
+int mf_process_ndim(const mf_process* p) { return p ? p->ndim : 0; }
+
+mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
+  g_err.clear();
+  if (!cfg || !out) return fail(MF_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (cfg->process < MF_GG_TTX || cfg->process > MF_GG_TTXGGG) return fail(MF_EINVAL, "unknown process %d", cfg->process);
+  if (cfg->precision != MF_PREC_FP64 && cfg->precision != MF_PREC_FP32_AMP)
+    return fail(MF_EINVAL, "unknown precision %d", cfg->precision);
+  if (!(cfg->m_t > 0.0)) return fail(MF_EINVAL, "m_t must be positive");
+  if (!(cfg->sqrt_s > 2.0 * cfg->m_t)) return fail(MF_EINVAL, "sqrt_s must exceed 2 m_t");
+  if (!(cfg->alpha_s > 0.0)) return fail(MF_EINVAL, "alpha_s must be positive");
+  if (!(cfg->alpha > 0.0)) return fail(MF_EINVAL, "VEGAS alpha must be positive");
+  if (cfg->n_bins < 1 || cfg->n_bins > MAX_BINS) return fail(MF_EINVAL, "n_bins must be in 1..%d", MAX_BINS);
+  double mu = cfg->mu > 0.0 ? cfg->mu : cfg->m_t;
+  if (!(mu >= PDF_Q0 && mu <= PDF_QMAX)) return fail(MF_ERANGE, "scale %g outside the PDF grid", mu);
+  const int ng = n_final_gluons(cfg->process);
+  if (ng == 3) return fail(MF_ENOTSUP, "g g -> t t~ g g g is not built");
+  if (channel_of(cfg->process) != 0 && cfg->precision != MF_PREC_FP64)
+    return fail(MF_ENOTSUP, "quark channels are built in FP64 only");
+  for (int i = 0; i < 20; i += 5)
+    if (!(cfg->pdf_params[i] > 0.0)) return fail(MF_EINVAL, "PDF normalisation %d must be positive", i / 5);
+
+  mf_process* p = new mf_process();
+  p->cfg = *cfg;
+  hipGetDevice(&p->device);
+  p->ndim = 3 * (ng + 2) - 2;
+  p->nb = cfg->n_bins;
+  DevCfg& c = p->dc;
+  c.ng = ng;
+  c.channel = channel_of(cfg->process);
+  c.ndim = p->ndim;
+  c.nb = p->nb;
+  c.s = cfg->sqrt_s * cfg->sqrt_s;
+  c.mt = cfg->m_t;
+  c.mu = mu;
+  c.mu_is_mt = cfg->mu > 0.0 ? 0 : 1;
+  c.pt_min = cfg->pt_min;
+  c.eta_max = cfg->eta_max;
+  c.dr_min = cfg->dr_min;
+  c.lx0 = std::log(std::pow(10.0, -9.0));
+  c.ihx = (NXK - 1) / (0.0 - c.lx0);
+  double g2 = 4.0 * M_PI * cfg->alpha_s;
+  if (c.channel == 0) c.norm = std::pow(g2, ng + 2) / 256.0 / factorial(ng) * GEV2_PB;
+  else c.norm = g2 * g2 / 36.0 * GEV2_PB;
+  p->L = pick_launchers(ng, c.channel, cfg->precision);
+  p->pstride = PART_HEAD + p->ndim * p->nb;
+  p->rec_cap = 4096;
+  auto cleanup = [&](mf_status s) {
+    mf_process_destroy(p);
+    return s;
+  };
+  if (hipMalloc(&p->d_pdf, sizeof(double) * 16 * NXK) != hipSuccess ||
+      hipMalloc(&p->d_edges, sizeof(double) * p->ndim * (p->nb + 1)) != hipSuccess ||
+      hipMalloc(&p->d_part, sizeof(double) * (size_t)MAX_BLOCKS * std::max(p->pstride, 3 * GV)) != hipSuccess ||
+      hipMalloc(&p->d_rec, sizeof(double) * REC * p->rec_cap) != hipSuccess ||
+      hipMalloc(&p->d_hist, sizeof(double) * p->ndim * p->nb) != hipSuccess ||
+      hipMalloc(&p->d_out, sizeof(double) * 64) != hipSuccess ||
+      hipMalloc(&p->d_status, sizeof(int) * 4) != hipSuccess) {
+    hipGetLastError();
+    return cleanup(fail(MF_ENOMEM, "device allocation failed"));
+  }
+  c.pdfc = p->d_pdf;
+  c.pdfd = p->d_pdf + 4 * NXK;
+  c.pdft = p->d_pdf + 8 * NXK;
+  PdfParams P;
+  for (int i = 0; i < 20; ++i) P.p[i] = cfg->pdf_params[i];
+  hipLaunchKernelGGL(k_pdf_setup, dim3((4 * NXK + 255) / 256), dim3(256), 0, 0, P, mu, p->d_pdf, p->d_pdf + 4 * NXK,
+                     p->d_pdf + 8 * NXK);
+  hipLaunchKernelGGL(k_fill_uniform, dim3((p->ndim * (p->nb + 1) + 255) / 256), dim3(256), 0, 0, p->d_edges,
+                     p->ndim, p->nb);
+  if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(MF_EDEVICE, "table set-up failed"));
+  *out = p;
+  return MF_OK;
+}
+
+void mf_process_destroy(mf_process* p) {
+  if (!p) return;
+  hipFree(p->d_pdf);
+  hipFree(p->d_edges);
+  hipFree(p->d_part);
+  hipFree(p->d_rec);
+  hipFree(p->d_hist);
+  hipFree(p->d_out);
+  hipFree(p->d_status);
+  delete p;
+}
+
+mf_status mf_integrand(mf_process* p, const double* u, int64_t n, double* w, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MF_EINVAL, "NULL process");
+  if (n < 0) return fail(MF_EINVAL, "negative event count");
+  if (n == 0) return MF_OK;
+  if (!u || !w) return fail(MF_EINVAL, "NULL buffer");
+  hipStream_t s = (hipStream_t)stream;
+  const int nblk = blocks_for(n);
+  p->L.integrand(p->dc, u, n, w, nblk, s);
+  return check_stream_launch("k_integrand");
+}
+
+mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w, double* dw, void* stream) {
+  g_err.clear();
+  if (!p) return fail(MF_EINVAL, "NULL process");
+  if (n < 0) return fail(MF_EINVAL, "negative event count");
+  if (n == 0) return MF_OK;
+  if (!u || !dw) return fail(MF_EINVAL, "NULL buffer");
+  hipStream_t s = (hipStream_t)stream;
+  const int nblk = blocks_for(n);
+  if (!p->L.integrand_grad) return fail(MF_ENOTSUP, "derivatives are not built for this process");
+  p->L.integrand_grad(p->dc, u, n, w, dw, nblk, s);
+  return check_stream_launch("k_integrand_grad");
+}
+
+mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins, double alpha, void* stream) {
+  g_err.clear();
+  if (!edges || !hist) return fail(MF_EINVAL, "NULL buffer");
+  if (ndim < 1 || ndim > MAXD) return fail(MF_EINVAL, "ndim must be in 1..%d", MAXD);
+  if (nbins < 1 || nbins > MAX_BINS) return fail(MF_EINVAL, "nbins must be in 1..%d", MAX_BINS);
+  if (!(alpha > 0.0)) return fail(MF_EINVAL, "alpha must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  int* st = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&st, sizeof(int), s));
+  HIP_TRY(hipMemsetAsync(st, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_refine, dim3(ndim), dim3(64), 0, s, edges, hist, ndim, nbins, alpha, st);
+  int hs = 0;
+  HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipFreeAsync(st, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hs) return fail(MF_ERANGE, "refined grid not strictly increasing; dimension left unchanged");
+  return MF_OK;
+}
+
+mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) {
+  g_err.clear();
+  if (!p || !o || !r) return fail(MF_EINVAL, "NULL argument");
+  if (o->n_iter < 1 || o->n_iter > p->rec_cap) return fail(MF_EINVAL, "n_iter must be in 1..%d", p->rec_cap);
+  if (o->n_events < 2) return fail(MF_EINVAL, "n_events must be >= 2");
+  if (o->warmup_iters_discarded < 0 || o->warmup_iters_discarded >= o->n_iter)
+    return fail(MF_EINVAL, "warmup_iters_discarded must be in 0..n_iter-1");
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = (hipStream_t)o->stream;
+  const int d = p->ndim, nb = p->nb;
+  if (o->edges_in) HIP_TRY(hipMemcpyAsync(p->d_edges, o->edges_in, sizeof(double) * d * (nb + 1),
+                                          hipMemcpyDeviceToDevice, s));
+  const int nblk = blocks_for(o->n_events);
+  const size_t lds = vegas_lds_bytes(d, nb);
+  std::vector<double> rec((size_t)REC * o->n_iter, 0.0);
+  double time_to_target = -1.0;
+  int done = 0;
+  std::vector<hipEvent_t> ev(2 * (size_t)o->n_iter);
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  struct EvGuard {
+    std::vector<hipEvent_t>& v;
+    ~EvGuard() {
+      for (auto& e : v) (void)hipEventDestroy(e);
+    }
+  } guard{ev};
+  double sw = 0.0, swi = 0.0;
+  for (int it = 0; it < o->n_iter; ++it) {
+    const uint64_t iter = o->iter_offset + (uint64_t)it;
+    HIP_TRY(hipEventRecord(ev[2 * it], s));
+    p->L.vegas(p->dc, p->d_edges, iter, o->n_events, p->cfg.seed, p->d_part, p->pstride, nblk, lds, s);
+    HIP_TRY(hipEventRecord(ev[2 * it + 1], s));
+    mf_status st = check_stream_launch("k_vegas");
+    if (st != MF_OK) return st;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, p->d_part, nblk, p->pstride, d, nb, o->n_events,
+                       p->cfg.alpha, o->adapt ? 1 : 0, p->d_edges, p->d_rec + (size_t)REC * it, p->d_hist);
+    st = check_stream_launch("k_finalize");
+    if (st != MF_OK) return st;
+    done = it + 1;
+    if (o->target_rel_err > 0.0) {
+      HIP_TRY(hipMemcpyAsync(rec.data() + (size_t)REC * it, p->d_rec + (size_t)REC * it, sizeof(double) * REC,
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      const double* q = rec.data() + (size_t)REC * it;
+      if (it >= o->warmup_iters_discarded && q[1] > 0.0) {
+        sw += 1.0 / (q[1] * q[1]);
+        swi += q[0] / (q[1] * q[1]);
+      }
+      if (sw > 0.0) {
+        double mean = swi / sw, err = std::sqrt(1.0 / sw);
+        if (mean != 0.0 && err / std::fabs(mean) <= o->target_rel_err) {
+          time_to_target = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+          break;
+        }
+      }
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(rec.data(), p->d_rec, sizeof(double) * REC * done, hipMemcpyDeviceToHost, s));
+  if (o->edges_out)
+    HIP_TRY(hipMemcpyAsync(o->edges_out, p->d_edges, sizeof(double) * d * (nb + 1), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // combination of the iteration estimates (inverse-variance weights)
+  double W = 0.0, WI = 0.0, nz = 0.0, bad = 0.0;
+  int k = 0;
+  for (int it = 0; it < done; ++it) {
+    const double* q = rec.data() + (size_t)REC * it;
+    nz += q[4];
+    bad += q[5];
+    if (r->iter_integral) r->iter_integral[it] = q[0];
+    if (r->iter_error) r->iter_error[it] = q[1];
+    if (it < o->warmup_iters_discarded || !(q[1] > 0.0)) continue;
+    W += 1.0 / (q[1] * q[1]);
+    WI += q[0] / (q[1] * q[1]);
+    ++k;
+  }
+  double mean = W > 0.0 ? WI / W : 0.0;
+  double chi2 = 0.0;
+  for (int it = o->warmup_iters_discarded; it < done; ++it) {
+    const double* q = rec.data() + (size_t)REC * it;
+    if (q[1] > 0.0) chi2 += (q[0] - mean) * (q[0] - mean) / (q[1] * q[1]);
+  }
+  r->integral = mean;
+  r->error = W > 0.0 ? std::sqrt(1.0 / W) : 0.0;
+  r->chi2_dof = k > 1 ? chi2 / (k - 1) : 0.0;
+  r->n_iter_done = done;
+  r->n_events_total = (int64_t)done * o->n_events;
+  r->n_nonzero = (int64_t)nz;
+  r->n_nonfinite = (int64_t)bad;
+  r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  r->time_to_target = time_to_target;
+  double ksec = 0.0;
+  for (int it = 0; it < done; ++it) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[2 * it], ev[2 * it + 1]));
+    ksec += 1e-3 * ms;
+  }
+  r->kernel_seconds = ksec;
+  for (int it = 0; it < done; ++it)
+    if (rec[(size_t)REC * it + 6] != 0.0) return fail(MF_ERANGE, "grid refinement failed at iteration %d", it);
+  return MF_OK;
+}
+
+mf_status mf_grad(mf_process* p, const mf_integrate_opts* o, double* out, double* err) {
+  g_err.clear();
+  if (!p || !o || !out || !err) return fail(MF_EINVAL, "NULL argument");
+  if (o->n_events < 2) return fail(MF_EINVAL, "n_events must be >= 2");
+  hipStream_t s = (hipStream_t)o->stream;
+  const int d = p->ndim, nb = p->nb;
+  if (o->edges_in) HIP_TRY(hipMemcpyAsync(p->d_edges, o->edges_in, sizeof(double) * d * (nb + 1),
+                                          hipMemcpyDeviceToDevice, s));
+  const int nblk = blocks_for(o->n_events);
+  const size_t lds = sizeof(double) * d * (nb + 1);
+  if (!p->L.grad_vegas) return fail(MF_ENOTSUP, "derivatives are not built for this process");
+  p->L.grad_vegas(p->dc, p->d_edges, o->iter_offset, o->n_events, p->cfg.seed, p->d_part, nblk, lds, s);
+  mf_status st = check_stream_launch("k_grad_vegas");
+  if (st != MF_OK) return st;
+  hipLaunchKernelGGL(k_grad_finalize, dim3(1), dim3(64), 0, s, p->d_part, nblk, o->n_events, p->d_out);
+  double h[2 * GV];
+  HIP_TRY(hipMemcpyAsync(h, p->d_out, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < GV; ++k) {
+    out[k] = h[k];
+    err[k] = h[GV + k];
+  }
+  return MF_OK;
+}
+
+}  // extern "C"

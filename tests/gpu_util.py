@@ -1,0 +1,34 @@
+"""Helpers shared by the GPU tests: device tensors in the library's layout."""
+import numpy as np
+
+
+def to_dev_soa(x: np.ndarray):
+    """[n][d] host array -> [d][n] float64 cuda tensor."""
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x.T)).to("cuda")
+
+
+def rel_err(a, b, floor=0.0):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.maximum(np.abs(b), floor)
+    out = np.zeros_like(a)
+    nz = den > 0
+    out[nz] = np.abs(a[nz] - b[nz]) / den[nz]
+    out[~nz] = np.abs(a[~nz] - b[~nz])
+    return out
+
+
+def assert_close(got, ref, rtol, floor_frac=1e-20):
+    """|got - ref| <= rtol |ref| + floor_frac max|ref| element by element.
+
+    The absolute floor only matters for values that are zero or denormal-tiny
+    on one side (for example x within one rounding of the last PDF knot,
+    where the interpolant is exactly 0 on one side and ~1e-38 on the other).
+    """
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    atol = floor_frac * float(np.max(np.abs(ref)))
+    bad = np.abs(got - ref) > rtol * np.abs(ref) + atol
+    assert not bad.any(), (int(bad.sum()), np.flatnonzero(bad)[:5], got[bad][:5], ref[bad][:5])

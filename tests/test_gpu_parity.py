@@ -1,0 +1,193 @@
+"""HIP path vs the FP64 oracle, element by element on identical seeded inputs.
+
+Tolerances: FP64 amplitudes agree with the oracle to 1e-11 relative per event
+(two independent FP64 evaluations of the same definition, which differ only
+in rounding order; cancellations between colour orderings cost a few digits
+at most).  FP32 amplitudes: |dME|/ME <= 1e-5 per event is the target of the
+FP32 mode; the test bound is the same.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+from gpu_util import assert_close, rel_err, to_dev_soa
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2105_10529_amd as mf  # noqa: E402
+
+SQRT_S, MT = 13000.0, 173.0
+PROC = {0: "gg>ttx", 1: "gg>ttxg", 2: "gg>ttxgg"}
+
+
+def _oracle(ng, channel="gg", dr=None):
+    return oracle.Oracle(oracle.Config(n_g=ng, channel=channel, dr_min=(0.4 if ng >= 2 else 0.0) if dr is None else dr))
+
+
+def _proc(ng, precision="fp64", process=None, dr=None):
+    return mf.Process(mf.Config(process=process or PROC[ng], precision=precision,
+                                dr_min=(0.4 if ng >= 2 else 0.0) if dr is None else dr))
+
+
+def _points(n, d, seed):
+    x = si.points_above_threshold(n, d, SQRT_S, MT, seed=seed)
+    return np.concatenate([x, si.edge_points(d)])
+
+
+@pytest.mark.parametrize("ng,n", [(0, 4099), (1, 3001), (2, 600)])
+def test_integrand_fp64_matches_oracle(ng, n):
+    d = si.ndim(ng)
+    x = _points(n, d, 100 + ng)
+    ref = _oracle(ng).integrand(x)
+    got = _proc(ng).integrand(to_dev_soa(x)).cpu().numpy()
+    assert np.count_nonzero(ref) > 0.5 * n
+    assert_close(got, ref, 1e-11)
+
+
+@pytest.mark.parametrize("channel,process", [("uu~", "uux>ttx"), ("dd~", "ddx>ttx")])
+def test_quark_channels_match_oracle(channel, process):
+    x = _points(2000, 4, 7)
+    ref = _oracle(0, channel).integrand(x)
+    got = _proc(0, process=process).integrand(to_dev_soa(x)).cpu().numpy()
+    assert_close(got, ref, 1e-11)
+
+
+@pytest.mark.parametrize("ng,n", [(0, 2000), (1, 2000), (2, 500)])
+def test_integrand_fp32_amplitudes_within_1e5(ng, n):
+    d = si.ndim(ng)
+    x = _points(n, d, 200 + ng)
+    ref = _oracle(ng).integrand(x)
+    got = _proc(ng, "fp32").integrand(to_dev_soa(x)).cpu().numpy()
+    e = rel_err(got, ref, floor=1e-20 * np.max(np.abs(ref)))
+    print(f"fp32 |dw|/w: median {np.median(e):.2e} q999 {np.quantile(e, 0.999):.2e} max {np.max(e):.2e}")
+    assert_close(got, ref, 1e-5)
+
+
+def test_empty_ragged_and_single_inputs():
+    p = _proc(1)
+    u = torch.empty((7, 0), dtype=torch.float64, device="cuda")
+    assert p.integrand(u).numel() == 0
+    orc = _oracle(1)
+    for n in (1, 63, 65, 257):
+        x = _points(n, 7, 300 + n)[:n]
+        got = p.integrand(to_dev_soa(x)).cpu().numpy()
+        assert_close(got, orc.integrand(x), 1e-11)
+
+
+def test_invalid_configurations_raise():
+    with pytest.raises(mf.MFError) as e:
+        mf.Process(mf.Config(sqrt_s=300.0))
+    assert e.value.status == mf.MF_EINVAL
+    with pytest.raises(mf.MFError) as e:
+        mf.Process(mf.Config(n_bins=0))
+    assert e.value.status == mf.MF_EINVAL
+    with pytest.raises(mf.MFError) as e:
+        mf.Process(mf.Config(mu=1e6))
+    assert e.value.status == mf.MF_ERANGE
+
+
+@pytest.mark.parametrize("ng,n", [(0, 20000), (1, 20000)])
+def test_vegas_iteration_matches_oracle_exactly(ng, n):
+    """One on-device iteration (same Philox stream) against the oracle's loop."""
+    p = _proc(ng)
+    orc = _oracle(ng)
+    d = si.ndim(ng)
+    edges = torch.from_numpy(si.random_grid(d, 50, seed=5)).to("cuda")
+    out = torch.empty_like(edges)
+    r = p.integrate(1, n, adapt=True, iter_offset=3, edges_in=edges, edges_out=out)
+    S1, S2, hist, nnz, nbad = orc.vegas_iteration(si.random_grid(d, 50, seed=5), 3, n, p.cfg.seed, purpose=0)
+    I, s = oracle.iteration_estimate(S1, S2, n)
+    assert abs(r.iter_integral[0] / I - 1) < 1e-12
+    assert abs(r.iter_error[0] / s - 1) < 1e-9
+    assert r.n_nonzero == nnz and r.n_nonfinite == nbad == 0
+    ref_edges = oracle.vegas_refine(si.random_grid(d, 50, seed=5), hist, 1.5)
+    assert np.max(np.abs(out.cpu().numpy() - ref_edges)) < 1e-10
+
+
+def test_refine_matches_oracle():
+    d, nb = 7, 50
+    rng = np.random.default_rng(9)
+    for trial in range(4):
+        e = si.random_grid(d, nb, seed=trial)
+        h = rng.exponential(size=(d, nb)) ** 3
+        h[1, :] = 0.0  # an all-zero dimension is left unchanged
+        h[2, 10:20] = 0.0
+        ed = torch.from_numpy(e).to("cuda")
+        mf.vegas_refine(ed, torch.from_numpy(h).to("cuda"))
+        ref = oracle.vegas_refine(e, h)
+        assert np.max(np.abs(ed.cpu().numpy() - ref)) < 1e-12
+        assert np.array_equal(ed.cpu().numpy()[1], e[1])
+
+
+def test_gg_ttbar_cross_section_matches_quadrature():
+    from oracle import quad
+
+    ref = quad.hadronic_sigma(_oracle(0), "gg")
+    r = _proc(0).integrate(5, 100000)
+    assert abs(r.integral - ref) < 3 * r.error
+    assert r.error / r.integral < 5e-3
+
+
+def test_quark_cross_section_matches_quadrature():
+    from oracle import quad
+
+    ref = quad.hadronic_sigma(_oracle(0, "uu~"), "qq")
+    ru = _proc(0, process="uux>ttx").integrate(5, 100000)
+    rd = _proc(0, process="ddx>ttx").integrate(5, 100000)
+    assert abs(ru.integral + rd.integral - ref) < 3 * math.hypot(ru.error, rd.error)
+
+
+def test_full_size_iteration_is_deterministic_and_consistent():
+    """gg -> t t~ g at 1e7 events per iteration (the benchmark's launch shape):
+    bitwise reproducible, and statistically consistent with the oracle's own
+    estimate on an independent stream."""
+    p = _proc(1)
+    d = 7
+    edges = torch.from_numpy(si.random_grid(d, 50, seed=11)).to("cuda")
+    a = p.integrate(1, 10_000_000, adapt=False, edges_in=edges)
+    b = p.integrate(1, 10_000_000, adapt=False, edges_in=edges)
+    assert a.iter_integral[0] == b.iter_integral[0] and a.iter_error[0] == b.iter_error[0]
+    orc = _oracle(1)
+    S1, S2, _, _, _ = orc.vegas_iteration(si.random_grid(d, 50, seed=11), 0, 200000, 12345, purpose=2)
+    I, s = oracle.iteration_estimate(S1, S2, 200000)
+    assert abs(a.iter_integral[0] - I) < 4 * math.hypot(a.iter_error[0], s)
+
+
+@pytest.mark.parametrize("ng,precision", [(0, "fp64"), (1, "fp64")])
+def test_gradients_match_oracle(ng, precision):
+    d = si.ndim(ng)
+    x = _points(400, d, 400 + ng)
+    orc = _oracle(ng)
+    p = _proc(ng, precision)
+    w, dw = p.integrand_grad(to_dev_soa(x))
+    w, dw = w.cpu().numpy(), dw.cpu().numpy()
+    for k, direction in enumerate(range(1, 10)):
+        rw, rdw = orc.integrand_grad(x, direction)
+        if k == 0:
+            assert_close(w, rw, 1e-11)
+        scale = max(np.max(np.abs(rdw)), 1e-300)
+        assert np.max(np.abs(dw[k] - rdw)) < 1e-10 * scale, k
+
+
+def test_grad_estimator_matches_oracle_sum():
+    """mf_grad over Philox events equals the oracle's mean over the same events."""
+    p = _proc(1)
+    d = 7
+    n = 4000
+    vals, errs = p.grad(n, iter_offset=2)
+    orc = _oracle(1)
+    u = oracle.event_uniforms(n, d, 2, p.cfg.seed, 0)
+    # uniform grid: x = u, Jacobian 1
+    w, _ = orc.integrand_grad(u, 2)
+    assert abs(vals[0] / w.mean() - 1) < 1e-12
+    for k, direction in enumerate(range(1, 10)):
+        _, dw = orc.integrand_grad(u, direction)
+        ref = dw.mean()
+        assert abs(vals[1 + k] - ref) <= 1e-10 * max(abs(ref), np.abs(dw).max() / n), k
