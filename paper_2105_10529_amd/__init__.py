@@ -269,3 +269,39 @@ def vegas_refine(edges, hist, alpha: float = 1.5, stream=None):
     d, nb1 = edges.shape
     _check(lib().mf_vegas_refine(_dev_ptr(edges), _dev_ptr(hist), d, nb1 - 1, alpha, _stream_ptr(stream)))
     return edges
+
+
+def make_autograd_integrand(process: "Process"):
+    """torch.autograd.Function over mf_integrand_grad for one process.
+
+    forward(u, m_t, theta) -> w[n]: u is the [ndim][n] device tensor of points,
+    m_t a 0-d tensor and theta the 8 PDF parameters (A_g, a_g, b_g, c_g, d_g,
+    A_u, A_d, A_u~); their values must equal the process configuration (the
+    kernels read the configured ones) -- they are inputs so that autograd can
+    route d sigma/d m_t and d sigma/d theta.  backward contracts the upstream
+    gradient with the per-event derivatives from the same kernel launch.
+    """
+    import torch
+
+    cfg = process.cfg
+    theta_cfg = [cfg.pdf_params[i] for i in (0, 1, 2, 3, 4, 5, 10, 15)]
+
+    class MfIntegrand(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, u, m_t, theta):
+            if abs(float(m_t) - cfg.m_t) > 1e-12 * cfg.m_t:
+                raise ValueError("m_t differs from the process configuration")
+            th = theta.detach().cpu().double().numpy()
+            if np.max(np.abs(th - np.array(theta_cfg))) > 1e-12 * np.max(np.abs(theta_cfg)):
+                raise ValueError("theta differs from the process configuration")
+            w, dw = process.integrand_grad(u.detach())
+            ctx.save_for_backward(dw)
+            return w
+
+        @staticmethod
+        def backward(ctx, g):
+            (dw,) = ctx.saved_tensors
+            gd = dw @ g.to(dw.dtype)  # [9]
+            return None, gd[0].to(torch.float64), gd[1:].to(torch.float64)
+
+    return MfIntegrand

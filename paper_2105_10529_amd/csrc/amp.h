@@ -74,6 +74,23 @@ template <class R, class RK> __device__ __forceinline__ V4<R> cvt4(const V4<RK>&
   return V4<R>{cvt<R>(p.t), cvt<R>(p.x), cvt<R>(p.y), cvt<R>(p.z)};
 }
 
+// Opaque copies: the compiler must treat the value as redefined here, so
+// expressions built from it are neither merged with earlier ones nor hoisted
+// out of the enclosing loop.  Used by the generated amplitude code to bound
+// register lifetimes.
+__device__ __forceinline__ void opaque(float& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void opaque(double& x) { asm volatile("" : "+v"(x)); }
+template <class T> __device__ __forceinline__ void opaque(Dual<T>& x) {
+  opaque(x.v);
+  opaque(x.d);
+}
+template <class R> __device__ __forceinline__ void opaque4(V4<R>& p) {
+  opaque(p.t);
+  opaque(p.x);
+  opaque(p.y);
+  opaque(p.z);
+}
+
 // Colour-ordered three-gluon vertex contracted with two currents X, Y of
 // outgoing momenta PX, PY (coupling and the off-shell propagator excluded):
 //   X (2PX+PY).Y + (X.Y)(PY-PX) - Y (PX+2PY).X
@@ -125,6 +142,16 @@ template <class R> __device__ __forceinline__ Sp<R> slash(const V4<R>& J, const 
   o.s2 = C2<R>{b * p.s0.re + (c * p.s1.re + d * p.s1.im), b * p.s0.im + (c * p.s1.im - d * p.s1.re)};
   o.s3 = C2<R>{a * p.s1.re + (c * p.s0.re - d * p.s0.im), a * p.s1.im + (c * p.s0.im + d * p.s0.re)};
   return o;
+}
+template <class R> __device__ __forceinline__ void opaque_sp(Sp<R>& p) {
+  opaque(p.s0.re);
+  opaque(p.s0.im);
+  opaque(p.s1.re);
+  opaque(p.s1.im);
+  opaque(p.s2.re);
+  opaque(p.s2.im);
+  opaque(p.s3.re);
+  opaque(p.s3.im);
 }
 // Fermion propagator applied to an off-shell spinor: f * (Qslash + m) phi.
 template <class R> __device__ __forceinline__ Sp<R> prop(const V4<R>& Q, R m, R f, const Sp<R>& phi) {

@@ -10,17 +10,33 @@
 namespace mf {
 namespace {
 
+// Block-chunked event loops: chunk `it` of this block covers events
+// [chunk_base(it), chunk_base(it) + BLOCK).  Both quantities are uniform over
+// the block and computed from scalars only.
+__device__ __forceinline__ int64_t chunk_base(int64_t it) {
+  return (int64_t)blockIdx.x * BLOCK + it * (int64_t)gridDim.x * BLOCK;
+}
+__device__ __forceinline__ int64_t chunks_of_block(int64_t n) {
+  const int64_t b0 = (int64_t)blockIdx.x * BLOCK, stride = (int64_t)gridDim.x * BLOCK;
+  return b0 < n ? (n - b0 + stride - 1) / stride : 0;
+}
+
 // -------------------------------------------------------------- integrand
 template <int NG, int CH, class RA>
 __global__ void __launch_bounds__(BLOCK) k_integrand(DevCfg c, const double* __restrict__ u, int64_t n,
                                                      double* __restrict__ w) {
-  for (int64_t e = blockIdx.x * (int64_t)BLOCK + threadIdx.x; e < n; e += (int64_t)gridDim.x * BLOCK) {
+  const int64_t nchunk = chunks_of_block(n);
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t e0 = chunk_base(it) + threadIdx.x;
+    const bool live = e0 < n;
+    const int64_t e = live ? e0 : n - 1;  // tail lanes recompute the last event
     double x[MAXD];
 #pragma unroll
     for (int j = 0; j < MAXD; ++j)
       if (j < c.ndim) x[j] = u[(int64_t)j * n + e];
     EventOut<double> r = event_weight<NG, CH, RA, double>(c, x, c.mt, c.pdfc);
-    w[e] = isfinite(r.w) ? r.w : 0.0;
+    const double v = isfinite(r.w) ? r.w : 0.0;
+    if (live) w[e] = v;
   }
 }
 
@@ -32,8 +48,7 @@ __device__ __forceinline__ void grad_event(const DevCfg& c, const double* x, dou
   EventOut<Dual<double>> r = event_weight<NG, CH, RA, Dual<double>>(c, x, Dual<double>(c.mt, 1.0), c.pdfc);
   w = r.w.v;
   for (int k = 0; k < 9; ++k) dw[k] = 0.0;
-  if (!r.pass) return;
-  dw[0] = r.w.d;
+  dw[0] = r.w.d;  // r1, r2 and w are zero for an event that fails, so every term below is 0
   if constexpr (CH == 0) {
     double f1 = hermite_x(c.pdfc, r.t1), f2 = hermite_x(c.pdfc, r.t2);
     if (c.mu_is_mt) dw[0] += r.r1.v * (hermite_x(c.pdfd, r.t1) * f2 + f1 * hermite_x(c.pdfd, r.t2));
@@ -62,7 +77,11 @@ __device__ __forceinline__ void grad_event(const DevCfg& c, const double* x, dou
 template <int NG, int CH, class RA>
 __global__ void __launch_bounds__(BLOCK) k_integrand_grad(DevCfg c, const double* __restrict__ u, int64_t n,
                                                           double* __restrict__ w, double* __restrict__ dw) {
-  for (int64_t e = blockIdx.x * (int64_t)BLOCK + threadIdx.x; e < n; e += (int64_t)gridDim.x * BLOCK) {
+  const int64_t nchunk = chunks_of_block(n);
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t e0 = chunk_base(it) + threadIdx.x;
+    const bool live = e0 < n;
+    const int64_t e = live ? e0 : n - 1;
     double x[MAXD];
 #pragma unroll
     for (int j = 0; j < MAXD; ++j)
@@ -71,8 +90,10 @@ __global__ void __launch_bounds__(BLOCK) k_integrand_grad(DevCfg c, const double
     grad_event<NG, CH, RA>(c, x, ww, d);
     bool ok = isfinite(ww);
     for (int k = 0; k < 9; ++k) ok = ok && isfinite(d[k]);
-    if (w) w[e] = ok ? ww : 0.0;
-    for (int k = 0; k < 9; ++k) dw[(int64_t)k * n + e] = ok ? d[k] : 0.0;
+    if (live) {
+      if (w) w[e] = ok ? ww : 0.0;
+      for (int k = 0; k < 9; ++k) dw[(int64_t)k * n + e] = ok ? d[k] : 0.0;
+    }
   }
 }
 
@@ -86,42 +107,42 @@ __global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restr
   double* edges = lds;                             // d*(nb+1)
   double* pdf = edges + d * (nb + 1);              // 4*196
   double* hist = pdf + 4 * NXK;                    // WAVES*d*nb
-  double* w2s = hist + WAVES * d * nb;             // BLOCK
+  double* dummy = hist + WAVES * d * nb;           // WAVES*nb: rows for lanes >= d
+  double* w2s = dummy + WAVES * nb;                // BLOCK
   unsigned char* bins_s = (unsigned char*)(w2s + BLOCK);  // d*BLOCK
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < d * (nb + 1); i += BLOCK) edges[i] = edges_g[i];
   for (int i = tid; i < 4 * NXK; i += BLOCK) pdf[i] = c.pdfc[i];
-  for (int i = tid; i < WAVES * d * nb; i += BLOCK) hist[i] = 0.0;
+  for (int i = tid; i < WAVES * (d + 1) * nb; i += BLOCK) hist[i] = 0.0;
   __syncthreads();
   DevCfg cl = c;
   cl.pdfc = pdf;
   KSum s1{0.0, 0.0}, s2{0.0, 0.0};
   int nnz = 0, nbad = 0;
   double* my_hist = hist + wave * d * nb;
-  for (int64_t base = (int64_t)blockIdx.x * BLOCK + wave * 64; base < N; base += (int64_t)gridDim.x * BLOCK) {
-    int64_t e = base + lane;
-    double w = 0.0;
+  // The chunk loop is controlled by block-uniform scalars (block index, grid
+  // size, N), so its counter lives in scalar registers and is not exposed to
+  // vector-register spills inside the divergent per-event code.
+  const int64_t nchunk = chunks_of_block(N);
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t e0 = chunk_base(it) + tid;
+    const bool live = e0 < N;
+    const int64_t e = live ? e0 : N - 1;  // tail lanes recompute the last event, weight masked
     int bins[MAXD];
-    if (e < N) {
-      double y[MAXD], x[MAXD];
-      event_uniforms((uint64_t)e, iter, seed, 0, d, y);
-      double jac = 1.0;
+    double y[MAXD], x[MAXD];
+    event_uniforms((uint64_t)e, iter, seed, 0, d, y);
+    double jac = 1.0;
 #pragma unroll
-      for (int j = 0; j < MAXD; ++j)
-        if (j < d) x[j] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], bins[j], jac);
-      EventOut<double> r = event_weight<NG, CH, RA, double>(cl, x, c.mt, pdf);
-      w = r.w * jac;
-      if (!isfinite(w)) {
-        w = 0.0;
-        ++nbad;
-      }
-      nnz += (w != 0.0);
-      kadd(s1, w);
-      kadd(s2, w * w);
-    } else {
-#pragma unroll
-      for (int j = 0; j < MAXD; ++j) bins[j] = 0;
-    }
+    for (int j = 0; j < MAXD; ++j)
+      if (j < d) x[j] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], bins[j], jac);
+    EventOut<double> r = event_weight<NG, CH, RA, double>(cl, x, c.mt, pdf);
+    double w = r.w * jac;
+    const bool finite = isfinite(w);
+    nbad += (live && !finite) ? 1 : 0;
+    w = (live && finite) ? w : 0.0;
+    nnz += (w != 0.0);
+    kadd(s1, w);
+    kadd(s2, w * w);
     // stage this wave's 64 events, then d lanes bin them in event order
     w2s[tid] = w * w;
 #pragma unroll
@@ -130,10 +151,13 @@ __global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restr
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < d) {
-      const unsigned char* bj = bins_s + lane * BLOCK + wave * 64;
+    {
+      // every lane runs the binning loop (no divergent region in the event
+      // loop); lanes >= d update a scratch row of their wave
+      const bool mine = lane < d;
+      const unsigned char* bj = bins_s + (mine ? lane : 0) * BLOCK + wave * 64;
       const double* ws = w2s + wave * 64;
-      double* hj = my_hist + lane * nb;
+      double* hj = mine ? my_hist + lane * nb : dummy + wave * nb;
       for (int k = 0; k < 64; ++k) hj[bj[k]] += ws[k];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -196,7 +220,11 @@ __global__ void __launch_bounds__(BLOCK) k_grad_vegas(DevCfg c, const double* __
     s[k] = KSum{0.0, 0.0};
     sq[k] = 0.0;
   }
-  for (int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x; e < N; e += (int64_t)gridDim.x * BLOCK) {
+  const int64_t nchunk = chunks_of_block(N);
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t e0 = chunk_base(it) + threadIdx.x;
+    const bool live = e0 < N;
+    const int64_t e = live ? e0 : N - 1;
     double y[MAXD], x[MAXD];
     int bins[MAXD];
     event_uniforms((uint64_t)e, iter, seed, 0, d, y);
@@ -206,7 +234,7 @@ __global__ void __launch_bounds__(BLOCK) k_grad_vegas(DevCfg c, const double* __
       if (j < d) x[j] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], bins[j], jac);
     double v[GV];
     grad_event<NG, CH, RA>(c, x, v[0], v + 1);
-    bool ok = true;
+    bool ok = live;
     for (int k = 0; k < GV; ++k) ok = ok && isfinite(v[k]);
     for (int k = 0; k < GV; ++k) {
       double t = ok ? v[k] * jac : 0.0;

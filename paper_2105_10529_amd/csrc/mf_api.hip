@@ -279,7 +279,7 @@ int blocks_for(int64_t n) {
 }
 
 size_t vegas_lds_bytes(int d, int nb) {
-  return sizeof(double) * (size_t)(d * (nb + 1) + 4 * NXK + WAVES * d * nb + BLOCK) + (size_t)d * BLOCK;
+  return sizeof(double) * (size_t)(d * (nb + 1) + 4 * NXK + WAVES * (d + 1) * nb + BLOCK) + (size_t)d * BLOCK;
 }
 
 Launchers pick_launchers(int ng, int ch, int prec) {

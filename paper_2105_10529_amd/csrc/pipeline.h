@@ -167,9 +167,11 @@ __device__ __forceinline__ R phase_space(int ng, const double* x, double shat, R
     Q = boost_from_rest(rest, Q, Mprev);
     Mprev = Mi;
   }
-  // t t~ split of the remaining system of mass Mprev
-  R Mtt = R(Mprev);
-  if (!(Mprev > 2.0 * val(mt))) return R(0.0);
+  // t t~ split of the remaining system of mass Mprev.  Below threshold the
+  // kinematics are built for a safe mass just above it and the weight is 0,
+  // so every lane follows the same instruction stream.
+  const bool above = Mprev > 2.0 * val(mt);
+  R Mtt = above ? R(Mprev) : R(2.0) * mt * R(1.0 + 1e-6);
   R beta = dsqrt(R(1.0) - R(4.0) * mt * mt / (Mtt * Mtt));
   R q = Mtt * beta * R(0.5);
   double ct = 2.0 * x[2 + (n - 2) + 2 * (n - 2)] - 1.0;
@@ -180,7 +182,8 @@ __device__ __forceinline__ R phase_space(int ng, const double* x, double shat, R
   R E = Mtt * R(0.5);
   V4<R> t{E, q * R(st * cp), q * R(st * sp), q * R(ct)};
   V4<R> tb{E, R(0.0) - t.x, R(0.0) - t.y, R(0.0) - t.z};
-  V4<R> QR{R(Q.t), R(Q.x), R(Q.y), R(Q.z)};
+  // rest frame of the pair: its momentum Q with the (possibly safe) mass Mtt
+  V4<R> QR{above ? R(Q.t) : dsqrt(Mtt * Mtt + R(Q.x * Q.x + Q.y * Q.y + Q.z * Q.z)), R(Q.x), R(Q.y), R(Q.z)};
   top = boost_from_rest(t, QR, Mtt);
   atop = boost_from_rest(tb, QR, Mtt);
   // massless volume V_n(s) = (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!)
@@ -189,7 +192,7 @@ __device__ __forceinline__ R phase_space(int ng, const double* x, double shat, R
   for (int k = 2; k <= n - 1; ++k) fact *= k;
   double fact2 = 1.0;
   for (int k = 2; k <= n - 2; ++k) fact2 *= k;
-  return R(vol / (fact * fact2)) * beta;
+  return above ? R(vol / (fact * fact2)) * beta : R(0.0);
 }
 
 // Fiducial cuts on the gluons in the lab frame: the lab rapidity differs from
@@ -340,41 +343,48 @@ template <class R> struct EventOut {
   int pass;
 };
 
-// The integrand at x (unit hypercube, after the VEGAS map).
+// The integrand at x (unit hypercube, after the VEGAS map).  Branch-free:
+// an event below threshold or outside the cuts is evaluated on safe
+// kinematics and its weight is selected to zero, so the amplitude code never
+// runs under a partial execution mask.
 template <int NG, int CH, class RA, class RK>
 __device__ __forceinline__ EventOut<RK> event_weight(const DevCfg& c, const double* x, RK mt, const double* pdf) {
   EventOut<RK> out;
-  out.w = RK(0.0);
-  out.r1 = RK(0.0);
-  out.r2 = RK(0.0);
-  out.t1 = out.t2 = 0.0;
-  out.pass = 0;
   double x1 = x[0], x2 = x[1];
   double shat = x1 * x2 * c.s;
-  if (!(shat > 4.0 * val(mt) * val(mt))) return out;
+  const double thr = 4.0 * val(mt) * val(mt);
+  bool ok = shat > thr;
+  const double shat_k = ok ? shat : thr * (1.0 + 1e-3);
   V4<double> gl[NG > 0 ? NG : 1];
   V4<RK> top, atop;
-  RK wps = phase_space<RK>(NG, x, shat, mt, gl, top, atop);
-  if (!(val(wps) > 0.0)) return out;
-  if (!pass_cuts(c, NG, gl, 0.5 * log(x1 / x2))) return out;
-  out.pass = 1;
-  double E = 0.5 * sqrt(shat);
+  RK wps = phase_space<RK>(NG, x, shat_k, mt, gl, top, atop);
+  ok = ok && (val(wps) > 0.0);
+  ok = ok && pass_cuts(c, NG, gl, 0.5 * log(x1 / x2));
+  out.pass = ok ? 1 : 0;
+  double E = 0.5 * sqrt(shat_k);
   out.t1 = x_position(c, x1);
   out.t2 = x_position(c, x2);
-  RK pre = RK(c.norm / (2.0 * shat * x1 * x2)) * wps;
+  RK pre = RK(c.norm / (2.0 * shat_k * x1 * x2)) * wps;
+  const RK zero = RK(0.0);
   if constexpr (CH == 0) {
     RK me = to_k(me_gg<NG, RA, RK>(E, gl, top, atop, mt), (RK*)nullptr);
-    out.r1 = pre * me;
-    out.w = out.r1 * RK(hermite_x(pdf, out.t1) * hermite_x(pdf, out.t2));
+    RK r1 = pre * me;
+    RK w = r1 * RK(hermite_x(pdf, out.t1) * hermite_x(pdf, out.t2));
+    out.r1 = ok ? r1 : zero;
+    out.r2 = zero;
+    out.w = ok ? w : zero;
   } else {
     V4<double> p1{E, 0.0, 0.0, E}, p2{E, 0.0, 0.0, -E};
-    out.r1 = pre * to_k(me_qqbar<RA, RK>(p1, p2, top, atop, mt), (RK*)nullptr);
-    out.r2 = pre * to_k(me_qqbar<RA, RK>(p2, p1, top, atop, mt), (RK*)nullptr);
+    RK r1 = pre * to_k(me_qqbar<RA, RK>(p1, p2, top, atop, mt), (RK*)nullptr);
+    RK r2 = pre * to_k(me_qqbar<RA, RK>(p2, p1, top, atop, mt), (RK*)nullptr);
     const double* fq = pdf + (CH == 1 ? 1 : 2) * NXK;
     const double* fa = pdf + 3 * NXK;
     double q1 = hermite_x(fq, out.t1), a2 = hermite_x(fa, out.t2), a1 = hermite_x(fa, out.t1),
            q2 = hermite_x(fq, out.t2);
-    out.w = out.r1 * RK(q1 * a2) + out.r2 * RK(a1 * q2);
+    RK w = r1 * RK(q1 * a2) + r2 * RK(a1 * q2);
+    out.r1 = ok ? r1 : zero;
+    out.r2 = ok ? r2 : zero;
+    out.w = ok ? w : zero;
   }
   return out;
 }

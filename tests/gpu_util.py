@@ -20,12 +20,14 @@ def rel_err(a, b, floor=0.0):
     return out
 
 
-def assert_close(got, ref, rtol, floor_frac=1e-20):
+def assert_close(got, ref, rtol, floor_frac=1e-14):
     """|got - ref| <= rtol |ref| + floor_frac max|ref| element by element.
 
-    The absolute floor only matters for values that are zero or denormal-tiny
-    on one side (for example x within one rounding of the last PDF knot,
-    where the interpolant is exactly 0 on one side and ~1e-38 on the other).
+    The absolute floor (a fraction of the largest value) covers events whose
+    value sits on a cancellation -- the PDF interpolant crossing zero near
+    x -> 1, or x within one rounding of the last knot where one side gives 0
+    and the other ~1e-38 -- where two FP64 evaluations differ by rounding
+    relative to the scale of the integrand rather than to the value itself.
     """
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
