@@ -55,6 +55,52 @@ def cpu_baseline(seed: int, target_seconds: float = 12.0) -> dict:
                       f"gg->ttg FP64, OpenMP over events, {dt:.1f} s"}
 
 
+def secondary(seed_events: int) -> dict:
+    """Bounded extra measurements on the same GPU (reported beside the main line).
+
+    * g g -> t t~ g g (10 dims, Delta R > 0.4): events/s of the fused kernel
+      with FP32 amplitudes (1e8 events per iteration) and with FP64 (1e7), and
+      the wall time to 1e-3 relative error of plain VEGAS in each precision.
+    * d sigma/d m_t on g g -> t t~ g at m_t = 171, 173, 175 GeV from 1e8
+      pathwise-derivative events each, with a grid frozen from a VEGAS warm-up.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2105_10529_amd as mf
+
+    out = {}
+    for prec, n in (("fp32", 100_000_000), ("fp64", 10_000_000)):
+        p = mf.Process(mf.Config(process="gg>ttxgg", precision=prec, dr_min=0.4))
+        p.integrate(2, min(n, 10_000_000), adapt=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = p.integrate(2, n, adapt=True, iter_offset=2)
+        dt = time.perf_counter() - t0
+        fresh = mf.Process(mf.Config(process="gg>ttxgg", precision=prec, dr_min=0.4))
+        tt = fresh.integrate(40, 10_000_000, target_rel_err=1e-3, adapt=True)
+        out[f"ttgg_{prec}"] = {
+            "events_per_s": 2 * n / dt, "kernel_ms_avg": 1e3 * r.kernel_seconds / 2, "events_per_iteration": n,
+            "integral_pb": r.integral, "error_pb": r.error,
+            "time_to_1e-3_s": tt.time_to_target, "iterations_to_1e-3": tt.n_iter_done,
+            "events_to_1e-3": tt.n_events_total, "integral_at_1e-3_pb": tt.integral, "error_at_1e-3_pb": tt.error,
+        }
+    grads = {}
+    for mt in (171.0, 173.0, 175.0):
+        p = mf.Process(mf.Config(process="gg>ttxg", m_t=mt))
+        p.integrate(5, 10_000_000, adapt=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vals, errs = p.grad(100_000_000, iter_offset=100)
+        dt = time.perf_counter() - t0
+        grads[f"{mt:g}"] = {"sigma_pb": vals[0], "sigma_err": errs[0], "dsigma_dmt_pb_per_gev": vals[1],
+                            "dsigma_dmt_err": errs[1], "dsigma_dtheta": list(map(float, vals[2:])),
+                            "dsigma_dtheta_err": list(map(float, errs[2:])), "events": 100_000_000,
+                            "seconds": dt}
+    out["ttg_gradients"] = grads
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +108,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events", type=int, default=EVENTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -132,6 +179,8 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p.cfg.seed)
+    if not args.no_secondary:
+        out["secondary"] = secondary(args.events)
     print(json.dumps(out), flush=True)
     return 0
 

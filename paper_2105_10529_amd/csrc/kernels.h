@@ -108,17 +108,23 @@ __global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restr
   double* pdf = edges + d * (nb + 1);              // 4*196
   double* hist = pdf + 4 * NXK;                    // WAVES*d*nb
   double* dummy = hist + WAVES * d * nb;           // WAVES*nb: rows for lanes >= d
-  double* w2s = dummy + WAVES * nb;                // BLOCK
-  unsigned char* bins_s = (unsigned char*)(w2s + BLOCK);  // d*BLOCK
+  double* wacc = dummy + WAVES * nb;               // WAVES*4 compensated sums
+  double* w2s = wacc + WAVES * 4;                  // BLOCK
+  double* jac_s = w2s + BLOCK;                     // BLOCK
+  double* xs = jac_s + BLOCK;                      // d*BLOCK mapped points
+  unsigned char* bins_s = (unsigned char*)(xs + d * BLOCK);  // d*BLOCK
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < d * (nb + 1); i += BLOCK) edges[i] = edges_g[i];
   for (int i = tid; i < 4 * NXK; i += BLOCK) pdf[i] = c.pdfc[i];
-  for (int i = tid; i < WAVES * (d + 1) * nb; i += BLOCK) hist[i] = 0.0;
+  for (int i = tid; i < WAVES * (d + 1) * nb + WAVES * 4; i += BLOCK) hist[i] = 0.0;
   __syncthreads();
   DevCfg cl = c;
   cl.pdfc = pdf;
-  KSum s1{0.0, 0.0}, s2{0.0, 0.0};
-  int nnz = 0, nbad = 0;
+  // Nothing per lane is carried from one event chunk to the next: sums go to
+  // per-wave LDS accumulators after a deterministic wave reduction, counts are
+  // ballots (wave-uniform scalars).
+  double* acc = wacc + wave * 4;  // S1 (hi, lo), S2 (hi, lo)
+  unsigned long long nnz = 0, nbad = 0;
   double* my_hist = hist + wave * d * nb;
   // The chunk loop is controlled by block-uniform scalars (block index, grid
   // size, N), so its counter lives in scalar registers and is not exposed to
@@ -128,26 +134,42 @@ __global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restr
     const int64_t e0 = chunk_base(it) + tid;
     const bool live = e0 < N;
     const int64_t e = live ? e0 : N - 1;  // tail lanes recompute the last event, weight masked
-    int bins[MAXD];
-    double y[MAXD], x[MAXD];
-    event_uniforms((uint64_t)e, iter, seed, 0, d, y);
-    double jac = 1.0;
+    {
+      // map the uniforms and stage the bin indices and the Jacobian in LDS
+      // before the amplitude, so no per-lane value is live across it
+      int bins[MAXD];
+      double y[MAXD];
+      event_uniforms((uint64_t)e, iter, seed, 0, d, y);
+      double jac = 1.0;
+#pragma unroll
+      for (int j = 0; j < MAXD; ++j)
+        if (j < d) xs[j * BLOCK + tid] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], bins[j], jac);
+#pragma unroll
+      for (int j = 0; j < MAXD; ++j)
+        if (j < d) bins_s[j * BLOCK + tid] = (unsigned char)bins[j];
+      jac_s[tid] = jac;
+    }
+    asm volatile("" ::: "memory");
+    double x[MAXD];
 #pragma unroll
     for (int j = 0; j < MAXD; ++j)
-      if (j < d) x[j] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], bins[j], jac);
+      if (j < d) x[j] = xs[j * BLOCK + tid];
     EventOut<double> r = event_weight<NG, CH, RA, double>(cl, x, c.mt, pdf);
-    double w = r.w * jac;
+    asm volatile("" ::: "memory");
+    double w = r.w * jac_s[tid];
     const bool finite = isfinite(w);
-    nbad += (live && !finite) ? 1 : 0;
+    nbad += __popcll(__ballot(live && !finite));
     w = (live && finite) ? w : 0.0;
-    nnz += (w != 0.0);
-    kadd(s1, w);
-    kadd(s2, w * w);
-    // stage this wave's 64 events, then d lanes bin them in event order
+    nnz += __popcll(__ballot(w != 0.0));
+    {
+      double h1, l1, h2, l2;
+      wave_sum_dd(w, h1, l1);
+      wave_sum_dd(w * w, h2, l2);
+      lds_dd_accumulate(acc, h1, l1);
+      lds_dd_accumulate(acc + 2, h2, l2);
+    }
+    // stage this wave's 64 weights, then bin them in event order
     w2s[tid] = w * w;
-#pragma unroll
-    for (int j = 0; j < MAXD; ++j)
-      if (j < d) bins_s[j * BLOCK + tid] = (unsigned char)bins[j];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -174,27 +196,23 @@ __global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restr
     p[PART_HEAD + i] = h;
   }
   __syncthreads();
-  double vals[4] = {s1.s, -s1.c, s2.s, -s2.c};
-  double acc_hi[2] = {0.0, 0.0}, acc_lo[2] = {0.0, 0.0};
-  for (int q = 0; q < 4; ++q) {
-    w2s[tid] = vals[q];
-    __syncthreads();
-    if (tid == 0) {
-      int slot = q >> 1;
-      for (int t = 0; t < BLOCK; ++t) dd_add(acc_hi[slot], acc_lo[slot], w2s[t]);
-    }
-    __syncthreads();
+  // counts: wave-uniform per wave; combine the four waves in order
+  unsigned long long* ci = (unsigned long long*)w2s;
+  if (lane == 0) {
+    ci[wave] = nnz;
+    ci[WAVES + wave] = nbad;
   }
-  // counts
-  int* ci = (int*)w2s;
-  ci[tid] = nnz;
-  ci[BLOCK + tid] = nbad;
   __syncthreads();
   if (tid == 0) {
-    long long tn = 0, tb = 0;
-    for (int t = 0; t < BLOCK; ++t) {
-      tn += ci[t];
-      tb += ci[BLOCK + t];
+    double acc_hi[2] = {0.0, 0.0}, acc_lo[2] = {0.0, 0.0};
+    unsigned long long tn = 0, tb = 0;
+    for (int v = 0; v < WAVES; ++v) {
+      dd_add(acc_hi[0], acc_lo[0], wacc[4 * v + 0]);
+      dd_add(acc_hi[0], acc_lo[0], wacc[4 * v + 1]);
+      dd_add(acc_hi[1], acc_lo[1], wacc[4 * v + 2]);
+      dd_add(acc_hi[1], acc_lo[1], wacc[4 * v + 3]);
+      tn += ci[v];
+      tb += ci[WAVES + v];
     }
     p[0] = acc_hi[0];
     p[1] = acc_lo[0];
@@ -211,18 +229,17 @@ __global__ void __launch_bounds__(BLOCK) k_grad_vegas(DevCfg c, const double* __
                                                       int64_t N, uint64_t seed, double* __restrict__ partials) {
   extern __shared__ double lds[];
   const int d = c.ndim, nb = c.nb;
+  const int tid = threadIdx.x, wave = tid >> 6;
   double* edges = lds;
-  for (int i = threadIdx.x; i < d * (nb + 1); i += BLOCK) edges[i] = edges_g[i];
+  double* wacc = lds + d * (nb + 1);  // [WAVES][GV][4]: sum (hi, lo), sum of squares (hi, lo)
+  for (int i = tid; i < d * (nb + 1); i += BLOCK) edges[i] = edges_g[i];
+  for (int i = tid; i < WAVES * GV * 4; i += BLOCK) wacc[i] = 0.0;
   __syncthreads();
-  KSum s[GV];
-  double sq[GV];
-  for (int k = 0; k < GV; ++k) {
-    s[k] = KSum{0.0, 0.0};
-    sq[k] = 0.0;
-  }
+  double* acc = wacc + wave * GV * 4;
+  // As in k_vegas, nothing per lane is carried across event chunks.
   const int64_t nchunk = chunks_of_block(N);
   for (int64_t it = 0; it < nchunk; ++it) {
-    const int64_t e0 = chunk_base(it) + threadIdx.x;
+    const int64_t e0 = chunk_base(it) + tid;
     const bool live = e0 < N;
     const int64_t e = live ? e0 : N - 1;
     double y[MAXD], x[MAXD];
@@ -237,24 +254,29 @@ __global__ void __launch_bounds__(BLOCK) k_grad_vegas(DevCfg c, const double* __
     bool ok = live;
     for (int k = 0; k < GV; ++k) ok = ok && isfinite(v[k]);
     for (int k = 0; k < GV; ++k) {
-      double t = ok ? v[k] * jac : 0.0;
-      kadd(s[k], t);
-      sq[k] += t * t;
+      const double t = ok ? v[k] * jac : 0.0;
+      double h, l;
+      wave_sum_dd(t, h, l);
+      lds_dd_accumulate(acc + 4 * k, h, l);
+      wave_sum_dd(t * t, h, l);
+      lds_dd_accumulate(acc + 4 * k + 2, h, l);
     }
   }
-  __shared__ double red[BLOCK];
-  double* p = partials + (int64_t)blockIdx.x * (3 * GV);
-  for (int k = 0; k < GV; ++k) {
-    for (int q = 0; q < 3; ++q) {
-      red[threadIdx.x] = q == 0 ? s[k].s : (q == 1 ? -s[k].c : sq[k]);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double hi = 0.0, lo = 0.0;
-        for (int t = 0; t < BLOCK; ++t) dd_add(hi, lo, red[t]);
-        p[3 * k + q] = hi + lo;
-      }
-      __syncthreads();
+  __syncthreads();
+  if (tid < GV) {
+    const int k = tid;
+    double hs = 0.0, ls = 0.0, hq = 0.0, lq = 0.0;
+    for (int v = 0; v < WAVES; ++v) {
+      const double* a = wacc + v * GV * 4 + 4 * k;
+      dd_add(hs, ls, a[0]);
+      dd_add(hs, ls, a[1]);
+      dd_add(hq, lq, a[2]);
+      dd_add(hq, lq, a[3]);
     }
+    double* p = partials + (int64_t)blockIdx.x * (3 * GV);
+    p[3 * k] = hs;
+    p[3 * k + 1] = ls;
+    p[3 * k + 2] = hq + lq;
   }
 }
 
@@ -262,9 +284,10 @@ __global__ void __launch_bounds__(BLOCK) k_grad_vegas(DevCfg c, const double* __
 
 // Launcher table of one (final gluons, channel, amplitude type) instance;
 // GRAD = 0 leaves the derivative kernels out.
-template <int NG, int CH, class RA, class RD, int GRAD>
+template <int NG, int CH, class RA, class RD, int GRAD, int FUSED = 1>
 Launchers make_launchers() {
   Launchers L;
+  L.fused = FUSED != 0;
   L.integrand = [](const DevCfg& c, const double* u, int64_t n, double* w, int nblk, hipStream_t s) {
     hipLaunchKernelGGL((k_integrand<NG, CH, RA>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w);
   };

@@ -39,7 +39,36 @@ __device__ __forceinline__ void dd_add(double& hi, double& lo, double v) {
   two_sum(s, lo, hi, lo);
 }
 
+// Deterministic wave-wide sum of a double with error terms (xor butterfly of
+// two-sums); every lane ends with the same (hi, lo).  The butterfly order is
+// fixed and two-sum is exact, so the result does not depend on timing.
+__device__ __forceinline__ void wave_sum_dd(double v, double& hi, double& lo) {
+  double s = v, e = 0.0;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double so = __shfl_xor(s, off), eo = __shfl_xor(e, off);
+    double t, err;
+    two_sum(s, so, t, err);
+    s = t;
+    e = (e + eo) + err;
+  }
+  hi = s;
+  lo = e;
+}
+// Per-wave double-double accumulator in LDS, updated identically by every
+// lane of the wave (all lanes hold the same addend).
+__device__ __forceinline__ void lds_dd_accumulate(double* acc, double hi, double lo) {
+  double h = acc[0], l = acc[1];
+  dd_add(h, l, hi);
+  dd_add(h, l, lo);
+  acc[0] = h;
+  acc[1] = l;
+}
+
 struct Launchers {
+  // false: VEGAS iterations go through the staged path (points kernel ->
+  // integrand kernel -> accumulation kernel) instead of the fused kernel
+  bool fused;
   void (*integrand)(const DevCfg&, const double*, int64_t, double*, int, hipStream_t);
   void (*integrand_grad)(const DevCfg&, const double*, int64_t, double*, double*, int, hipStream_t);
   void (*vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, int, size_t, hipStream_t);

@@ -51,6 +51,7 @@ mf_status fail(mf_status s, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(MF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+constexpr int RED_ROWS = 32;  // rows of the first reduction stage
 constexpr int REC = 8;        // per-iteration record: I, sigma, S1, S2, nonzero, nonfinite, status, pad
 
 struct PdfParams {
@@ -119,6 +120,102 @@ __global__ void k_fill_uniform(double* edges, int d, int nb) {
   edges[t] = (double)k / nb;
 }
 
+// ------------------------------------------------------- staged iteration
+// Points kernel: Philox uniforms through the grid; writes the mapped point
+// [ndim][N], the Jacobian [N] and the bin indices [ndim][N].
+__global__ void __launch_bounds__(256) k_stage_points(const double* __restrict__ edges_g, int d, int nb, uint64_t iter,
+                                                      int64_t N, uint64_t seed, double* __restrict__ x,
+                                                      double* __restrict__ jac, unsigned char* __restrict__ bins) {
+  extern __shared__ double edges[];
+  for (int i = threadIdx.x; i < d * (nb + 1); i += blockDim.x) edges[i] = edges_g[i];
+  __syncthreads();
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x, stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nchunk = b0 < N ? (N - b0 + stride - 1) / stride : 0;
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t e = b0 + it * stride + threadIdx.x;
+    if (e >= N) continue;
+    double y[MAXD];
+    event_uniforms((uint64_t)e, iter, seed, 0, d, y);
+    double J = 1.0;
+    for (int j = 0; j < d; ++j) {
+      int b;
+      x[(int64_t)j * N + e] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], b, J);
+      bins[(int64_t)j * N + e] = (unsigned char)b;
+    }
+    jac[e] = J;
+  }
+}
+
+// Accumulation kernel: weights w*J into the same per-block partials as the
+// fused kernel (compensated sums from deterministic wave reductions, per-wave
+// histograms combined in order).
+__global__ void __launch_bounds__(256) k_stage_accumulate(const double* __restrict__ f, const double* __restrict__ jac,
+                                                          const unsigned char* __restrict__ bins, int d, int nb,
+                                                          int64_t N, double* __restrict__ partials, int pstride) {
+  __shared__ double hist[WAVES][MAXD * MAX_BINS];
+  __shared__ double wacc[WAVES][4];
+  __shared__ unsigned long long cnt[2 * WAVES];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = lane; i < d * nb; i += 64) hist[wave][i] = 0.0;
+  if (lane < 4) wacc[wave][lane] = 0.0;
+  __syncthreads();
+  unsigned long long nnz = 0, nbad = 0;
+  const int64_t b0 = (int64_t)blockIdx.x * BLOCK, stride = (int64_t)gridDim.x * BLOCK;
+  const int64_t nchunk = b0 < N ? (N - b0 + stride - 1) / stride : 0;
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t e0 = b0 + it * stride + tid;
+    const bool live = e0 < N;
+    const int64_t e = live ? e0 : N - 1;
+    double w = f[e] * jac[e];
+    const bool finite = isfinite(w);
+    nbad += __popcll(__ballot(live && !finite));
+    w = (live && finite) ? w : 0.0;
+    nnz += __popcll(__ballot(w != 0.0));
+    double h, l;
+    wave_sum_dd(w, h, l);
+    lds_dd_accumulate(wacc[wave], h, l);
+    wave_sum_dd(w * w, h, l);
+    lds_dd_accumulate(wacc[wave] + 2, h, l);
+    // bin in event order: lane j < d walks the wave's 64 events of dimension j
+    const double w2 = w * w;
+    for (int k = 0; k < 64; ++k) {
+      const double wk = __shfl(w2, k);
+      const int64_t ek = __shfl(e, k);
+      if (lane < d) hist[wave][lane * nb + bins[(int64_t)lane * N + ek]] += wk;
+    }
+  }
+  __syncthreads();
+  double* p = partials + (int64_t)blockIdx.x * pstride;
+  for (int i = tid; i < d * nb; i += BLOCK) {
+    double s = 0.0;
+    for (int v = 0; v < WAVES; ++v) s += hist[v][i];
+    p[PART_HEAD + i] = s;
+  }
+  if (lane == 0) {
+    cnt[wave] = nnz;
+    cnt[WAVES + wave] = nbad;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double h1 = 0.0, l1 = 0.0, h2 = 0.0, l2 = 0.0;
+    unsigned long long tn = 0, tb = 0;
+    for (int v = 0; v < WAVES; ++v) {
+      dd_add(h1, l1, wacc[v][0]);
+      dd_add(h1, l1, wacc[v][1]);
+      dd_add(h2, l2, wacc[v][2]);
+      dd_add(h2, l2, wacc[v][3]);
+      tn += cnt[v];
+      tb += cnt[WAVES + v];
+    }
+    p[0] = h1;
+    p[1] = l1;
+    p[2] = h2;
+    p[3] = l2;
+    p[4] = (double)tn;
+    p[5] = (double)tb;
+  }
+}
+
 // -------------------------------------------------------- refinement
 // Lepage's refinement of one dimension, serial over bins (50-ish), FP64.
 // Returns false (and leaves e unchanged) if the new edges are not strictly
@@ -172,6 +269,32 @@ __global__ void k_refine(double* edges, const double* hist, int d, int nb, doubl
   if (threadIdx.x == 0 && j < d) {
     bool ok = refine_dim(edges + j * (nb + 1), hist + j * nb, nb, alpha, scratch);
     if (!ok) status[0] = 1;
+  }
+}
+
+// First reduction stage: block r of R sums the partials of source blocks
+// [r*nblk/R, (r+1)*nblk/R) in order and writes one row in the same layout
+// (compensated pairs stay pairs).  A fixed partition keeps the result
+// bitwise reproducible; R rows then go to the single-block finaliser.
+__global__ void k_reduce_partials(const double* partials, int nblk, int pstride, int width, int R, double* out) {
+  const int r = blockIdx.x;
+  const int b0 = (int)((int64_t)r * nblk / R), b1 = (int)((int64_t)(r + 1) * nblk / R);
+  double* o = out + (int64_t)r * pstride;
+  for (int i = threadIdx.x; i < width; i += blockDim.x) {
+    if (i == 1 || i == 3) continue;  // low words are folded into their pair below
+    if (i == 0 || i == 2) {
+      double hi = 0.0, lo = 0.0;
+      for (int b = b0; b < b1; ++b) {
+        dd_add(hi, lo, partials[(int64_t)b * pstride + i]);
+        dd_add(hi, lo, partials[(int64_t)b * pstride + i + 1]);
+      }
+      o[i] = hi;
+      o[i + 1] = lo;
+    } else {
+      double acc = 0.0;
+      for (int b = b0; b < b1; ++b) acc += partials[(int64_t)b * pstride + i];
+      o[i] = acc;
+    }
   }
 }
 
@@ -244,6 +367,7 @@ struct mf_process {
   double* d_pdf = nullptr;      // pdfc | pdfd | pdft
   double* d_edges = nullptr;    // ndim*(nb+1)
   double* d_part = nullptr;     // MAX_BLOCKS * pstride
+  double* d_part2 = nullptr;    // RED_ROWS * pstride (first reduction stage)
   double* d_rec = nullptr;      // per-iteration records
   double* d_hist = nullptr;     // last histogram
   double* d_out = nullptr;      // small outputs
@@ -251,6 +375,12 @@ struct mf_process {
   int pstride;
   int rec_cap;
   Launchers L;
+  // staged-iteration buffers (allocated on first use, grown on demand)
+  int64_t stage_cap = 0;
+  double* d_sx = nullptr;          // [ndim][cap]
+  double* d_sjac = nullptr;        // [cap]
+  double* d_sw = nullptr;          // [cap]
+  unsigned char* d_sbins = nullptr;  // [ndim][cap]
 };
 
 namespace {
@@ -279,7 +409,9 @@ int blocks_for(int64_t n) {
 }
 
 size_t vegas_lds_bytes(int d, int nb) {
-  return sizeof(double) * (size_t)(d * (nb + 1) + 4 * NXK + WAVES * (d + 1) * nb + BLOCK) + (size_t)d * BLOCK;
+  return sizeof(double) * (size_t)(d * (nb + 1) + 4 * NXK + WAVES * (d + 1) * nb + WAVES * 4 + 2 * BLOCK +
+                                  d * BLOCK) +
+         (size_t)d * BLOCK;
 }
 
 Launchers pick_launchers(int ng, int ch, int prec) {
@@ -358,6 +490,7 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
   if (hipMalloc(&p->d_pdf, sizeof(double) * 16 * NXK) != hipSuccess ||
       hipMalloc(&p->d_edges, sizeof(double) * p->ndim * (p->nb + 1)) != hipSuccess ||
       hipMalloc(&p->d_part, sizeof(double) * (size_t)MAX_BLOCKS * std::max(p->pstride, 3 * GV)) != hipSuccess ||
+      hipMalloc(&p->d_part2, sizeof(double) * (size_t)RED_ROWS * p->pstride) != hipSuccess ||
       hipMalloc(&p->d_rec, sizeof(double) * REC * p->rec_cap) != hipSuccess ||
       hipMalloc(&p->d_hist, sizeof(double) * p->ndim * p->nb) != hipSuccess ||
       hipMalloc(&p->d_out, sizeof(double) * 64) != hipSuccess ||
@@ -384,10 +517,15 @@ void mf_process_destroy(mf_process* p) {
   hipFree(p->d_pdf);
   hipFree(p->d_edges);
   hipFree(p->d_part);
+  hipFree(p->d_part2);
   hipFree(p->d_rec);
   hipFree(p->d_hist);
   hipFree(p->d_out);
   hipFree(p->d_status);
+  hipFree(p->d_sx);
+  hipFree(p->d_sjac);
+  hipFree(p->d_sw);
+  hipFree(p->d_sbins);
   delete p;
 }
 
@@ -449,6 +587,23 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
                                           hipMemcpyDeviceToDevice, s));
   const int nblk = blocks_for(o->n_events);
   const size_t lds = vegas_lds_bytes(d, nb);
+  if (!p->L.fused && p->stage_cap < o->n_events) {
+    HIP_TRY(hipStreamSynchronize(s));
+    hipFree(p->d_sx);
+    hipFree(p->d_sjac);
+    hipFree(p->d_sw);
+    hipFree(p->d_sbins);
+    p->d_sx = p->d_sjac = p->d_sw = nullptr;
+    p->d_sbins = nullptr;
+    p->stage_cap = 0;
+    const size_t n = (size_t)o->n_events;
+    if (hipMalloc(&p->d_sx, sizeof(double) * d * n) != hipSuccess || hipMalloc(&p->d_sjac, sizeof(double) * n) != hipSuccess ||
+        hipMalloc(&p->d_sw, sizeof(double) * n) != hipSuccess || hipMalloc(&p->d_sbins, (size_t)d * n) != hipSuccess) {
+      hipGetLastError();
+      return fail(MF_ENOMEM, "staged-iteration buffers for %lld events", (long long)o->n_events);
+    }
+    p->stage_cap = o->n_events;
+  }
   std::vector<double> rec((size_t)REC * o->n_iter, 0.0);
   double time_to_target = -1.0;
   int done = 0;
@@ -464,7 +619,16 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   for (int it = 0; it < o->n_iter; ++it) {
     const uint64_t iter = o->iter_offset + (uint64_t)it;
     HIP_TRY(hipEventRecord(ev[2 * it], s));
-    p->L.vegas(p->dc, p->d_edges, iter, o->n_events, p->cfg.seed, p->d_part, p->pstride, nblk, lds, s);
+    if (p->L.fused) {
+      p->L.vegas(p->dc, p->d_edges, iter, o->n_events, p->cfg.seed, p->d_part, p->pstride, nblk, lds, s);
+    } else {
+      const int64_t N = o->n_events;
+      hipLaunchKernelGGL(k_stage_points, dim3(nblk), dim3(256), sizeof(double) * d * (nb + 1), s, p->d_edges, d, nb,
+                         iter, N, p->cfg.seed, p->d_sx, p->d_sjac, p->d_sbins);
+      p->L.integrand(p->dc, p->d_sx, N, p->d_sw, nblk, s);
+      hipLaunchKernelGGL(k_stage_accumulate, dim3(nblk), dim3(256), 0, s, p->d_sw, p->d_sjac, p->d_sbins, d, nb, N,
+                         p->d_part, p->pstride);
+    }
     HIP_TRY(hipEventRecord(ev[2 * it + 1], s));
     mf_status st = check_stream_launch("k_vegas");
     if (st != MF_OK) return st;
@@ -545,7 +709,7 @@ mf_status mf_grad(mf_process* p, const mf_integrate_opts* o, double* out, double
   if (o->edges_in) HIP_TRY(hipMemcpyAsync(p->d_edges, o->edges_in, sizeof(double) * d * (nb + 1),
                                           hipMemcpyDeviceToDevice, s));
   const int nblk = blocks_for(o->n_events);
-  const size_t lds = sizeof(double) * d * (nb + 1);
+  const size_t lds = sizeof(double) * (d * (nb + 1) + WAVES * GV * 4);
   if (!p->L.grad_vegas) return fail(MF_ENOTSUP, "derivatives are not built for this process");
   p->L.grad_vegas(p->dc, p->d_edges, o->iter_offset, o->n_events, p->cfg.seed, p->d_part, nblk, lds, s);
   mf_status st = check_stream_launch("k_grad_vegas");

@@ -93,10 +93,16 @@ def test_invalid_configurations_raise():
     assert e.value.status == mf.MF_ERANGE
 
 
-@pytest.mark.parametrize("ng,n", [(0, 20000), (1, 20000)])
-def test_vegas_iteration_matches_oracle_exactly(ng, n):
-    """One on-device iteration (same Philox stream) against the oracle's loop."""
-    p = _proc(ng)
+@pytest.mark.parametrize("ng,n,precision", [(0, 20000, "fp64"), (1, 20000, "fp64"), (2, 3000, "fp64"),
+                                            (1, 20000, "fp32"), (2, 3000, "fp32")])
+def test_vegas_iteration_matches_oracle_exactly(ng, n, precision):
+    """One on-device iteration (same Philox stream) against the oracle's loop.
+
+    FP64: equal to rounding (1e-12 on the iteration estimate); FP32 amplitudes:
+    every weight within 1e-5 of the FP64 oracle, so the mean is within 1e-5.
+    """
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    p = _proc(ng, precision)
     orc = _oracle(ng)
     d = si.ndim(ng)
     edges = torch.from_numpy(si.random_grid(d, 50, seed=5)).to("cuda")
@@ -104,11 +110,11 @@ def test_vegas_iteration_matches_oracle_exactly(ng, n):
     r = p.integrate(1, n, adapt=True, iter_offset=3, edges_in=edges, edges_out=out)
     S1, S2, hist, nnz, nbad = orc.vegas_iteration(si.random_grid(d, 50, seed=5), 3, n, p.cfg.seed, purpose=0)
     I, s = oracle.iteration_estimate(S1, S2, n)
-    assert abs(r.iter_integral[0] / I - 1) < 1e-12
-    assert abs(r.iter_error[0] / s - 1) < 1e-9
+    assert abs(r.iter_integral[0] / I - 1) < tol
+    assert abs(r.iter_error[0] / s - 1) < (1e-9 if precision == "fp64" else 1e-4)
     assert r.n_nonzero == nnz and r.n_nonfinite == nbad == 0
     ref_edges = oracle.vegas_refine(si.random_grid(d, 50, seed=5), hist, 1.5)
-    assert np.max(np.abs(out.cpu().numpy() - ref_edges)) < 1e-10
+    assert np.max(np.abs(out.cpu().numpy() - ref_edges)) < (1e-10 if precision == "fp64" else 1e-5)
 
 
 def test_refine_matches_oracle():
@@ -160,7 +166,7 @@ def test_full_size_iteration_is_deterministic_and_consistent():
     assert abs(a.iter_integral[0] - I) < 4 * math.hypot(a.iter_error[0], s)
 
 
-@pytest.mark.parametrize("ng,precision", [(0, "fp64"), (1, "fp64")])
+@pytest.mark.parametrize("ng,precision", [(0, "fp64"), (1, "fp64"), (1, "fp32")])
 def test_gradients_match_oracle(ng, precision):
     d = si.ndim(ng)
     x = _points(400, d, 400 + ng)
@@ -168,12 +174,13 @@ def test_gradients_match_oracle(ng, precision):
     p = _proc(ng, precision)
     w, dw = p.integrand_grad(to_dev_soa(x))
     w, dw = w.cpu().numpy(), dw.cpu().numpy()
+    tol = 1e-10 if precision == "fp64" else 2e-5
     for k, direction in enumerate(range(1, 10)):
         rw, rdw = orc.integrand_grad(x, direction)
         if k == 0:
-            assert_close(w, rw, 1e-11)
+            assert_close(w, rw, 1e-11 if precision == "fp64" else 1e-5)
         scale = max(np.max(np.abs(rdw)), 1e-300)
-        assert np.max(np.abs(dw[k] - rdw)) < 1e-10 * scale, k
+        assert np.max(np.abs(dw[k] - rdw)) < tol * scale, k
 
 
 def test_grad_estimator_matches_oracle_sum():
