@@ -27,6 +27,11 @@ sys.path.insert(0, ROOT)
 METRIC = "events/s per MI355X and time to 1e-3 rel. error: FP32+flow vs FP64 VEGAS"
 FP64_VECTOR_PEAK = 78.6e12  # MI355X FP64 vector FLOP/s (256 CUs x 128 FLOP/clk x 2.4 GHz)
 EVENTS = 10_000_000
+# HBM bytes per launch of the fused kernel k_vegas<1,0,double> at 1e7 events,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy
+# calibration (profiles/traffic_k_vegas_gg_ttg_fp64_1e7.md).  Set to None when
+# that kernel changes until the counters are taken again.
+MEASURED_TRAFFIC_BYTES = 20.12e6
 
 
 def flops_per_event(m: int) -> int:
@@ -109,6 +114,11 @@ def main() -> int:
     ap.add_argument("--events", type=int, default=EVENTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--workload", choices=("ttg", "ttgg"), default="ttg",
+                    help="ttg: g g -> t t~ g FP64 (the reported workload); ttgg: g g -> t t~ g g with FP32 "
+                         "amplitudes (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (to calibrate HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -120,6 +130,24 @@ def main() -> int:
     import paper_2105_10529_amd as mf
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 8}), flush=True)
+        return 0
+    if args.workload == "ttgg":
+        p = mf.Process(mf.Config(process="gg>ttxgg", precision="fp32", dr_min=0.4))
+        if args.warmup:
+            p.integrate(args.warmup, args.events, adapt=True)
+        r = p.integrate(args.steps, args.events, adapt=True, iter_offset=args.warmup)
+        print(json.dumps({"workload": "gg>ttxgg fp32", "events_per_s": args.steps * args.events / r.seconds,
+                          "kernel_ms_avg": 1e3 * r.kernel_seconds / args.steps,
+                          "flops_per_event": flops_per_event(4)}), flush=True)
+        return 0
     p = mf.Process(mf.Config(process="gg>ttxg", precision="fp64"))
     stream = torch.cuda.current_stream()
     if args.warmup > 0:
@@ -167,7 +195,8 @@ def main() -> int:
             "peak": FP64_VECTOR_PEAK / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK,
-            "traffic": None,
+            "traffic": MEASURED_TRAFFIC_BYTES if args.events == EVENTS else None,
+            "traffic_unit": "bytes per launch (HBM read + write, counter-calibrated)",
             "kernel": "k_vegas<1,0,double> (fused per-event VEGAS iteration)",
             "flops_per_event": fpe,
             "kernel_ms_avg": 1e3 * kernel_avg,

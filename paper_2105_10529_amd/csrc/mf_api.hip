@@ -632,7 +632,10 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
     HIP_TRY(hipEventRecord(ev[2 * it + 1], s));
     mf_status st = check_stream_launch("k_vegas");
     if (st != MF_OK) return st;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, p->d_part, nblk, p->pstride, d, nb, o->n_events,
+    const int R = nblk < RED_ROWS ? nblk : RED_ROWS;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(R), dim3(256), 0, s, p->d_part, nblk, p->pstride, PART_HEAD + d * nb,
+                       R, p->d_part2);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, p->d_part2, R, p->pstride, d, nb, o->n_events,
                        p->cfg.alpha, o->adapt ? 1 : 0, p->d_edges, p->d_rec + (size_t)REC * it, p->d_hist);
     st = check_stream_launch("k_finalize");
     if (st != MF_OK) return st;
