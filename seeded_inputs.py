@@ -81,3 +81,23 @@ def rotation_matrix(seed: int = BASE_SEED) -> np.ndarray:
     L = np.eye(4)
     L[1:, 1:] = q
     return L
+
+
+def flow_params(shapes, seed: int = BASE_SEED, scale_out: float = 0.3):
+    """Random dense-layer parameters for the coupling flow, one dict per layer.
+
+    shapes: list of (d_in, hidden, d_out) per layer.  Hidden layers use the
+    uniform fan-in scaling sqrt(6/fan_in); the output layer is scaled by
+    scale_out (0 gives the identity flow).  float64, row-major [in][out].
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for d_in, h, d_out in shapes:
+        a1 = np.sqrt(6.0 / d_in)
+        a2 = np.sqrt(6.0 / h)
+        out.append({
+            "W1": rng.uniform(-a1, a1, (d_in, h)), "b1": rng.uniform(-0.1, 0.1, h),
+            "W2": rng.uniform(-a2, a2, (h, h)), "b2": rng.uniform(-0.1, 0.1, h),
+            "W3": scale_out * rng.uniform(-a2, a2, (h, d_out)), "b3": scale_out * rng.uniform(-0.5, 0.5, d_out),
+        })
+    return out

@@ -1,0 +1,105 @@
+"""Pins of the oracle's coupling flow (CPU only): bijectivity, normalisation,
+identity at zero output layer, mask coverage, and the analytic gradient
+against central differences."""
+import itertools
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import flow
+
+K = 8
+
+
+def _setup(d=5, hidden=16, scale=0.5, seed=3):
+    mk = flow.masks(d)
+    shapes = [(int((~m).sum()), hidden, int(m.sum()) * (2 * K + 1)) for m in mk]
+    return mk, si.flow_params(shapes, seed=seed, scale_out=scale)
+
+
+def test_masks_cover_every_coordinate_and_pair():
+    for d in (4, 7, 10, 13):
+        mk = flow.masks(d)
+        assert len(mk) == 6
+        assert all(m.any() and (~m).any() for m in mk)
+        counts = sum(m.astype(int) for m in mk)
+        assert counts.min() >= 2
+        for i, j in itertools.combinations(range(d), 2):
+            assert any(m[i] != m[j] for m in mk)
+
+
+def test_identity_at_zero_output_layer():
+    mk, params = _setup(scale=0.0)
+    y = si.unit_points(100, 5, seed=1)
+    z, logq, _ = flow.forward(params, mk, y, K)
+    assert np.allclose(z, y, atol=1e-15) and np.allclose(logq, 0.0, atol=1e-14)
+
+
+def test_density_normalised_and_bijective():
+    mk, params = _setup()
+    y = si.unit_points(2000, 5, seed=2)
+    z, logq, _ = flow.forward(params, mk, y, K)
+    assert np.all((z >= 0) & (z <= 1))
+    y2, logq2 = flow.inverse(params, mk, z, K)
+    assert np.max(np.abs(y2 - y)) < 1e-12
+    assert np.max(np.abs(logq2 - logq)) < 1e-10
+    # per-coordinate PQ densities integrate to one: sum_k W_k (V_k + V_k+1)/2 = 1
+    o, _ = flow.mlp(params[0], y[:, ~mk[0]])
+    o = o.reshape(2000, int(mk[0].sum()), 2 * K + 1)
+    W, V, _ = flow._pq_params(o[:, 0, :], K)
+    assert np.allclose(np.sum(W * 0.5 * (V[:, :-1] + V[:, 1:]), axis=1), 1.0, atol=1e-13)
+    # the flow density integrates to one over the cube (Monte Carlo, uniform y)
+    q = np.exp(flow.forward(params, mk, si.unit_points(200000, 5, seed=4), K)[1])
+    assert abs(q.mean() - 1.0) < 5 * q.std() / np.sqrt(q.size)
+
+
+def test_cdf_is_integral_of_pdf():
+    rng = np.random.default_rng(5)
+    o = rng.normal(size=(1, 2 * K + 1))
+    W, V, _ = flow._pq_params(o, K)
+    ys = np.linspace(0, 1, 20001)
+    z, pdf, _, _ = flow._pq_forward(ys, np.repeat(W, ys.size, 0), np.repeat(V, ys.size, 0))
+    trap = np.concatenate([[0.0], np.cumsum(0.5 * (pdf[1:] + pdf[:-1]) * np.diff(ys))])
+    assert np.max(np.abs(trap - z)) < 1e-7
+
+
+def test_gradient_matches_central_differences():
+    mk, params = _setup(d=5, hidden=8, scale=0.5)
+    y = si.unit_points(64, 5, seed=6)
+    w = np.random.default_rng(7).exponential(size=64)
+    _, logq, caches = flow.forward(params, mk, y, K)
+    grads = flow.backward(params, mk, caches, w, K)
+    rng = np.random.default_rng(8)
+    for li in (0, 3, 5):
+        for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            arr = params[li][name]
+            for _ in range(3):
+                idx = tuple(rng.integers(0, s) for s in arr.shape)
+                old = arr[idx]
+                h = 1e-6
+                arr[idx] = old + h
+                lp = flow.loss(flow.forward(params, mk, y, K)[1], w)
+                arr[idx] = old - h
+                lm = flow.loss(flow.forward(params, mk, y, K)[1], w)
+                arr[idx] = old
+                fd = (lp - lm) / (2 * h)
+                g = grads[li][name][idx]
+                assert abs(g - fd) <= 1e-6 * max(1.0, abs(fd)), (li, name, idx, g, fd)
+
+
+def test_training_lowers_the_loss_on_a_peaked_target():
+    mk, params = _setup(d=4, hidden=16, scale=0.0, seed=9)
+    mk = flow.masks(4)
+    shapes = [(int((~m).sum()), 16, int(m.sum()) * (2 * K + 1)) for m in mk]
+    params = si.flow_params(shapes, seed=9, scale_out=0.0)
+    y = si.unit_points(4096, 4, seed=10)
+    w = np.exp(-np.sum((y - 0.3) ** 2, axis=1) / 0.02)
+    state = [{("m" + k): np.zeros_like(v) for k, v in p.items()} | {("v" + k): np.zeros_like(v) for k, v in p.items()}
+             for p in params]
+    l0 = flow.loss(flow.forward(params, mk, y, K)[1], w)
+    for t in range(1, 61):
+        _, lq, c = flow.forward(params, mk, y, K)
+        flow.adam_step(params, flow.backward(params, mk, c, w, K), state, 3e-3, t)
+    l1 = flow.loss(flow.forward(params, mk, y, K)[1], w)
+    assert l0 == pytest.approx(0.0, abs=1e-12) and l1 < -0.5
