@@ -129,6 +129,8 @@ mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w
  * before returning. */
 mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins, double alpha, void* stream);
 
+struct mf_flow; /* learned proposal, mf_flow.h */
+
 typedef struct {
   int32_t n_iter;                 /* iterations, >= 1 */
   int64_t n_events;               /* events per iteration, >= 2 */
@@ -139,6 +141,10 @@ typedef struct {
   const double* edges_in;         /* device [ndim][nbins+1] start grid, or NULL = current grid */
   double* edges_out;              /* device [ndim][nbins+1] final grid, or NULL */
   void* stream;                   /* hipStream_t or NULL */
+  struct mf_flow* flow;           /* NULL: VEGAS proposal.  Else the flow is the
+                                     proposal on the frozen grid (adapt must be
+                                     0): z from Philox with key (seed, 1),
+                                     y = flow inverse of z, w = f J / q(y) */
 } mf_integrate_opts;
 
 typedef struct {
@@ -166,6 +172,29 @@ typedef struct {
  * is refined on the device.  The handle keeps the final grid.  Blocks until
  * the result is on the host. */
 mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r);
+
+/* Per-event weights of one sample with the frozen grid of the handle:
+ *  flow == NULL: y from Philox with counter (e, iter, call, 0) and key
+ *                (cfg.seed, 0) -- the points of VEGAS iteration `iter` --
+ *                and w = f(x(y)) J(y);
+ *  flow != NULL: z from Philox with key (cfg.seed, 1), y = flow inverse of z
+ *                (mf_flow.h), w = f(x(y)) J(y) / q(y).
+ *   y_out: device [ndim][n] FP32 copy of y, or NULL
+ *   w_out: device [n] FP64 weights (pb)
+ * This is how training samples for the flow are drawn and how the weight
+ * distributions of the two proposals are compared.  The flow's dimension
+ * must equal the process's.  Staging buffers of the handle grow to n. */
+mf_status mf_weights(mf_process* p, struct mf_flow* flow, uint64_t iter, int64_t n, float* y_out, double* w_out,
+                     void* stream);
+
+/* Statistics of weights (device [n] FP64, n >= 1; they may be negative
+ * where the interpolated PDFs dip below zero near x = 1):
+ *   out: host [4] = mean, maximum, the q-quantile (the smallest weight with
+ *        at least ceil(q n) weights <= it), number of non-zero weights.
+ * The quantile is exact (radix selection on order-preserving bit keys).  The
+ * unweighting efficiency of a sample is mean / max (or mean / quantile).
+ * MF_EINVAL for a NaN weight or q outside (0,1].  Synchronous. */
+mf_status mf_weight_stats(const double* w, int64_t n, double q, double* out, void* stream);
 
 /* Pathwise Monte Carlo estimate of sigma and its parameter derivatives with
  * a frozen grid (the current grid of the handle, or o->edges_in): events as

@@ -1,0 +1,139 @@
+/*
+ * mf_flow.h -- C ABI of the learned proposal: a coupling normalising flow on
+ * the VEGAS y-space of an integrand (MI355X, gfx950).
+ *
+ * The paper lists new integration algorithms based on deep learning as its
+ * next step (arXiv:2105.10529, Sec. 1 and Sec. 4); the proposal here is the
+ * piecewise-quadratic coupling flow of Mueller et al., "Neural Importance
+ * Sampling" (ACM TOG 38, 2019), on top of a frozen VEGAS grid:
+ *
+ *  - L coupling layers act on y in (0,1)^d.  Layer l keeps the coordinates
+ *    of A_l and maps each coordinate j of B_l by a monotone piecewise-
+ *    quadratic CDF whose 2K+1 parameters come from an MLP of y_{A_l}:
+ *    d_A -> 256 -> 256 -> |B_l| (2K+1), LeakyReLU with slope 0.01.
+ *  - Masks: with nb the bit length of d-1, layer l transforms the coordinates
+ *    whose index has bit (l mod nb) set when floor(l/nb) is even, clear when
+ *    it is odd.
+ *  - Per transformed coordinate the outputs are K width logits then K+1
+ *    vertex logits: W = softmax(width logits), V_k = exp(v_k) / N with
+ *    N = sum_k W_k (exp(v_k) + exp(v_k+1)) / 2, so that the density is linear
+ *    in each bin and integrates to one.
+ *  - log q(y) is the sum of the log densities of every transformed coordinate
+ *    of every layer.  "Forward" is the density direction y -> z, "inverse"
+ *    the sampling direction z -> y.
+ *  - Training minimises the forward KL divergence on weighted samples,
+ *    L = - sum_i w_i log q(y_i) / sum_i w_i, with Adam.
+ *
+ * Arithmetic: the three dense layers run as BF16 matrix-core products with
+ * FP32 accumulation (weights and activations rounded to BF16, biases FP32);
+ * the PQ transform, its derivatives, the loss and Adam run in FP32; the
+ * parameters are kept as FP32 master copies.
+ *
+ * Conventions (as in mf.h): every call returns mf_status and sets
+ * mf_last_error(); "device" pointers are HIP device pointers owned by the
+ * caller; points are [ndim][n] FP32 structure-of-arrays; `stream` is a
+ * hipStream_t or NULL; calls are asynchronous unless stated otherwise.
+ *
+ * Parameter layout (FP32, host): layer after layer, each as
+ *   W1 [d_A][256], b1 [256], W2 [256][256], b2 [256],
+ *   W3 [256][|B| (2K+1)], b3 [|B| (2K+1)]
+ * (row-major [in][out]; output column c(2K+1) + r is output r of the c-th
+ * transformed coordinate in increasing coordinate order; the inputs are the
+ * kept coordinates in increasing order).  Zero W3 and b3 give the identity
+ * map with log q = 0.
+ */
+#ifndef MF_FLOW_H
+#define MF_FLOW_H
+
+#include <stdint.h>
+
+#include "mf.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mf_flow mf_flow;
+
+typedef struct {
+  int32_t ndim;       /* 2..16 */
+  int32_t n_layers;   /* 1..8 */
+  int32_t hidden;     /* hidden width; only 256 is built */
+  int32_t bins;       /* K; only 32 is built */
+  int64_t max_batch;  /* largest n accepted by mf_flow_loss_grad (sizes the
+                         per-layer activation caches: about
+                         n_layers * max_batch * (2 KB + 0.3 KB * ndim) bytes) */
+} mf_flow_config;
+
+/* Create a flow with all parameters zero (the identity map) on the current
+ * device.  MF_EINVAL for sizes outside the ranges above, MF_ENOTSUP for
+ * another hidden width or bin count, MF_ENOMEM on allocation failure. */
+mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out);
+
+/* Release the handle and its device memory (NULL is accepted). */
+void mf_flow_destroy(mf_flow* f);
+
+/* Number of dimensions of the flow, or 0 for NULL. */
+int mf_flow_ndim(const mf_flow* f);
+
+/* Number of FP32 parameters (the length of the layout above), or -1. */
+int64_t mf_flow_param_count(const mf_flow* f);
+
+/* Masks, host [n_layers][ndim]: 1 where the layer transforms the coordinate. */
+mf_status mf_flow_masks(const mf_flow* f, uint8_t* out);
+
+/* Copy all parameters in (host FP32, exactly param_count values), refresh the
+ * BF16 copies, and reset the Adam moments and step counter.  Synchronous. */
+mf_status mf_flow_set_params(mf_flow* f, const float* params, int64_t count);
+
+/* Copy the FP32 master parameters out (host, param_count values).
+ * Synchronous. */
+mf_status mf_flow_get_params(const mf_flow* f, float* params, int64_t count);
+
+/* Density direction: z = T(y) and log q(y) for n points.
+ *   y:    device [ndim][n] FP32 in [0,1];   z: device [ndim][n] FP32 output
+ *         (may equal y for an in-place transform);
+ *   logq: device [n] FP32 output.
+ * Any n >= 0 (no cache is kept).  MF_EINVAL for NULL buffers with n > 0. */
+mf_status mf_flow_forward(mf_flow* f, const float* y, int64_t n, float* z, float* logq, void* stream);
+
+/* Sampling direction: y = T^-1(z) and log q(y) (the density of the produced
+ * point), same buffer conventions as mf_flow_forward. */
+mf_status mf_flow_inverse(mf_flow* f, const float* z, int64_t n, float* y, float* logq, void* stream);
+
+/* Loss L = - sum_i w_i log q(y_i) / sum_i w_i of one batch and its gradient
+ * with respect to every parameter (the forward pass keeps the activations of
+ * the batch, the backward pass runs through the PQ transforms and the
+ * layers).  The gradient is kept in the handle for mf_flow_adam_step.
+ *   y:    device [ndim][n] FP32;  w: device [n] FP32, >= 0 with a positive sum
+ *   grad: device [param_count] FP32 copy of the gradient, or NULL
+ *   loss: host, receives L (the call then synchronises `stream`), or NULL
+ * 1 <= n <= max_batch, else MF_EINVAL. */
+mf_status mf_flow_loss_grad(mf_flow* f, const float* y, const float* w, int64_t n, float* grad, double* loss,
+                            void* stream);
+
+/* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) of the
+ * FP32 masters with the gradient of the last mf_flow_loss_grad, followed by
+ * the refresh of the BF16 copies. */
+mf_status mf_flow_adam_step(mf_flow* f, double lr, void* stream);
+
+typedef struct {
+  int32_t epochs;     /* passes over the data, >= 1 */
+  int64_t batch;      /* events per step, 1..max_batch; the last short batch
+                         of an epoch is used as it is */
+  double lr;          /* initial learning rate, > 0 */
+  double lr_final;    /* learning rate after the last step (cosine decay) */
+  void* stream;
+} mf_flow_train_opts;
+
+/* Train on n weighted points (mf_flow_loss_grad + mf_flow_adam_step per
+ * batch, batches in order).  loss_per_epoch: host [epochs] mean batch loss,
+ * or NULL.  Blocks until done. */
+mf_status mf_flow_train(mf_flow* f, const float* y, const float* w, int64_t n, const mf_flow_train_opts* o,
+                        double* loss_per_epoch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_FLOW_H */

@@ -61,6 +61,27 @@ class _IntegrateOpts(ctypes.Structure):
         ("edges_in", ctypes.c_void_p),
         ("edges_out", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
+        ("flow", ctypes.c_void_p),
+    ]
+
+
+class _FlowConfig(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("n_layers", ctypes.c_int32),
+        ("hidden", ctypes.c_int32),
+        ("bins", ctypes.c_int32),
+        ("max_batch", ctypes.c_int64),
+    ]
+
+
+class _FlowTrainOpts(ctypes.Structure):
+    _fields_ = [
+        ("epochs", ctypes.c_int32),
+        ("batch", ctypes.c_int64),
+        ("lr", ctypes.c_double),
+        ("lr_final", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -82,7 +103,10 @@ class _Result(ctypes.Structure):
 
 
 EXPORTS = ("mf_process_create", "mf_process_destroy", "mf_process_ndim", "mf_last_error", "mf_integrand",
-           "mf_integrand_grad", "mf_vegas_refine", "mf_integrate", "mf_grad")
+           "mf_integrand_grad", "mf_vegas_refine", "mf_integrate", "mf_grad", "mf_weights", "mf_weight_stats",
+           "mf_flow_create", "mf_flow_destroy", "mf_flow_ndim", "mf_flow_param_count", "mf_flow_masks",
+           "mf_flow_set_params", "mf_flow_get_params", "mf_flow_forward", "mf_flow_inverse", "mf_flow_loss_grad",
+           "mf_flow_adam_step", "mf_flow_train")
 
 _lib = None
 
@@ -113,6 +137,34 @@ def lib():
         L.mf_integrate.restype = i32
         L.mf_grad.argtypes = [P, ctypes.POINTER(_IntegrateOpts), P, P]
         L.mf_grad.restype = i32
+        L.mf_weights.argtypes = [P, P, ctypes.c_uint64, i64, P, P, P]
+        L.mf_weights.restype = i32
+        L.mf_weight_stats.argtypes = [P, i64, d, P, P]
+        L.mf_weight_stats.restype = i32
+        L.mf_flow_create.argtypes = [ctypes.POINTER(_FlowConfig), ctypes.POINTER(P)]
+        L.mf_flow_create.restype = i32
+        L.mf_flow_destroy.argtypes = [P]
+        L.mf_flow_destroy.restype = None
+        L.mf_flow_ndim.argtypes = [P]
+        L.mf_flow_ndim.restype = ctypes.c_int
+        L.mf_flow_param_count.argtypes = [P]
+        L.mf_flow_param_count.restype = i64
+        L.mf_flow_masks.argtypes = [P, P]
+        L.mf_flow_masks.restype = i32
+        L.mf_flow_set_params.argtypes = [P, P, i64]
+        L.mf_flow_set_params.restype = i32
+        L.mf_flow_get_params.argtypes = [P, P, i64]
+        L.mf_flow_get_params.restype = i32
+        L.mf_flow_forward.argtypes = [P, P, i64, P, P, P]
+        L.mf_flow_forward.restype = i32
+        L.mf_flow_inverse.argtypes = [P, P, i64, P, P, P]
+        L.mf_flow_inverse.restype = i32
+        L.mf_flow_loss_grad.argtypes = [P, P, P, i64, P, ctypes.POINTER(d), P]
+        L.mf_flow_loss_grad.restype = i32
+        L.mf_flow_adam_step.argtypes = [P, d, P]
+        L.mf_flow_adam_step.restype = i32
+        L.mf_flow_train.argtypes = [P, P, P, i64, ctypes.POINTER(_FlowTrainOpts), P]
+        L.mf_flow_train.restype = i32
         _lib = L
     return _lib
 
@@ -234,9 +286,11 @@ class Process:
         return w, dw
 
     def integrate(self, n_iter: int, n_events: int, target_rel_err: float = 0.0, warmup: int = 0, adapt: bool = True,
-                  iter_offset: int = 0, edges_in=None, edges_out=None, stream=None) -> IntegrationResult:
-        """VEGAS integration entirely on the device -- mf_integrate."""
+                  iter_offset: int = 0, edges_in=None, edges_out=None, stream=None,
+                  flow: "Flow | None" = None) -> IntegrationResult:
+        """VEGAS integration entirely on the device -- mf_integrate (flow: learned proposal, frozen grid)."""
         o = _IntegrateOpts()
+        o.flow = flow._h.value if flow is not None else None
         o.n_iter, o.n_events, o.target_rel_err = n_iter, n_events, target_rel_err
         o.warmup_iters_discarded, o.adapt, o.iter_offset = warmup, int(adapt), iter_offset
         o.edges_in = _dev_ptr(edges_in) if edges_in is not None else None
@@ -252,6 +306,17 @@ class Process:
         return IntegrationResult(r.integral, r.error, r.chi2_dof, k, r.n_events_total, r.n_nonzero, r.n_nonfinite,
                                  r.seconds, r.time_to_target, r.kernel_seconds, Ii[:k].copy(), Ie[:k].copy())
 
+    def weights(self, it: int, n: int, flow: "Flow | None" = None, want_y: bool = False, stream=None):
+        """(w[n] float64, y[ndim][n] float32 or None) of one frozen-grid sample -- mf_weights."""
+        import torch
+
+        w = torch.empty(n, dtype=torch.float64, device="cuda")
+        y = torch.empty((self.ndim, n), dtype=torch.float32, device="cuda") if want_y else None
+        _check(lib().mf_weights(self._h, flow._h.value if flow is not None else None, it, n,
+                                _dev_ptr(y, "float32") if y is not None else None, _dev_ptr(w),
+                                _stream_ptr(stream)))
+        return w, y
+
     def grad(self, n_events: int, iter_offset: int = 0, edges_in=None, stream=None):
         """(values[10], errors[10]): sigma, d sigma/d m_t, d sigma/d theta_0..7 -- mf_grad."""
         o = _IntegrateOpts()
@@ -262,6 +327,118 @@ class Process:
         err = np.zeros(10)
         _check(lib().mf_grad(self._h, ctypes.byref(o), out.ctypes.data, err.ctypes.data))
         return out, err
+
+
+def weight_stats(w, q: float = 0.999, stream=None) -> dict:
+    """mean, max, q-quantile and non-zero count of non-negative device weights -- mf_weight_stats."""
+    out = np.zeros(4)
+    _check(lib().mf_weight_stats(_dev_ptr(w), w.numel(), q, out.ctypes.data, _stream_ptr(stream)))
+    return {"mean": out[0], "max": out[1], "quantile": out[2], "nonzero": int(out[3])}
+
+
+class Flow:
+    """Coupling normalising flow on the device (include/mf_flow.h)."""
+
+    HIDDEN = 256
+    BINS = 32
+
+    def __init__(self, ndim: int, n_layers: int = 6, max_batch: int = 16384):
+        c = _FlowConfig(ndim, n_layers, self.HIDDEN, self.BINS, max_batch)
+        h = ctypes.c_void_p()
+        _check(lib().mf_flow_create(ctypes.byref(c), ctypes.byref(h)))
+        self._h = h
+        self.ndim, self.n_layers, self.max_batch = ndim, n_layers, max_batch
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().mf_flow_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def param_count(self) -> int:
+        return lib().mf_flow_param_count(self._h)
+
+    def masks(self) -> np.ndarray:
+        out = np.zeros((self.n_layers, self.ndim), dtype=np.uint8)
+        _check(lib().mf_flow_masks(self._h, out.ctypes.data))
+        return out.astype(bool)
+
+    def set_params(self, flat: np.ndarray):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib().mf_flow_set_params(self._h, flat.ctypes.data, flat.size))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.param_count, dtype=np.float32)
+        _check(lib().mf_flow_get_params(self._h, out.ctypes.data, out.size))
+        return out
+
+    @staticmethod
+    def flatten(layers) -> np.ndarray:
+        """Concatenate per-layer dicts (W1, b1, W2, b2, W3, b3; [in][out]) in the library's layout."""
+        return np.concatenate([np.asarray(p[k], dtype=np.float64).ravel()
+                               for p in layers for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+    def unflatten(self, flat: np.ndarray):
+        """Inverse of flatten for this flow's masks."""
+        out, off = [], 0
+        H, NO = self.HIDDEN, 2 * self.BINS + 1
+        for m in self.masks():
+            dA, dB = int((~m).sum()), int(m.sum())
+            shapes = [("W1", (dA, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (H, dB * NO)),
+                      ("b3", (dB * NO,))]
+            p = {}
+            for k, shp in shapes:
+                size = int(np.prod(shp))
+                p[k] = np.asarray(flat[off:off + size], dtype=np.float64).reshape(shp)
+                off += size
+            out.append(p)
+        return out
+
+    def _run(self, fn, x, stream):
+        import torch
+
+        n = x.shape[1]
+        out = torch.empty_like(x)
+        lq = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(fn(self._h, _dev_ptr(x, "float32"), n, _dev_ptr(out, "float32"), _dev_ptr(lq, "float32"),
+                  _stream_ptr(stream)))
+        return out, lq
+
+    def forward(self, y, stream=None):
+        """(z, log q(y)) for y [ndim][n] float32 -- mf_flow_forward."""
+        return self._run(lib().mf_flow_forward, y, stream)
+
+    def inverse(self, z, stream=None):
+        """(y, log q(y)) for z [ndim][n] float32 -- mf_flow_inverse."""
+        return self._run(lib().mf_flow_inverse, z, stream)
+
+    def loss_grad(self, y, w, stream=None):
+        """(loss, gradient [param_count] float32 device tensor) of one batch -- mf_flow_loss_grad."""
+        import torch
+
+        g = torch.empty(self.param_count, dtype=torch.float32, device=y.device)
+        loss = ctypes.c_double()
+        _check(lib().mf_flow_loss_grad(self._h, _dev_ptr(y, "float32"), _dev_ptr(w, "float32"), y.shape[1],
+                                       _dev_ptr(g, "float32"), ctypes.byref(loss), _stream_ptr(stream)))
+        return loss.value, g
+
+    def adam_step(self, lr: float, stream=None):
+        _check(lib().mf_flow_adam_step(self._h, lr, _stream_ptr(stream)))
+
+    def train(self, y, w, epochs: int, batch: int = 16384, lr: float = 1e-3, lr_final: float = 1e-5,
+              stream=None) -> np.ndarray:
+        """Mean batch loss per epoch -- mf_flow_train."""
+        o = _FlowTrainOpts(epochs, batch, lr, lr_final, _stream_ptr(stream))
+        out = np.zeros(epochs)
+        _check(lib().mf_flow_train(self._h, _dev_ptr(y, "float32"), _dev_ptr(w, "float32"), y.shape[1],
+                                   ctypes.byref(o), out.ctypes.data))
+        return out
 
 
 def vegas_refine(edges, hist, alpha: float = 1.5, stream=None):

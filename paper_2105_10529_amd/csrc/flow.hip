@@ -1,0 +1,1089 @@
+// Coupling normalising flow (piecewise-quadratic coupling layers, Mueller et
+// al. 2019) on gfx950: forward/inverse layer kernel, backward kernels, Adam,
+// and the flow part of the C ABI.
+//
+// Kernels:
+//   k_coupling      one coupling layer for a tile of 64 events: the three
+//                   dense layers as BF16 MFMA products (v_mfma_f32_16x16x32_bf16,
+//                   FP32 accumulation) with the hidden activations resident in
+//                   LDS, then the FP32 piecewise-quadratic CDF (or its inverse)
+//                   of each transformed coordinate; optionally writes the
+//                   activations needed by the backward pass
+//   k_pq_backward   derivatives of the PQ transform with respect to its input
+//                   and its 2K+1 logits (per event and transformed coordinate)
+//   k_gemm          LDS-staged BF16 MFMA product with split-K for the weight
+//                   gradients and a LeakyReLU-derivative epilogue for the
+//                   activation gradients
+//   k_colsum / k_reduce_grad   ordered reductions into the FP32 gradient
+//   k_adam          Adam on the FP32 masters and refresh of the BF16 copies
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/mf_flow.h"
+#include "status.h"
+
+namespace mf {
+namespace flow {
+
+constexpr int H = 256;        // hidden width
+constexpr int KB = 32;        // PQ bins
+constexpr int NO = 2 * KB + 1;  // logits per transformed coordinate
+constexpr int NOP = 80;       // NO padded to five 16-column MFMA tiles
+constexpr int KA = 32;        // first-layer k width: inputs split as BF16 hi (k < 16) + lo (k >= 16)
+constexpr int KLO = 16;       // offset of the low parts
+constexpr int T = 64;         // events per workgroup of the layer kernel
+constexpr int LDO = NOP + 1;  // LDS row stride (floats) of one coordinate's logits
+constexpr int MAXD = 16;
+constexpr int MAXL = 8;
+constexpr float SLOPE = 0.01f;
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct LayerDev {
+  int dA, dB;
+  int a_idx[MAXD];
+  int b_idx[MAXD];
+  const bf16* W1t;   // [H][KA]      (W1 transposed, at k = i and k = KLO + i)
+  const float* b1;   // [H]
+  const bf16* W2t;   // [H][H]       (W2 transposed)
+  const float* b2;   // [H]
+  const bf16* W3t;   // [dB*NOP][H]  (W3 transposed, zero-padded outputs)
+  const float* b3p;  // [dB*NOP]
+};
+
+struct LayerCache {
+  bf16* xa;    // [n][KA]  inputs of the first dense layer (hi | lo)
+  bf16* h1;    // [n][H]
+  bf16* h2;    // [n][H]
+  float* o;    // [n][dB][NOP] logits
+  float* lin;  // [d][n]   layer input
+};
+
+__device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Hidden activations in LDS: [T][H] bf16 with the 16-byte chunks of a row
+// permuted by the row index, so that the 16 rows read by one fragment load
+// fall in different banks.
+__device__ __forceinline__ int hs(int m, int k) { return m * H + ((((k >> 3) ^ (m & 15))) << 3) + (k & 7); }
+
+__device__ __forceinline__ float leaky(float v) { return v > 0.0f ? v : SLOPE * v; }
+
+// ------------------------------------------------------------ PQ transform
+// Softmax widths and normalised vertex heights from the 2K+1 logits.
+__device__ __forceinline__ void pq_params(const float* o, float* W, float* V) {
+  float mw = o[0];
+#pragma unroll
+  for (int k = 1; k < KB; ++k) mw = fmaxf(mw, o[k]);
+  float sw = 0.0f;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    W[k] = __expf(o[k] - mw);
+    sw += W[k];
+  }
+  const float isw = 1.0f / sw;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) W[k] *= isw;
+  float mv = o[KB];
+#pragma unroll
+  for (int k = 1; k <= KB; ++k) mv = fmaxf(mv, o[KB + k]);
+#pragma unroll
+  for (int k = 0; k <= KB; ++k) V[k] = __expf(o[KB + k] - mv);
+  float N = 0.0f;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) N += 0.5f * (V[k] + V[k + 1]) * W[k];
+  const float iN = 1.0f / N;
+#pragma unroll
+  for (int k = 0; k <= KB; ++k) V[k] *= iN;
+}
+
+// Bin b of a point: the largest k >= 1 with edge_k <= t (else 0), where
+// edge_k is the running sum of W (by_area = 0) or of the bin areas
+// (by_area = 1).  Returns the bin's left edge S_b, its area offset A_b,
+// W_b, V_b, V_b+1 through static register indices only.
+struct Bin {
+  int b;
+  float S, A, Wb, Vb, Vb1;
+};
+__device__ __forceinline__ Bin find_bin(const float* W, const float* V, float t, bool by_area) {
+  Bin r{0, 0.0f, 0.0f, W[0], V[0], V[1]};
+  float S = W[0], A = 0.5f * (V[0] + V[1]) * W[0];
+#pragma unroll
+  for (int k = 1; k < KB; ++k) {
+    const bool take = (by_area ? A : S) <= t;
+    r.b = take ? k : r.b;
+    r.S = take ? S : r.S;
+    r.A = take ? A : r.A;
+    r.Wb = take ? W[k] : r.Wb;
+    r.Vb = take ? V[k] : r.Vb;
+    r.Vb1 = take ? V[k + 1] : r.Vb1;
+    S += W[k];
+    A += 0.5f * (V[k] + V[k + 1]) * W[k];
+  }
+  return r;
+}
+
+// --------------------------------------------------------- coupling layer
+// One layer for events [64 blockIdx.x, +64): y is [d][n] and is transformed
+// in place (the kept coordinates are only read).  INVERSE selects the
+// sampling direction.  logq[e] is set (first layer) or accumulated.
+template <bool INVERSE, bool CACHE>
+__global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict__ y, int64_t n, float* __restrict__ logq,
+                                                  int first, LayerCache C, int d) {
+  __shared__ __attribute__((aligned(16))) bf16 h1[T * H];  // also the logits of one coordinate (FP32)
+  __shared__ __attribute__((aligned(16))) bf16 h2[T * H];  // also the first-layer inputs
+  bf16* xa = h2;                                           // [T][KA]
+  float* out = reinterpret_cast<float*>(h1);               // [T][LDO]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t e0 = (int64_t)blockIdx.x * T;
+  const int row = lane & 15, quad = lane >> 4;
+
+  // inputs of the first dense layer (events fastest, so the reads coalesce):
+  // each kept coordinate as a BF16 pair hi + lo (about 16 significant bits),
+  // multiplied by the same weight column
+  for (int idx = tid; idx < T * KLO; idx += 256) {
+    const int m = idx % T, i = idx / T;
+    const int64_t e = e0 + m;
+    float v = 0.0f;
+    if (i < L.dA && e < n) v = y[(int64_t)L.a_idx[i] * n + e];
+    const bf16 hi = (bf16)v;
+    const bf16 lo = (bf16)(v - (float)hi);
+    const int il = i + KLO;
+    xa[m * KA + (((i >> 3) ^ (m & 3)) << 3) + (i & 7)] = hi;
+    xa[m * KA + (((il >> 3) ^ (m & 3)) << 3) + (il & 7)] = lo;
+    if (CACHE && e < n) {
+      C.xa[e * KA + i] = hi;
+      C.xa[e * KA + il] = lo;
+    }
+  }
+  if (CACHE) {
+    for (int idx = tid; idx < T * d; idx += 256) {
+      const int m = idx % T, j = idx / T;
+      const int64_t e = e0 + m;
+      if (e < n) C.lin[(int64_t)j * n + e] = y[(int64_t)j * n + e];
+    }
+  }
+  __syncthreads();
+
+  // dense layer 1: [T x KA] . [KA x H]; wave w owns hidden columns [64w, 64w+64)
+  {
+    bf16x8 a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = 16 * r + row;
+      a[r] = *reinterpret_cast<const bf16x8*>(xa + m * KA + ((quad ^ (m & 3)) << 3));
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int col = 64 * wave + 16 * c + row;
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(L.W1t + col * KA + 8 * quad);
+      const float bias = L.b1[64 * wave + 16 * c + row];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = mfma16(a[r], b, acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h1[hs(16 * r + 4 * quad + i, col)] = (bf16)leaky(acc[i] + bias);
+      }
+    }
+  }
+  __syncthreads();
+
+  // dense layer 2: [T x H] . [H x H]
+  {
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int ks = 0; ks < H / 32; ++ks) {
+      bf16x8 a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        a[r] = *reinterpret_cast<const bf16x8*>(h1 + hs(16 * r + row, 32 * ks + 8 * quad));
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        b[c] = *reinterpret_cast<const bf16x8*>(L.W2t + (64 * wave + 16 * c + row) * H + 32 * ks + 8 * quad);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = mfma16(a[r], b[c], acc[r][c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int col = 64 * wave + 16 * c + row;
+      const float bias = L.b2[col];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h2[hs(16 * r + 4 * quad + i, col)] = (bf16)leaky(acc[r][c][i] + bias);
+    }
+  }
+  __syncthreads();
+  if (CACHE) {
+    // 16-byte chunks, un-permuted, rows of H contiguous
+    for (int idx = tid; idx < T * (H / 8); idx += 256) {
+      const int m = idx / (H / 8), ch = idx % (H / 8);
+      const int64_t e = e0 + m;
+      if (e >= n) continue;
+      const int src = m * H + ((ch ^ (m & 15)) << 3);
+      *reinterpret_cast<bf16x8*>(C.h1 + e * H + 8 * ch) = *reinterpret_cast<const bf16x8*>(h1 + src);
+      *reinterpret_cast<bf16x8*>(C.h2 + e * H + 8 * ch) = *reinterpret_cast<const bf16x8*>(h2 + src);
+    }
+    __syncthreads();
+  }
+
+  // dense layer 3 and the PQ transform, one transformed coordinate at a time
+  float lq = 0.0f;
+  for (int c = 0; c < L.dB; ++c) {
+    {
+      f32x4 acc[5];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      const bf16* W3 = L.W3t + (int64_t)c * NOP * H;
+      for (int ks = 0; ks < H / 32; ++ks) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(h2 + hs(16 * wave + row, 32 * ks + 8 * quad));
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8*>(W3 + (16 * t + row) * H + 32 * ks + 8 * quad);
+          acc[t] = mfma16(a, b, acc[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        const int col = 16 * t + row;
+        const float bias = L.b3p[c * NOP + col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[(16 * wave + 4 * quad + i) * LDO + col] = acc[t][i] + bias;
+      }
+    }
+    __syncthreads();
+    if (CACHE) {
+      for (int idx = tid; idx < T * NOP; idx += 256) {
+        const int m = idx / NOP, col = idx % NOP;
+        const int64_t e = e0 + m;
+        if (e < n) C.o[(e * L.dB + c) * NOP + col] = out[m * LDO + col];
+      }
+    }
+    if (tid < T) {
+      const int64_t e = e0 + tid;
+      if (e < n) {
+        float W[KB], V[KB + 1];
+        pq_params(out + tid * LDO, W, V);
+        float* yp = y + (int64_t)L.b_idx[c] * n + e;
+        const float t = *yp;
+        const Bin B = find_bin(W, V, t, INVERSE);
+        const float dV = B.Vb1 - B.Vb;
+        float res, pdf;
+        if (!INVERSE) {
+          const float al = fminf(fmaxf((t - B.S) / B.Wb, 0.0f), 1.0f);
+          res = B.A + B.Wb * (al * B.Vb + 0.5f * al * al * dV);
+          pdf = B.Vb + al * dV;
+        } else {
+          const float cc = (t - B.A) / B.Wb;
+          const float disc = fmaxf(B.Vb * B.Vb + 2.0f * dV * cc, 0.0f);
+          float al = 2.0f * cc / (B.Vb + sqrtf(disc));
+          al = fminf(fmaxf(al, 0.0f), 1.0f);
+          res = B.S + al * B.Wb;
+          pdf = B.Vb + al * dV;
+        }
+        *yp = res;
+        lq += __logf(pdf);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < T) {
+    const int64_t e = e0 + tid;
+    if (e < n) logq[e] = first ? lq : logq[e] + lq;
+  }
+}
+
+// ------------------------------------------------------------ PQ backward
+// For event e and transformed coordinate c (thread e + n c): given the
+// gradient gz of the loss with respect to the layer output at that coordinate
+// (g[j][e]) and glp = dL/dlog q = -w_e / sum w, replaces g[j][e] by the
+// gradient with respect to the layer input and writes the gradient with
+// respect to the 2K+1 logits (BF16, padded to NOP with zeros).
+__global__ void __launch_bounds__(256) k_pq_backward(LayerDev L, LayerCache C, int64_t n, float* __restrict__ g,
+                                                     const float* __restrict__ w, const float* __restrict__ wsum,
+                                                     bf16* __restrict__ go) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * L.dB) return;
+  const int c = (int)(idx / n);
+  const int64_t e = idx % n;
+  const int j = L.b_idx[c];
+  const float* o = C.o + (e * L.dB + c) * NOP;
+  float ol[NO];
+#pragma unroll
+  for (int k = 0; k < NO; ++k) ol[k] = o[k];
+  float W[KB], V[KB + 1];
+  pq_params(ol, W, V);
+  const float yv = C.lin[(int64_t)j * n + e];
+  const Bin B = find_bin(W, V, yv, false);
+  const float al = fminf(fmaxf((yv - B.S) / B.Wb, 0.0f), 1.0f);
+  const float dV = B.Vb1 - B.Vb;
+  const float pdf = B.Vb + al * dV;
+  const float gz = g[(int64_t)j * n + e];
+  const float glp = -w[e] / wsum[0];
+  const float gp = glp / pdf;
+  // d/dW_k and d/dV_k of (gz z + glp log pdf) at fixed logits of other bins
+  float GW[KB], GV[KB + 1];
+#pragma unroll
+  for (int k = 0; k <= KB; ++k) GV[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const bool below = k < B.b, at = k == B.b;
+    const float dz = below ? 0.5f * (V[k] + V[k + 1]) - B.Vb - al * dV : (at ? -0.5f * al * al * dV : 0.0f);
+    const float dp = below ? -dV / B.Wb : (at ? -al * dV / B.Wb : 0.0f);
+    GW[k] = gz * dz + gp * dp;
+    // area terms of z: A_b = sum_{k<b} W_k (V_k + V_k+1)/2
+    if (below) {
+      GV[k] += gz * 0.5f * W[k];
+      GV[k + 1] += gz * 0.5f * W[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k <= KB; ++k) {
+    const bool at = k == B.b, next = k == B.b + 1;
+    GV[k] += at ? gz * B.Wb * (al - 0.5f * al * al) + gp * (1.0f - al) : 0.0f;
+    GV[k] += next ? gz * B.Wb * 0.5f * al * al + gp * al : 0.0f;
+  }
+  g[(int64_t)j * n + e] = gz * pdf + glp * (dV / B.Wb) / pdf;
+  // through V = exp(v) / N, N = sum_k W_k (exp(v_k) + exp(v_k+1)) / 2, and W = softmax
+  float SG = 0.0f;
+#pragma unroll
+  for (int k = 0; k <= KB; ++k) SG += GV[k] * V[k];
+  float SW = 0.0f;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    GW[k] -= SG * 0.5f * (V[k] + V[k + 1]);
+    SW += W[k] * GW[k];
+  }
+  bf16* dst = go + e * ((int64_t)L.dB * NOP) + (int64_t)c * NOP;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) dst[k] = (bf16)(W[k] * (GW[k] - SW));
+#pragma unroll
+  for (int k = 0; k <= KB; ++k) {
+    const float wl = k > 0 ? W[k - 1] : 0.0f, wr = k < KB ? W[k] : 0.0f;
+    dst[KB + k] = (bf16)(V[k] * (GV[k] - SG * 0.5f * (wl + wr)));
+  }
+#pragma unroll
+  for (int k = NO; k < NOP; ++k) dst[k] = (bf16)0.0f;
+}
+
+// ------------------------------------------------------------------ GEMM
+// C[M x N] = sum over k in the z-th chunk of A(m,k) B(k,n), BF16 operands,
+// FP32 accumulation, tile 64 x 64 per workgroup, k-step 32 staged in LDS.
+//   A_KC: A(m,k) = A[m lda + k] (1) or A[k lda + m] (0)
+//   B_NC: B(k,n) = B[k ldb + n] (1) or B[n ldb + k] (0)
+//   EPI 0: FP32 store to Cf + z zs + m ldc + n (split-K partials)
+//   EPI 1: BF16 store to Cb[m ldc + n] of acc * (ref[m ldr + n] > 0 ? 1 : slope)
+struct GemmArgs {
+  const bf16* A;
+  int64_t lda;
+  const bf16* B;
+  int64_t ldb;
+  int M, N;
+  int64_t K, kchunk;
+  float* Cf;
+  int64_t zs;
+  bf16* Cb;
+  const bf16* ref;
+  int64_t ldc, ldr;
+};
+
+constexpr int GLD = 40;  // LDS row stride (bf16) of a staged 32-wide k slice
+
+template <int A_KC, int B_NC, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) bf16 As[64 * GLD];
+  __shared__ __attribute__((aligned(16))) bf16 Bs[64 * GLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row = lane & 15, quad = lane >> 4;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t ke = kb + g.kchunk < g.K ? kb + g.kchunk : g.K;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t k0 = kb; k0 < ke; k0 += 32) {
+    // stage A: 64 x 32
+    if (A_KC) {
+      const int m = tid >> 2, k8 = (tid & 3) * 8;
+      const int gm = m0 + m;
+      bf16x8 v;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t gk = k0 + k8 + i;
+        v[i] = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.lda + gk] : (bf16)0.0f;
+      }
+      *reinterpret_cast<bf16x8*>(As + m * GLD + k8) = v;
+    } else {
+      const int k = tid >> 3, m8 = (tid & 7) * 8;
+      const int64_t gk = k0 + k;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gm = m0 + m8 + i;
+        As[(m8 + i) * GLD + k] = (gm < g.M && gk < ke) ? g.A[gk * g.lda + gm] : (bf16)0.0f;
+      }
+    }
+    // stage B: 32 x 64, stored n-major
+    if (B_NC) {
+      const int k = tid >> 3, n8 = (tid & 7) * 8;
+      const int64_t gk = k0 + k;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gn = n0 + n8 + i;
+        Bs[(n8 + i) * GLD + k] = (gn < g.N && gk < ke) ? g.B[gk * g.ldb + gn] : (bf16)0.0f;
+      }
+    } else {
+      const int nn = tid >> 2, k8 = (tid & 3) * 8;
+      const int gn = n0 + nn;
+      bf16x8 v;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t gk = k0 + k8 + i;
+        v[i] = (gn < g.N && gk < ke) ? g.B[(int64_t)gn * g.ldb + gk] : (bf16)0.0f;
+      }
+      *reinterpret_cast<bf16x8*>(Bs + nn * GLD + k8) = v;
+    }
+    __syncthreads();
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(As + (wm + 16 * i + row) * GLD + 8 * quad);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(Bs + (wn + 16 * j + row) * GLD + 8 * quad);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gn = n0 + wn + 16 * j + row;
+      if (gn >= g.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + 16 * i + 4 * quad + r;
+        if (gm >= g.M) continue;
+        if (EPI == 0) {
+          g.Cf[(int64_t)blockIdx.z * g.zs + (int64_t)gm * g.ldc + gn] = acc[i][j][r];
+        } else {
+          const float s = (float)g.ref[(int64_t)gm * g.ldr + gn] > 0.0f ? 1.0f : SLOPE;
+          g.Cb[(int64_t)gm * g.ldc + gn] = (bf16)(acc[i][j][r] * s);
+        }
+      }
+    }
+}
+
+// Column sums of X[rows][ld] (first ncols columns) over row chunk z into
+// part[z][ncols] (FP32, in row order).
+__global__ void k_colsum(const bf16* __restrict__ X, int64_t rows, int ncols, int64_t ld, int64_t rchunk,
+                         float* __restrict__ part) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncols) return;
+  const int64_t r0 = (int64_t)blockIdx.y * rchunk;
+  const int64_t r1 = r0 + rchunk < rows ? r0 + rchunk : rows;
+  float s = 0.0f;
+  for (int64_t r = r0; r < r1; ++r) s += (float)X[r * ld + col];
+  part[(int64_t)blockIdx.y * ncols + col] = s;
+}
+
+// out[m ldo + map(n)] = sum_z part[z][m][n] (+ part[z][m + fold][n] when
+// fold > 0: the two halves of a split input) for m < m_real; the column map
+// drops the padding of groups of gpad columns to greal (gpad = 0: identity).
+__global__ void k_reduce_grad(const float* __restrict__ part, int Z, int M, int N, int m_real, int gpad, int greal,
+                              float* __restrict__ out, int ldo, int fold) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m_real * N) return;
+  const int m = (int)(idx / N), nn = (int)(idx % N);
+  int col = nn;
+  if (gpad) {
+    if (nn % gpad >= greal) return;
+    col = (nn / gpad) * greal + nn % gpad;
+  }
+  float s = 0.0f;
+  for (int z = 0; z < Z; ++z) {
+    s += part[((int64_t)z * M + m) * N + nn];
+    if (fold) s += part[((int64_t)z * M + m + fold) * N + nn];
+  }
+  out[(int64_t)m * ldo + col] = s;
+}
+
+// g[a_idx[i]][e] += gx[e][i] (gradient reaching the kept coordinates)
+__global__ void k_add_gx(LayerDev L, const float* __restrict__ gx, int64_t n, float* __restrict__ g) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * L.dA) return;
+  const int i = (int)(idx / n);
+  const int64_t e = idx % n;
+  g[(int64_t)L.a_idx[i] * n + e] += gx[e * KA + i];
+}
+
+// sum of w over the batch (one block, fixed order) and the loss
+// -sum w logq / sum w
+__global__ void k_wsum(const float* __restrict__ w, int64_t n, float* __restrict__ out) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) a += w[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)s[0];
+}
+__global__ void k_loss(const float* __restrict__ w, const float* __restrict__ logq, int64_t n,
+                       const float* __restrict__ wsum, float* __restrict__ out) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) a += (double)w[i] * logq[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)(-s[0] / wsum[0]);
+}
+
+// Parameter segments of one layer in the master layout and the BF16 copies.
+struct SegLayer {
+  int64_t off;  // start of the layer in the master array
+  int dA, dB;
+  bf16* W1t;
+  bf16* W2t;
+  bf16* W3t;
+  float* b3p;
+};
+struct SegTable {
+  int nl;
+  SegLayer l[MAXL];
+};
+
+// Adam on the masters (in place) and refresh of the BF16 copies.  With
+// do_adam = 0 only the copies are refreshed.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m1,
+                       float* __restrict__ m2, int64_t count, float lr, float c1, float c2, int do_adam, SegTable S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float v = p[i];
+  if (do_adam) {
+    const float gg = gr[i];
+    const float a = 0.9f * m1[i] + 0.1f * gg;
+    const float b = 0.999f * m2[i] + 0.001f * gg * gg;
+    m1[i] = a;
+    m2[i] = b;
+    v -= lr * (a / c1) / (sqrtf(b / c2) + 1e-8f);
+    p[i] = v;
+  }
+  int l = 0;
+  while (l + 1 < S.nl && i >= S.l[l + 1].off) ++l;
+  const SegLayer& s = S.l[l];
+  int64_t r = i - s.off;
+  const int64_t nW1 = (int64_t)s.dA * H, nW2 = (int64_t)H * H, nO = (int64_t)s.dB * NO;
+  if (r < nW1) {
+    const int a = (int)(r / H), j = (int)(r % H);
+    s.W1t[j * KA + a] = (bf16)v;
+    s.W1t[j * KA + KLO + a] = (bf16)v;
+    return;
+  }
+  r -= nW1 + H;  // b1 is used in FP32 from the master array
+  if (r < 0) return;
+  if (r < nW2) {
+    const int a = (int)(r / H), j = (int)(r % H);
+    s.W2t[(int64_t)j * H + a] = (bf16)v;
+    return;
+  }
+  r -= nW2 + H;
+  if (r < 0) return;
+  if (r < H * nO) {
+    const int a = (int)(r / nO), o = (int)(r % nO);
+    s.W3t[((int64_t)(o / NO) * NOP + o % NO) * H + a] = (bf16)v;
+    return;
+  }
+  r -= H * nO;
+  s.b3p[(r / NO) * NOP + r % NO] = v;
+}
+
+}  // namespace flow
+}  // namespace mf
+
+using namespace mf;
+using namespace mf::flow;
+
+struct mf_flow {
+  mf_flow_config cfg;
+  int d, nl;
+  int64_t count = 0;
+  std::vector<std::vector<uint8_t>> mask;
+  LayerDev L[MAXL];
+  SegTable seg;
+  int64_t loff[MAXL];
+  float* d_p = nullptr;   // masters
+  float* d_g = nullptr;   // gradient
+  float* d_m1 = nullptr;  // Adam moments
+  float* d_m2 = nullptr;
+  bf16* d_w16 = nullptr;  // BF16 weight copies of every layer
+  float* d_b3p = nullptr;
+  int64_t step = 0;
+  // training caches and work buffers (max_batch events)
+  int64_t cap = 0;
+  LayerCache cache[MAXL];
+  void* d_cachemem = nullptr;
+  float* d_y = nullptr;     // [d][cap]
+  float* d_gy = nullptr;    // [d][cap]
+  float* d_lq = nullptr;    // [cap]
+  bf16* d_go = nullptr;     // [cap][dBmax*NOP]
+  bf16* d_ga2 = nullptr;    // [cap][H]
+  bf16* d_ga1 = nullptr;    // [cap][H]
+  float* d_gx = nullptr;    // [cap][KA]
+  float* d_part = nullptr;  // split-K partials
+  size_t part_cap = 0;
+  float* d_scal = nullptr;  // wsum, loss
+  std::vector<float*> d_losses;
+};
+
+namespace {
+
+constexpr int64_t SPLITK_CHUNK = 1024;
+
+mf_status launch_err(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(MF_EDEVICE, "%s launch: %s", what, hipGetErrorString(e));
+  return MF_OK;
+}
+
+template <int A_KC, int B_NC, int EPI>
+void gemm(const GemmArgs& a, int Z, hipStream_t s) {
+  dim3 grid((a.N + 63) / 64, (a.M + 63) / 64, Z);
+  hipLaunchKernelGGL((k_gemm<A_KC, B_NC, EPI>), grid, dim3(256), 0, s, a);
+}
+
+// Weight gradient dW[in][out] = X^T G over the batch: X [n][ldx] (first M
+// columns), G [n][ldg] (first N columns), both BF16, split over events.
+void weight_grad(mf_flow* f, const bf16* X, int64_t ldx, int M, int m_real, const bf16* G, int64_t ldg, int N,
+                 int gpad, int greal, int64_t n, float* out, int ldo, hipStream_t s, int fold = 0) {
+  const int Z = (int)((n + SPLITK_CHUNK - 1) / SPLITK_CHUNK);
+  GemmArgs a{};
+  a.A = X;
+  a.lda = ldx;
+  a.B = G;
+  a.ldb = ldg;
+  a.M = M;
+  a.N = N;
+  a.K = n;
+  a.kchunk = SPLITK_CHUNK;
+  a.Cf = f->d_part;
+  a.zs = (int64_t)M * N;
+  a.ldc = N;
+  gemm<0, 1, 0>(a, Z, s);
+  const int64_t tot = (int64_t)m_real * N;
+  hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, f->d_part, Z, M, N, m_real,
+                     gpad, greal, out, ldo, fold);
+}
+
+// Bias gradient: column sums of G [n][ldg] over events.
+void bias_grad(mf_flow* f, const bf16* G, int64_t ldg, int N, int gpad, int greal, int64_t n, float* out,
+               hipStream_t s) {
+  const int Z = (int)((n + SPLITK_CHUNK - 1) / SPLITK_CHUNK);
+  hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256, Z), dim3(256), 0, s, G, n, N, ldg, SPLITK_CHUNK, f->d_part);
+  hipLaunchKernelGGL(k_reduce_grad, dim3((N + 255) / 256), dim3(256), 0, s, f->d_part, Z, 1, N, 1, gpad, greal, out,
+                     N, 0);
+}
+
+void run_layers(mf_flow* f, float* y, int64_t n, float* logq, bool inverse, bool cache, hipStream_t s) {
+  const unsigned nblk = (unsigned)((n + T - 1) / T);
+  for (int k = 0; k < f->nl; ++k) {
+    const int l = inverse ? f->nl - 1 - k : k;
+    LayerCache C = cache ? f->cache[l] : LayerCache{};
+    if (inverse)
+      hipLaunchKernelGGL((k_coupling<true, false>), dim3(nblk), dim3(256), 0, s, f->L[l], y, n, logq, k == 0 ? 1 : 0,
+                         C, f->d);
+    else if (cache)
+      hipLaunchKernelGGL((k_coupling<false, true>), dim3(nblk), dim3(256), 0, s, f->L[l], y, n, logq, k == 0 ? 1 : 0,
+                         C, f->d);
+    else
+      hipLaunchKernelGGL((k_coupling<false, false>), dim3(nblk), dim3(256), 0, s, f->L[l], y, n, logq,
+                         k == 0 ? 1 : 0, C, f->d);
+  }
+}
+
+mf_status refresh(mf_flow* f, hipStream_t s, int do_adam, float lr, float c1, float c2) {
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((f->count + 255) / 256)), dim3(256), 0, s, f->d_p, f->d_g, f->d_m1,
+                     f->d_m2, f->count, lr, c1, c2, do_adam, f->seg);
+  return launch_err("k_adam");
+}
+
+mf_status copy_points(mf_flow* f, const float* src, int64_t n, float* dst, hipStream_t s) {
+  if (src == dst) return MF_OK;
+  hipError_t e = hipMemcpyAsync(dst, src, sizeof(float) * f->d * n, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return set_error(MF_EDEVICE, "copy of points: %s", hipGetErrorString(e));
+  return MF_OK;
+}
+
+mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w, int64_t n, float* loss_dev,
+                         hipStream_t s) {
+  const int d = f->d;
+  hipError_t e = hipMemcpy2DAsync(f->d_y, sizeof(float) * n, y, sizeof(float) * ldy, sizeof(float) * n, d,
+                                  hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return set_error(MF_EDEVICE, "batch copy: %s", hipGetErrorString(e));
+  hipLaunchKernelGGL(k_wsum, dim3(1), dim3(256), 0, s, w, n, f->d_scal);
+  run_layers(f, f->d_y, n, f->d_lq, false, true, s);
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, s, w, f->d_lq, n, f->d_scal, loss_dev);
+  e = hipMemsetAsync(f->d_gy, 0, sizeof(float) * d * n, s);
+  if (e != hipSuccess) return set_error(MF_EDEVICE, "gradient clear: %s", hipGetErrorString(e));
+  for (int l = f->nl - 1; l >= 0; --l) {
+    const LayerDev& L = f->L[l];
+    const LayerCache& C = f->cache[l];
+    const int NB = L.dB * NOP, nO = L.dB * NO;
+    float* gW1 = f->d_g + f->loff[l];
+    float* gb1 = gW1 + (int64_t)L.dA * H;
+    float* gW2 = gb1 + H;
+    float* gb2 = gW2 + (int64_t)H * H;
+    float* gW3 = gb2 + H;
+    float* gb3 = gW3 + (int64_t)H * nO;
+    const int64_t tot = n * L.dB;
+    hipLaunchKernelGGL(k_pq_backward, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L, C, n, f->d_gy, w,
+                       f->d_scal, f->d_go);
+    bias_grad(f, f->d_go, NB, NB, NOP, NO, n, gb3, s);
+    weight_grad(f, C.h2, H, H, H, f->d_go, NB, NB, NOP, NO, n, gW3, nO, s);
+    // ga2 = (go W3^T) * leaky'(h2): A = go [n][NB], B(k=o, n=j) = W3t[o][j]
+    GemmArgs a{};
+    a.A = f->d_go;
+    a.lda = NB;
+    a.B = L.W3t;
+    a.ldb = H;
+    a.M = (int)n;
+    a.N = H;
+    a.K = NB;
+    a.kchunk = NB;
+    a.Cb = f->d_ga2;
+    a.ref = C.h2;
+    a.ldc = H;
+    a.ldr = H;
+    gemm<1, 1, 1>(a, 1, s);
+    bias_grad(f, f->d_ga2, H, H, 0, 0, n, gb2, s);
+    weight_grad(f, C.h1, H, H, H, f->d_ga2, H, H, 0, 0, n, gW2, H, s);
+    // ga1 = (ga2 W2^T) * leaky'(h1): B(k=j2, n=j1) = W2[j1][j2] = W2t[j2][j1]
+    a.A = f->d_ga2;
+    a.lda = H;
+    a.B = L.W2t;
+    a.ldb = H;
+    a.K = H;
+    a.kchunk = H;
+    a.Cb = f->d_ga1;
+    a.ref = C.h1;
+    gemm<1, 1, 1>(a, 1, s);
+    bias_grad(f, f->d_ga1, H, H, 0, 0, n, gb1, s);
+    weight_grad(f, C.xa, KA, KA, L.dA, f->d_ga1, H, H, 0, 0, n, gW1, H, s, KLO);
+    // gx = ga1 W1^T: B(k=j, n=i) = W1[i][j] = W1t[j][i]
+    GemmArgs b{};
+    b.A = f->d_ga1;
+    b.lda = H;
+    b.B = L.W1t;
+    b.ldb = KA;
+    b.M = (int)n;
+    b.N = KA;
+    b.K = H;
+    b.kchunk = H;
+    b.Cf = f->d_gx;
+    b.zs = 0;
+    b.ldc = KA;
+    gemm<1, 1, 0>(b, 1, s);
+    const int64_t ta = n * L.dA;
+    if (ta > 0)
+      hipLaunchKernelGGL(k_add_gx, dim3((unsigned)((ta + 255) / 256)), dim3(256), 0, s, L, f->d_gx, n, f->d_gy);
+  }
+  return launch_err("flow backward");
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
+  clear_error();
+  if (!cfg || !out) return set_error(MF_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (cfg->ndim < 2 || cfg->ndim > MAXD) return set_error(MF_EINVAL, "ndim must be in 2..%d", MAXD);
+  static_assert(MAXD - 1 <= KLO, "kept coordinates must fit the high half of the first-layer inputs");
+  if (cfg->n_layers < 1 || cfg->n_layers > MAXL) return set_error(MF_EINVAL, "n_layers must be in 1..%d", MAXL);
+  if (cfg->hidden != H) return set_error(MF_ENOTSUP, "only hidden width %d is built", H);
+  if (cfg->bins != KB) return set_error(MF_ENOTSUP, "only %d bins are built", KB);
+  if (cfg->max_batch < 1 || cfg->max_batch > (1LL << 24))
+    return set_error(MF_EINVAL, "max_batch must be in 1..2^24");
+  mf_flow* f = new mf_flow();
+  f->cfg = *cfg;
+  f->d = cfg->ndim;
+  f->nl = cfg->n_layers;
+  const int d = f->d;
+  int nb = 0;
+  while ((1 << nb) < d) ++nb;
+  if (nb < 1) nb = 1;
+  int64_t off = 0, w16 = 0, b3 = 0, dBmax = 0;
+  f->seg.nl = f->nl;
+  for (int l = 0; l < f->nl; ++l) {
+    std::vector<uint8_t> m(d);
+    LayerDev& L = f->L[l];
+    L.dA = L.dB = 0;
+    for (int j = 0; j < d; ++j) {
+      const int bit = (j >> (l % nb)) & 1;
+      m[j] = (uint8_t)(bit == (((l / nb) % 2 == 0) ? 1 : 0));
+      if (m[j]) L.b_idx[L.dB++] = j;
+      else L.a_idx[L.dA++] = j;
+    }
+    f->mask.push_back(m);
+    f->loff[l] = off;
+    f->seg.l[l].off = off;
+    f->seg.l[l].dA = L.dA;
+    f->seg.l[l].dB = L.dB;
+    off += (int64_t)L.dA * H + H + (int64_t)H * H + H + (int64_t)H * L.dB * NO + L.dB * NO;
+    w16 += (int64_t)H * KA + (int64_t)H * H + (int64_t)L.dB * NOP * H;
+    b3 += (int64_t)L.dB * NOP;
+    if (L.dB > dBmax) dBmax = L.dB;
+  }
+  f->count = off;
+  auto cleanup = [&](mf_status s) {
+    mf_flow_destroy(f);
+    return s;
+  };
+  const int64_t cap = cfg->max_batch;
+  f->cap = cap;
+  // caches: xa, h1, h2, o, lin per layer
+  size_t per_layer = sizeof(bf16) * (size_t)cap * (KA + 2 * H) + sizeof(float) * (size_t)cap * (dBmax * NOP + d);
+  const int64_t Zmax = (cap + SPLITK_CHUNK - 1) / SPLITK_CHUNK;
+  f->part_cap = (size_t)Zmax * (size_t)std::max<int64_t>((int64_t)H * dBmax * NOP, (int64_t)H * H);
+  if (hipMalloc(&f->d_p, sizeof(float) * off) != hipSuccess || hipMalloc(&f->d_g, sizeof(float) * off) != hipSuccess ||
+      hipMalloc(&f->d_m1, sizeof(float) * off) != hipSuccess || hipMalloc(&f->d_m2, sizeof(float) * off) != hipSuccess ||
+      hipMalloc(&f->d_w16, sizeof(bf16) * w16) != hipSuccess || hipMalloc(&f->d_b3p, sizeof(float) * b3) != hipSuccess ||
+      hipMalloc(&f->d_cachemem, per_layer * f->nl) != hipSuccess ||
+      hipMalloc(&f->d_y, sizeof(float) * d * cap) != hipSuccess ||
+      hipMalloc(&f->d_gy, sizeof(float) * d * cap) != hipSuccess ||
+      hipMalloc(&f->d_lq, sizeof(float) * cap) != hipSuccess ||
+      hipMalloc(&f->d_go, sizeof(bf16) * cap * dBmax * NOP) != hipSuccess ||
+      hipMalloc(&f->d_ga2, sizeof(bf16) * cap * H) != hipSuccess ||
+      hipMalloc(&f->d_ga1, sizeof(bf16) * cap * H) != hipSuccess ||
+      hipMalloc(&f->d_gx, sizeof(float) * cap * KA) != hipSuccess ||
+      hipMalloc(&f->d_part, sizeof(float) * f->part_cap) != hipSuccess ||
+      hipMalloc(&f->d_scal, sizeof(float) * 4) != hipSuccess) {
+    hipGetLastError();
+    return cleanup(set_error(MF_ENOMEM, "flow allocation failed"));
+  }
+  if (hipMemset(f->d_p, 0, sizeof(float) * off) != hipSuccess ||
+      hipMemset(f->d_g, 0, sizeof(float) * off) != hipSuccess ||
+      hipMemset(f->d_m1, 0, sizeof(float) * off) != hipSuccess ||
+      hipMemset(f->d_m2, 0, sizeof(float) * off) != hipSuccess ||
+      hipMemset(f->d_w16, 0, sizeof(bf16) * w16) != hipSuccess ||
+      hipMemset(f->d_b3p, 0, sizeof(float) * b3) != hipSuccess)
+    return cleanup(set_error(MF_EDEVICE, "flow initialisation failed"));
+  bf16* wp = f->d_w16;
+  float* bp = f->d_b3p;
+  char* cm = (char*)f->d_cachemem;
+  for (int l = 0; l < f->nl; ++l) {
+    LayerDev& L = f->L[l];
+    L.W1t = wp;
+    f->seg.l[l].W1t = wp;
+    wp += (int64_t)H * KA;
+    L.W2t = wp;
+    f->seg.l[l].W2t = wp;
+    wp += (int64_t)H * H;
+    L.W3t = wp;
+    f->seg.l[l].W3t = wp;
+    wp += (int64_t)L.dB * NOP * H;
+    L.b3p = bp;
+    f->seg.l[l].b3p = bp;
+    bp += (int64_t)L.dB * NOP;
+    L.b1 = f->d_p + f->loff[l] + (int64_t)L.dA * H;
+    L.b2 = L.b1 + H + (int64_t)H * H;
+    LayerCache& C = f->cache[l];
+    C.xa = (bf16*)cm;
+    cm += sizeof(bf16) * cap * KA;
+    C.h1 = (bf16*)cm;
+    cm += sizeof(bf16) * cap * H;
+    C.h2 = (bf16*)cm;
+    cm += sizeof(bf16) * cap * H;
+    C.o = (float*)cm;
+    cm += sizeof(float) * cap * dBmax * NOP;
+    C.lin = (float*)cm;
+    cm += sizeof(float) * cap * d;
+  }
+  *out = f;
+  return MF_OK;
+}
+
+void mf_flow_destroy(mf_flow* f) {
+  if (!f) return;
+  hipFree(f->d_p);
+  hipFree(f->d_g);
+  hipFree(f->d_m1);
+  hipFree(f->d_m2);
+  hipFree(f->d_w16);
+  hipFree(f->d_b3p);
+  hipFree(f->d_cachemem);
+  hipFree(f->d_y);
+  hipFree(f->d_gy);
+  hipFree(f->d_lq);
+  hipFree(f->d_go);
+  hipFree(f->d_ga2);
+  hipFree(f->d_ga1);
+  hipFree(f->d_gx);
+  hipFree(f->d_part);
+  hipFree(f->d_scal);
+  for (float* p : f->d_losses) hipFree(p);
+  delete f;
+}
+
+int64_t mf_flow_param_count(const mf_flow* f) { return f ? f->count : -1; }
+
+int mf_flow_ndim(const mf_flow* f) { return f ? f->d : 0; }
+
+mf_status mf_flow_masks(const mf_flow* f, uint8_t* out) {
+  clear_error();
+  if (!f || !out) return set_error(MF_EINVAL, "NULL argument");
+  for (int l = 0; l < f->nl; ++l) std::memcpy(out + (size_t)l * f->d, f->mask[l].data(), f->d);
+  return MF_OK;
+}
+
+mf_status mf_flow_set_params(mf_flow* f, const float* params, int64_t count) {
+  clear_error();
+  if (!f || !params) return set_error(MF_EINVAL, "NULL argument");
+  if (count != f->count) return set_error(MF_EINVAL, "expected %lld parameters, got %lld", (long long)f->count,
+                                          (long long)count);
+  if (hipMemcpy(f->d_p, params, sizeof(float) * count, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(f->d_m1, 0, sizeof(float) * count) != hipSuccess ||
+      hipMemset(f->d_m2, 0, sizeof(float) * count) != hipSuccess)
+    return set_error(MF_EDEVICE, "parameter upload failed");
+  f->step = 0;
+  mf_status st = refresh(f, nullptr, 0, 0.0f, 1.0f, 1.0f);
+  if (st != MF_OK) return st;
+  if (hipDeviceSynchronize() != hipSuccess) return set_error(MF_EDEVICE, "parameter refresh failed");
+  return MF_OK;
+}
+
+mf_status mf_flow_get_params(const mf_flow* f, float* params, int64_t count) {
+  clear_error();
+  if (!f || !params) return set_error(MF_EINVAL, "NULL argument");
+  if (count != f->count) return set_error(MF_EINVAL, "expected %lld parameters", (long long)f->count);
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(params, f->d_p, sizeof(float) * count, hipMemcpyDeviceToHost) != hipSuccess)
+    return set_error(MF_EDEVICE, "parameter download failed");
+  return MF_OK;
+}
+
+mf_status mf_flow_forward(mf_flow* f, const float* y, int64_t n, float* z, float* logq, void* stream) {
+  clear_error();
+  if (!f) return set_error(MF_EINVAL, "NULL flow");
+  if (n < 0) return set_error(MF_EINVAL, "negative event count");
+  if (n == 0) return MF_OK;
+  if (!y || !z || !logq) return set_error(MF_EINVAL, "NULL buffer");
+  hipStream_t s = (hipStream_t)stream;
+  mf_status st = copy_points(f, y, n, z, s);
+  if (st != MF_OK) return st;
+  run_layers(f, z, n, logq, false, false, s);
+  return launch_err("k_coupling");
+}
+
+mf_status mf_flow_inverse(mf_flow* f, const float* z, int64_t n, float* y, float* logq, void* stream) {
+  clear_error();
+  if (!f) return set_error(MF_EINVAL, "NULL flow");
+  if (n < 0) return set_error(MF_EINVAL, "negative event count");
+  if (n == 0) return MF_OK;
+  if (!y || !z || !logq) return set_error(MF_EINVAL, "NULL buffer");
+  hipStream_t s = (hipStream_t)stream;
+  mf_status st = copy_points(f, z, n, y, s);
+  if (st != MF_OK) return st;
+  run_layers(f, y, n, logq, true, false, s);
+  return launch_err("k_coupling");
+}
+
+mf_status mf_flow_loss_grad(mf_flow* f, const float* y, const float* w, int64_t n, float* grad, double* loss,
+                            void* stream) {
+  clear_error();
+  if (!f) return set_error(MF_EINVAL, "NULL flow");
+  if (n < 1 || n > f->cap) return set_error(MF_EINVAL, "n must be in 1..%lld", (long long)f->cap);
+  if (!y || !w) return set_error(MF_EINVAL, "NULL buffer");
+  hipStream_t s = (hipStream_t)stream;
+  mf_status st = loss_grad_impl(f, y, n, w, n, f->d_scal + 1, s);
+  if (st != MF_OK) return st;
+  if (grad && hipMemcpyAsync(grad, f->d_g, sizeof(float) * f->count, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return set_error(MF_EDEVICE, "gradient copy failed");
+  if (loss) {
+    float l = 0.0f;
+    if (hipMemcpyAsync(&l, f->d_scal + 1, sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return set_error(MF_EDEVICE, "loss copy failed");
+    *loss = l;
+  }
+  return MF_OK;
+}
+
+mf_status mf_flow_adam_step(mf_flow* f, double lr, void* stream) {
+  clear_error();
+  if (!f) return set_error(MF_EINVAL, "NULL flow");
+  if (!(lr >= 0.0)) return set_error(MF_EINVAL, "learning rate must be >= 0");
+  f->step += 1;
+  const float c1 = (float)(1.0 - std::pow(0.9, (double)f->step));
+  const float c2 = (float)(1.0 - std::pow(0.999, (double)f->step));
+  return refresh(f, (hipStream_t)stream, 1, (float)lr, c1, c2);
+}
+
+mf_status mf_flow_train(mf_flow* f, const float* y, const float* w, int64_t n, const mf_flow_train_opts* o,
+                        double* loss_per_epoch) {
+  clear_error();
+  if (!f || !o) return set_error(MF_EINVAL, "NULL argument");
+  if (!y || !w) return set_error(MF_EINVAL, "NULL buffer");
+  if (o->epochs < 1) return set_error(MF_EINVAL, "epochs must be >= 1");
+  if (o->batch < 1 || o->batch > f->cap) return set_error(MF_EINVAL, "batch must be in 1..%lld", (long long)f->cap);
+  if (n < 1) return set_error(MF_EINVAL, "no training points");
+  if (!(o->lr > 0.0) || !(o->lr_final >= 0.0)) return set_error(MF_EINVAL, "invalid learning rates");
+  hipStream_t s = (hipStream_t)o->stream;
+  const int64_t per_epoch = (n + o->batch - 1) / o->batch;
+  const int64_t total = per_epoch * o->epochs;
+  float* d_loss = nullptr;
+  if (hipMalloc(&d_loss, sizeof(float) * total) != hipSuccess) return set_error(MF_ENOMEM, "loss history");
+  struct Free {
+    float* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{d_loss};
+  int64_t t = 0;
+  for (int ep = 0; ep < o->epochs; ++ep) {
+    for (int64_t b = 0; b < per_epoch; ++b, ++t) {
+      const int64_t off = b * o->batch;
+      const int64_t nb = std::min<int64_t>(o->batch, n - off);
+      // batch slice of the [d][n] points: rows of nb values with pitch n
+      mf_status st = loss_grad_impl(f, y + off, n, w + off, nb, d_loss + t, s);
+      if (st != MF_OK) return st;
+      const double lr = o->lr_final + 0.5 * (o->lr - o->lr_final) * (1.0 + std::cos(M_PI * (double)t / (double)total));
+      st = mf_flow_adam_step(f, lr, s);
+      if (st != MF_OK) return st;
+    }
+  }
+  std::vector<float> hl((size_t)total);
+  if (hipMemcpyAsync(hl.data(), d_loss, sizeof(float) * total, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(MF_EDEVICE, "training failed");
+  if (loss_per_epoch)
+    for (int ep = 0; ep < o->epochs; ++ep) {
+      double a = 0.0;
+      for (int64_t b = 0; b < per_epoch; ++b) a += hl[(size_t)(ep * per_epoch + b)];
+      loss_per_epoch[ep] = a / (double)per_epoch;
+    }
+  return MF_OK;
+}
+
+}  // extern "C"

@@ -26,16 +26,18 @@
 #include <vector>
 
 #include "../../include/mf.h"
+#include "../../include/mf_flow.h"
 #include "launch.h"
 #include "pipeline.h"
+#include "status.h"
 
 using namespace mf;
 
+namespace mf {
 namespace {
-
 thread_local std::string g_err;
-
-mf_status fail(mf_status s, const char* fmt, ...) {
+}
+mf_status set_error(mf_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -44,6 +46,13 @@ mf_status fail(mf_status s, const char* fmt, ...) {
   g_err = buf;
   return s;
 }
+void clear_error() { mf::clear_error(); }
+const char* last_error() { return g_err.c_str(); }
+}  // namespace mf
+
+namespace {
+
+#define fail mf::set_error
 
 #define HIP_TRY(expr)                                                                  \
   do {                                                                                 \
@@ -144,6 +153,64 @@ __global__ void __launch_bounds__(256) k_stage_points(const double* __restrict__
     }
     jac[e] = J;
   }
+}
+
+// Points of a frozen-grid sample: y from Philox (yin == NULL, key word 1 =
+// purpose) or from the caller (FP32, e.g. drawn by the flow); x = map(y), the
+// Jacobian (divided by exp(logq) when logq is given: the weight of a point
+// drawn from the density exp(logq) in y), bins, and optionally y as FP32.
+__global__ void __launch_bounds__(256) k_sample_points(const double* __restrict__ edges_g, int d, int nb, uint64_t iter,
+                                                       int64_t N, uint64_t seed, uint64_t purpose,
+                                                       const float* __restrict__ yin, const float* __restrict__ logq,
+                                                       float* __restrict__ yout, double* __restrict__ x,
+                                                       double* __restrict__ jac, unsigned char* __restrict__ bins) {
+  extern __shared__ double edges[];
+  for (int i = threadIdx.x; i < d * (nb + 1); i += blockDim.x) edges[i] = edges_g[i];
+  __syncthreads();
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x, stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nchunk = b0 < N ? (N - b0 + stride - 1) / stride : 0;
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t e = b0 + it * stride + threadIdx.x;
+    if (e >= N) continue;
+    double y[MAXD];
+    if (yin) {
+      for (int j = 0; j < d; ++j) y[j] = (double)yin[(int64_t)j * N + e];
+    } else {
+      event_uniforms((uint64_t)e, iter, seed, purpose, d, y);
+    }
+    double J = 1.0;
+    for (int j = 0; j < d; ++j) {
+      int b;
+      x[(int64_t)j * N + e] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], b, J);
+      bins[(int64_t)j * N + e] = (unsigned char)b;
+      if (yout) yout[(int64_t)j * N + e] = (float)y[j];
+    }
+    if (logq) J *= exp(-(double)logq[e]);
+    jac[e] = J;
+  }
+}
+
+// FP32 Philox uniforms [d][N] (key (seed, purpose), counter (e, iter, call, 0)).
+__global__ void __launch_bounds__(256) k_uniform_f32(int d, uint64_t iter, int64_t N, uint64_t seed, uint64_t purpose,
+                                                     float* __restrict__ out) {
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x, stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nchunk = b0 < N ? (N - b0 + stride - 1) / stride : 0;
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t e = b0 + it * stride + threadIdx.x;
+    if (e >= N) continue;
+    double u[MAXD];
+    event_uniforms((uint64_t)e, iter, seed, purpose, d, u);
+    for (int j = 0; j < d; ++j) out[(int64_t)j * N + e] = (float)u[j];
+  }
+}
+
+// w[e] = f[e] * jac[e] (non-finite products give 0)
+__global__ void k_weight(const double* __restrict__ f, const double* __restrict__ jac, int64_t N,
+                         double* __restrict__ w) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  const double v = f[e] * jac[e];
+  w[e] = isfinite(v) ? v : 0.0;
 }
 
 // Accumulation kernel: weights w*J into the same per-block partials as the
@@ -381,6 +448,8 @@ struct mf_process {
   double* d_sjac = nullptr;        // [cap]
   double* d_sw = nullptr;          // [cap]
   unsigned char* d_sbins = nullptr;  // [ndim][cap]
+  float* d_sy = nullptr;           // [ndim][cap] flow points (FP32)
+  float* d_slq = nullptr;          // [cap] flow log-density
 };
 
 namespace {
@@ -429,16 +498,62 @@ mf_status check_stream_launch(const char* what) {
   return MF_OK;
 }
 
+// Grow the staging buffers of the handle to n events.
+mf_status ensure_stage(mf_process* p, int64_t n, hipStream_t s) {
+  if (p->stage_cap >= n) return MF_OK;
+  HIP_TRY(hipStreamSynchronize(s));
+  hipFree(p->d_sx);
+  hipFree(p->d_sjac);
+  hipFree(p->d_sw);
+  hipFree(p->d_sbins);
+  hipFree(p->d_sy);
+  hipFree(p->d_slq);
+  p->d_sx = p->d_sjac = p->d_sw = nullptr;
+  p->d_sbins = nullptr;
+  p->d_sy = p->d_slq = nullptr;
+  p->stage_cap = 0;
+  const size_t d = (size_t)p->ndim, m = (size_t)n;
+  if (hipMalloc(&p->d_sx, sizeof(double) * d * m) != hipSuccess || hipMalloc(&p->d_sjac, sizeof(double) * m) != hipSuccess ||
+      hipMalloc(&p->d_sw, sizeof(double) * m) != hipSuccess || hipMalloc(&p->d_sbins, d * m) != hipSuccess ||
+      hipMalloc(&p->d_sy, sizeof(float) * d * m) != hipSuccess || hipMalloc(&p->d_slq, sizeof(float) * m) != hipSuccess) {
+    hipGetLastError();
+    return fail(MF_ENOMEM, "staging buffers for %lld events", (long long)n);
+  }
+  p->stage_cap = n;
+  return MF_OK;
+}
+
+// Points and Jacobians of one frozen-grid sample into the staging buffers
+// (flow: Philox z -> flow inverse -> y -> map; else Philox y -> map).
+mf_status stage_sample(mf_process* p, mf_flow* flow, uint64_t iter, int64_t n, float* yout, hipStream_t s) {
+  const int d = p->ndim, nb = p->nb;
+  const int nblk = blocks_for(n);
+  const size_t lds = sizeof(double) * d * (nb + 1);
+  if (flow) {
+    hipLaunchKernelGGL(k_uniform_f32, dim3(nblk), dim3(256), 0, s, d, iter, n, p->cfg.seed, (uint64_t)1, p->d_sy);
+    mf_status st = mf_flow_inverse(flow, p->d_sy, n, p->d_sy, p->d_slq, s);
+    if (st != MF_OK) return st;
+    hipLaunchKernelGGL(k_sample_points, dim3(nblk), dim3(256), lds, s, p->d_edges, d, nb, iter, n, p->cfg.seed,
+                       (uint64_t)1, p->d_sy, p->d_slq, yout, p->d_sx, p->d_sjac, p->d_sbins);
+  } else {
+    hipLaunchKernelGGL(k_sample_points, dim3(nblk), dim3(256), lds, s, p->d_edges, d, nb, iter, n, p->cfg.seed,
+                       (uint64_t)0, (const float*)nullptr, (const float*)nullptr, yout, p->d_sx, p->d_sjac,
+                       p->d_sbins);
+  }
+  return check_stream_launch("k_sample_points");
+}
+
+
 }  // namespace
 
 extern "C" {
 
-const char* mf_last_error(void) { return g_err.c_str(); }
+const char* mf_last_error(void) { return mf::last_error(); }
 
 int mf_process_ndim(const mf_process* p) { return p ? p->ndim : 0; }
 
 mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
-  g_err.clear();
+  mf::clear_error();
   if (!cfg || !out) return fail(MF_EINVAL, "NULL argument");
   *out = nullptr;
   if (cfg->process < MF_GG_TTX || cfg->process > MF_GG_TTXGGG) return fail(MF_EINVAL, "unknown process %d", cfg->process);
@@ -526,11 +641,13 @@ void mf_process_destroy(mf_process* p) {
   hipFree(p->d_sjac);
   hipFree(p->d_sw);
   hipFree(p->d_sbins);
+  hipFree(p->d_sy);
+  hipFree(p->d_slq);
   delete p;
 }
 
 mf_status mf_integrand(mf_process* p, const double* u, int64_t n, double* w, void* stream) {
-  g_err.clear();
+  mf::clear_error();
   if (!p) return fail(MF_EINVAL, "NULL process");
   if (n < 0) return fail(MF_EINVAL, "negative event count");
   if (n == 0) return MF_OK;
@@ -542,7 +659,7 @@ mf_status mf_integrand(mf_process* p, const double* u, int64_t n, double* w, voi
 }
 
 mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w, double* dw, void* stream) {
-  g_err.clear();
+  mf::clear_error();
   if (!p) return fail(MF_EINVAL, "NULL process");
   if (n < 0) return fail(MF_EINVAL, "negative event count");
   if (n == 0) return MF_OK;
@@ -555,7 +672,7 @@ mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w
 }
 
 mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins, double alpha, void* stream) {
-  g_err.clear();
+  mf::clear_error();
   if (!edges || !hist) return fail(MF_EINVAL, "NULL buffer");
   if (ndim < 1 || ndim > MAXD) return fail(MF_EINVAL, "ndim must be in 1..%d", MAXD);
   if (nbins < 1 || nbins > MAX_BINS) return fail(MF_EINVAL, "nbins must be in 1..%d", MAX_BINS);
@@ -574,7 +691,7 @@ mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins
 }
 
 mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) {
-  g_err.clear();
+  mf::clear_error();
   if (!p || !o || !r) return fail(MF_EINVAL, "NULL argument");
   if (o->n_iter < 1 || o->n_iter > p->rec_cap) return fail(MF_EINVAL, "n_iter must be in 1..%d", p->rec_cap);
   if (o->n_events < 2) return fail(MF_EINVAL, "n_events must be >= 2");
@@ -587,22 +704,13 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
                                           hipMemcpyDeviceToDevice, s));
   const int nblk = blocks_for(o->n_events);
   const size_t lds = vegas_lds_bytes(d, nb);
-  if (!p->L.fused && p->stage_cap < o->n_events) {
-    HIP_TRY(hipStreamSynchronize(s));
-    hipFree(p->d_sx);
-    hipFree(p->d_sjac);
-    hipFree(p->d_sw);
-    hipFree(p->d_sbins);
-    p->d_sx = p->d_sjac = p->d_sw = nullptr;
-    p->d_sbins = nullptr;
-    p->stage_cap = 0;
-    const size_t n = (size_t)o->n_events;
-    if (hipMalloc(&p->d_sx, sizeof(double) * d * n) != hipSuccess || hipMalloc(&p->d_sjac, sizeof(double) * n) != hipSuccess ||
-        hipMalloc(&p->d_sw, sizeof(double) * n) != hipSuccess || hipMalloc(&p->d_sbins, (size_t)d * n) != hipSuccess) {
-      hipGetLastError();
-      return fail(MF_ENOMEM, "staged-iteration buffers for %lld events", (long long)o->n_events);
-    }
-    p->stage_cap = o->n_events;
+  if (o->flow) {
+    if (o->adapt) return fail(MF_EINVAL, "the grid is frozen under a flow proposal (adapt must be 0)");
+    if (mf_flow_ndim(o->flow) != d) return fail(MF_EINVAL, "flow dimension differs from the integrand's");
+  }
+  if (!p->L.fused || o->flow) {
+    mf_status st = ensure_stage(p, o->n_events, s);
+    if (st != MF_OK) return st;
   }
   std::vector<double> rec((size_t)REC * o->n_iter, 0.0);
   double time_to_target = -1.0;
@@ -619,7 +727,14 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   for (int it = 0; it < o->n_iter; ++it) {
     const uint64_t iter = o->iter_offset + (uint64_t)it;
     HIP_TRY(hipEventRecord(ev[2 * it], s));
-    if (p->L.fused) {
+    if (o->flow) {
+      const int64_t N = o->n_events;
+      mf_status sst = stage_sample(p, o->flow, iter, N, nullptr, s);
+      if (sst != MF_OK) return sst;
+      p->L.integrand(p->dc, p->d_sx, N, p->d_sw, nblk, s);
+      hipLaunchKernelGGL(k_stage_accumulate, dim3(nblk), dim3(256), 0, s, p->d_sw, p->d_sjac, p->d_sbins, d, nb, N,
+                         p->d_part, p->pstride);
+    } else if (p->L.fused) {
       p->L.vegas(p->dc, p->d_edges, iter, o->n_events, p->cfg.seed, p->d_part, p->pstride, nblk, lds, s);
     } else {
       const int64_t N = o->n_events;
@@ -703,8 +818,27 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   return MF_OK;
 }
 
+mf_status mf_weights(mf_process* p, mf_flow* flow, uint64_t iter, int64_t n, float* y_out, double* w_out,
+                     void* stream) {
+  mf::clear_error();
+  if (!p) return fail(MF_EINVAL, "NULL process");
+  if (n < 0) return fail(MF_EINVAL, "negative event count");
+  if (n == 0) return MF_OK;
+  if (!w_out) return fail(MF_EINVAL, "NULL weight buffer");
+  if (flow && mf_flow_ndim(flow) != p->ndim) return fail(MF_EINVAL, "flow dimension differs from the integrand's");
+  hipStream_t s = (hipStream_t)stream;
+  mf_status st = ensure_stage(p, n, s);
+  if (st != MF_OK) return st;
+  st = stage_sample(p, flow, iter, n, y_out, s);
+  if (st != MF_OK) return st;
+  const int nblk = blocks_for(n);
+  p->L.integrand(p->dc, p->d_sx, n, p->d_sw, nblk, s);
+  hipLaunchKernelGGL(k_weight, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->d_sw, p->d_sjac, n, w_out);
+  return check_stream_launch("k_weight");
+}
+
 mf_status mf_grad(mf_process* p, const mf_integrate_opts* o, double* out, double* err) {
-  g_err.clear();
+  mf::clear_error();
   if (!p || !o || !out || !err) return fail(MF_EINVAL, "NULL argument");
   if (o->n_events < 2) return fail(MF_EINVAL, "n_events must be >= 2");
   hipStream_t s = (hipStream_t)o->stream;

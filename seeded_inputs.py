@@ -101,3 +101,29 @@ def flow_params(shapes, seed: int = BASE_SEED, scale_out: float = 0.3):
             "W3": scale_out * rng.uniform(-a2, a2, (h, d_out)), "b3": scale_out * rng.uniform(-0.5, 0.5, d_out),
         })
     return out
+
+
+def flow_params_dyadic(shapes, seed: int = BASE_SEED):
+    """Coupling-flow parameters whose forward pass is exact in BF16 on inputs
+    on the grid (k + 1/2)/16: first-layer weights in {0, 1/4} and biases in
+    (0, 1/2] on a 1/128 grid (so every first hidden value is positive with at
+    most 8 significant bits), one weight of 1/2 or 1 per second-layer column
+    and zero second-layer biases, sparse output weights in {0, +-1/8, +-1/4}
+    and output biases on a 1/16 grid.  shapes as for flow_params."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for d_in, h, d_out in shapes:
+        W2 = np.zeros((h, h))
+        W2[rng.integers(0, h, h), np.arange(h)] = rng.choice([0.5, 1.0], h)
+        out.append({
+            "W1": rng.integers(0, 2, (d_in, h)) / 4.0, "b1": rng.integers(1, 65, h) / 128.0,
+            "W2": W2, "b2": np.zeros(h),
+            "W3": rng.integers(-2, 3, (h, d_out)) / 8.0 * (rng.random((h, d_out)) < 0.05),
+            "b3": rng.integers(-16, 17, d_out) / 16.0,
+        })
+    return out
+
+
+def grid_points(n: int, d: int, cells: int = 16, seed: int = BASE_SEED) -> np.ndarray:
+    """[n][d] points at the cell centres (k + 1/2)/cells."""
+    return (np.floor(unit_points(n, d, seed=seed) * cells) + 0.5) / cells

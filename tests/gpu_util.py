@@ -34,3 +34,20 @@ def assert_close(got, ref, rtol, floor_frac=1e-14):
     atol = floor_frac * float(np.max(np.abs(ref)))
     bad = np.abs(got - ref) > rtol * np.abs(ref) + atol
     assert not bad.any(), (int(bad.sum()), np.flatnonzero(bad)[:5], got[bad][:5], ref[bad][:5])
+
+
+def bf16_round(a) -> np.ndarray:
+    """Round to the nearest BF16 value (ties to even), returned as float64:
+    parameters given in this form are exact in the kernels' BF16 copies."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def cosine_rel_l2(got, ref):
+    """(cosine similarity, |got - ref| / |ref|) of two flattened arrays."""
+    g = np.asarray(got, dtype=np.float64).ravel()
+    r = np.asarray(ref, dtype=np.float64).ravel()
+    cos = float(g @ r / (np.linalg.norm(g) * np.linalg.norm(r)))
+    return cos, float(np.linalg.norm(g - r) / np.linalg.norm(r))

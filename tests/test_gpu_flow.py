@@ -1,0 +1,302 @@
+"""The coupling flow on the GPU (BF16 matrix-core layers, FP32 transform)
+against the FP64 numpy oracle of the same flow, and the flow as a proposal.
+
+Tolerance for BF16 work: cosine >= 0.999 and relative L2 <= 1e-2 over the
+compared vectors (the layers round activations to BF16, a relative error of
+2^-9 per value); the weights handed to both sides are BF16-exact, so no
+parameter rounding enters the comparison.  Where the GPU inverts its own
+forward map it evaluates the same BF16 layers on the same inputs, so the
+round trip is held to FP32 accuracy.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import seeded_inputs as si
+from gpu_util import bf16_round, cosine_rel_l2
+from oracle import flow as oflow
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2105_10529_amd as mf  # noqa: E402
+
+K = 32
+
+
+def _flow_and_params(d, scale, seed, max_batch=4096, layers=6):
+    f = mf.Flow(d, n_layers=layers, max_batch=max_batch)
+    mk = oflow.masks(d, layers)
+    shapes = [(int((~m).sum()), 256, int(m.sum()) * (2 * K + 1)) for m in mk]
+    params = si.flow_params(shapes, seed=seed, scale_out=scale)
+    for p in params:
+        for k in ("W1", "W2", "W3"):
+            p[k] = bf16_round(p[k])
+        for k in ("b1", "b2", "b3"):
+            p[k] = np.asarray(p[k], dtype=np.float32).astype(np.float64)
+    f.set_params(mf.Flow.flatten(params))
+    return f, mk, params
+
+
+def _dev32(x):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.float32).T)).to("cuda")
+
+
+def test_masks_and_layout_match_oracle():
+    for d in (2, 4, 7, 10, 13):
+        f = mf.Flow(d, max_batch=64)
+        assert np.array_equal(f.masks(), np.array(oflow.masks(d))), d
+        mk = oflow.masks(d)
+        n = sum(int((~m).sum()) * 256 + 256 + 256 * 256 + 256 + 256 * int(m.sum()) * 65 + int(m.sum()) * 65
+                for m in mk)
+        assert f.param_count == n
+
+
+def test_zero_parameters_give_the_identity():
+    f = mf.Flow(7, max_batch=64)
+    y = si.unit_points(1000, 7, seed=11)
+    z, lq = f.forward(_dev32(y))
+    assert np.max(np.abs(z.cpu().numpy().T - y.astype(np.float32))) < 2e-7
+    assert np.all(lq.cpu().numpy() == 0.0)
+
+
+@pytest.mark.parametrize("d,n", [(10, 3001), (4, 3000), (13, 700)])
+def test_forward_and_inverse_match_oracle(d, n):
+    f, mk, params = _flow_and_params(d, 0.5, seed=20 + d)
+    y = np.clip(si.unit_points(n, d, seed=21), 1e-6, 1 - 1e-6)
+    z_ref, lq_ref, _ = oflow.forward(params, mk, y, K)
+    z, lq = f.forward(_dev32(y))
+    z = z.cpu().numpy().T.astype(np.float64)
+    lq = lq.cpu().numpy().astype(np.float64)
+    assert np.std(lq_ref) > 0.3  # the map is far from the identity
+    cos, rl2 = cosine_rel_l2(z - y, z_ref - y)
+    assert cos >= 0.999 and rl2 <= 1e-2, (cos, rl2)
+    cos, rl2 = cosine_rel_l2(lq, lq_ref)
+    assert cos >= 0.999 and rl2 <= 1e-2, (cos, rl2)
+    assert np.max(np.abs(z - z_ref)) < 5e-3
+    # sampling direction from the oracle's z, against the oracle's inverse
+    y_ref, lq_inv_ref = oflow.inverse(params, mk, z_ref, K)
+    yi, lqi = f.inverse(_dev32(z_ref))
+    yi = yi.cpu().numpy().T.astype(np.float64)
+    cos, rl2 = cosine_rel_l2(yi - z_ref, y_ref - z_ref)
+    assert cos >= 0.999 and rl2 <= 1e-2, (cos, rl2)
+    # the density reported with a sampled point is the flow's density there:
+    # the oracle's log q at the GPU's point (comparing at the oracle's own
+    # point would add the slope of log q times the point's BF16 shift)
+    _, lq_at_yi, _ = oflow.forward(params, mk, np.clip(yi, 0.0, 1.0), K)
+    cos, rl2 = cosine_rel_l2(lqi.cpu().numpy(), lq_at_yi)
+    assert cos >= 0.999 and rl2 <= 1e-2, (cos, rl2)
+    assert np.corrcoef(lqi.cpu().numpy(), lq_inv_ref)[0, 1] > 0.999
+    # events are independent of the tile they share: a ragged prefix gives
+    # the same bits
+    for m in (1, 63, 65):
+        zm, lqm = f.forward(_dev32(y[:m]))
+        assert np.array_equal(zm.cpu().numpy().T, z[:m].astype(np.float32))
+        assert np.array_equal(lqm.cpu().numpy(), lq[:m].astype(np.float32))
+    # GPU round trip: inverse(forward(y)) = y with the same BF16 layers, to
+    # FP32 accuracy.  One FP32 rounding of a CDF value (6e-8) moves the
+    # inverse by 6e-8 / pdf, and a moved kept coordinate changes the next
+    # layers' inputs; an FP32 replay of this arithmetic on the CPU gives, for
+    # these parameters, median |dy| 1e-8, 99th percentile 2e-7, maximum 3e-4,
+    # and |d log q| median 2e-6, 99th percentile 7e-5, maximum 1e-2.
+    yr, lqr = f.inverse(_dev32(z))
+    dy = np.abs(yr.cpu().numpy().T - y)
+    dl = np.abs(lqr.cpu().numpy() - lq)
+    assert np.median(dy) < 1e-7 and np.quantile(dy, 0.99) < 2e-6 and dy.max() < 2e-3, np.quantile(dy, [0.5, 0.99, 1])
+    assert np.median(dl) < 2e-5 and np.quantile(dl, 0.99) < 1e-3 and dl.max() < 5e-2, np.quantile(dl, [0.5, 0.99, 1])
+
+
+def _set(f, params):
+    f.set_params(mf.Flow.flatten(params))
+    return params
+
+
+@pytest.mark.parametrize("d,n", [(10, 2000), (7, 1100)])
+def test_loss_gradient_matches_oracle_exact_forward(d, n):
+    """One layer with BF16-exact forward arithmetic (dyadic parameters and
+    inputs): the loss agrees to FP32 rounding and the gradient differs from
+    the FP64 one only by the BF16 rounding of the backward pass itself."""
+    f = mf.Flow(d, n_layers=1, max_batch=4096)
+    mk = oflow.masks(d, 1)
+    shapes = [(int((~m).sum()), 256, int(m.sum()) * (2 * K + 1)) for m in mk]
+    params = _set(f, si.flow_params_dyadic(shapes, seed=70 + d))
+    y = si.grid_points(n, d, seed=71)
+    w = np.exp(-np.sum((y - 0.3) ** 2, axis=1) / (0.05 * d))
+    _, lq_ref, caches = oflow.forward(params, mk, y, K)
+    g_ref = oflow.backward(params, mk, caches, w, K)
+    z, lq = f.forward(_dev32(y))
+    assert np.max(np.abs(lq.cpu().numpy() - lq_ref)) < 1e-4
+    L, g = f.loss_grad(_dev32(y), torch.from_numpy(w.astype(np.float32)).cuda())
+    L_ref = oflow.loss(lq_ref, w)
+    assert abs(L - L_ref) <= 1e-5 * max(1.0, abs(L_ref)), (L, L_ref)
+    g_layers = f.unflatten(g.cpu().numpy())
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        cos, rl2 = cosine_rel_l2(g_layers[0][name], g_ref[0][name])
+        assert cos >= 0.9999 and rl2 <= 5e-3, (name, cos, rl2)
+
+
+@pytest.mark.parametrize("d,n", [(10, 2000), (7, 1100)])
+def test_loss_gradient_matches_oracle_six_layers(d, n):
+    """Six layers with random weights.  A BF16 forward moves points across PQ
+    bin edges, where the derivative jumps, and changes every later layer's
+    inputs; an FP64 replay of exactly that rounding, with an exact backward,
+    differs from the FP64 gradient for these inputs by up to cosine 0.9988 /
+    relative L2 0.05 per block, which sets the bound.  A wrong term in the
+    propagation between layers gives cosines far below it."""
+    f, mk, params = _flow_and_params(d, 0.1, seed=30 + d)
+    y = si.unit_points(n, d, seed=31)
+    w = np.exp(-np.sum((y - 0.3) ** 2, axis=1) / (0.05 * d)) * np.random.default_rng(32).exponential(size=n)
+    _, lq_ref, caches = oflow.forward(params, mk, y, K)
+    L_ref = oflow.loss(lq_ref, w)
+    g_ref = oflow.backward(params, mk, caches, w, K)
+    L, g = f.loss_grad(_dev32(y), torch.from_numpy(w.astype(np.float32)).cuda())
+    assert abs(L - L_ref) <= 2e-3 * max(1.0, abs(L_ref)), (L, L_ref)
+    g_layers = f.unflatten(g.cpu().numpy())
+    bad = []
+    for li in range(len(mk)):
+        for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            cos, rl2 = cosine_rel_l2(g_layers[li][name], g_ref[li][name])
+            if not (cos >= 0.995 and rl2 <= 0.1):
+                bad.append((li, name, cos, rl2))
+    assert not bad, bad
+    cos, rl2 = cosine_rel_l2(g.cpu().numpy(), mf.Flow.flatten(g_ref))
+    assert cos >= 0.999, (cos, rl2)
+
+
+def test_training_trajectory_matches_oracle():
+    """Full-batch Adam from the identity flow on a peaked target: the GPU's
+    BF16 training follows the FP64 oracle's loss curve (a step size at which
+    the oracle's descent is smooth: where Adam oscillates, rounding-level
+    differences between two runs grow step by step)."""
+    d, n, steps, lr = 4, 2048, 20, 5e-4
+    f = mf.Flow(d, max_batch=n)
+    mk = oflow.masks(d)
+    shapes = [(int((~m).sum()), 256, int(m.sum()) * (2 * K + 1)) for m in mk]
+    params = si.flow_params(shapes, seed=80, scale_out=0.0)
+    for p in params:
+        for k in ("W1", "W2", "W3"):
+            p[k] = bf16_round(p[k])
+        for k in ("b1", "b2", "b3"):
+            p[k] = np.asarray(p[k], dtype=np.float32).astype(np.float64)
+    _set(f, params)
+    y = si.unit_points(n, d, seed=81)
+    w = np.exp(-np.sum((y - 0.3) ** 2, axis=1) / 0.05)
+    yd, wd = _dev32(y), torch.from_numpy(w.astype(np.float32)).cuda()
+    state = [{("m" + k): np.zeros_like(v) for k, v in p.items()} | {("v" + k): np.zeros_like(v) for k, v in p.items()}
+             for p in params]
+    got, ref = [], []
+    for t in range(1, steps + 1):
+        L, _ = f.loss_grad(yd, wd)
+        f.adam_step(lr)
+        got.append(L)
+        _, lq, c = oflow.forward(params, mk, y, K)
+        ref.append(oflow.loss(lq, w))
+        oflow.adam_step(params, oflow.backward(params, mk, c, w, K), state, lr, t)
+    got, ref = np.array(got), np.array(ref)
+    assert ref[-1] < -2.0
+    # step by step while the descent is smooth, then the level reached
+    assert np.max(np.abs(got[:12] - ref[:12])) <= 0.01 * np.max(np.abs(ref[:12])), np.c_[got, ref]
+    assert abs(np.mean(got[-5:]) - np.mean(ref[-5:])) <= 0.03 * abs(np.mean(ref[-5:])), np.c_[got, ref]
+
+
+def test_adam_step_matches_oracle():
+    f, mk, params = _flow_and_params(7, 0.5, seed=40)
+    y = si.unit_points(512, 7, seed=41)
+    w = np.random.default_rng(42).exponential(size=512)
+    p0 = f.get_params().astype(np.float64)
+    _, g = f.loss_grad(_dev32(y), torch.from_numpy(w.astype(np.float32)).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    f.adam_step(1e-3)
+    g2 = f.unflatten(f.loss_grad(_dev32(y), torch.from_numpy(w.astype(np.float32)).cuda())[1].cpu().numpy())
+    f.adam_step(5e-4)
+    got = f.get_params().astype(np.float64)
+    ref = f.unflatten(p0)
+    state = [{("m" + k): np.zeros_like(v) for k, v in p.items()} | {("v" + k): np.zeros_like(v) for k, v in p.items()}
+             for p in ref]
+    oflow.adam_step(ref, f.unflatten(g), state, 1e-3, 1)
+    oflow.adam_step(ref, g2, state, 5e-4, 2)
+    exp = mf.Flow.flatten(ref)
+    assert np.max(np.abs(got - exp)) <= 1e-6 + 1e-5 * np.max(np.abs(exp))
+
+
+def test_weight_stats_are_exact():
+    rng = np.random.default_rng(50)
+    for n in (1, 7, 1000, 300001):
+        w = rng.lognormal(0.0, 2.0, n) * (rng.random(n) > 0.3)
+        w[rng.random(n) < 0.05] *= -1e-6  # small negative weights, as near x = 1
+        t = torch.from_numpy(w).cuda()
+        for q in (0.5, 0.999, 1.0):
+            s = mf.weight_stats(t, q)
+            assert s["max"] == w.max() and s["nonzero"] == np.count_nonzero(w)
+            assert s["quantile"] == np.quantile(w, q, method="inverted_cdf"), (n, q)
+            assert abs(s["mean"] - w.mean()) <= 1e-13 * max(abs(w.mean()), 1e-300)
+    w = -rng.lognormal(0.0, 1.0, 1001)
+    s = mf.weight_stats(torch.from_numpy(w).cuda(), 0.25)
+    assert s["quantile"] == np.quantile(w, 0.25, method="inverted_cdf") and s["max"] == w.max()
+    with pytest.raises(mf.MFError):
+        mf.weight_stats(torch.tensor([1.0, float("nan")], dtype=torch.float64, device="cuda"))
+
+
+def test_invalid_flow_arguments():
+    with pytest.raises(mf.MFError):
+        mf.Flow(1)
+    with pytest.raises(mf.MFError):
+        mf.Flow(17)
+    f = mf.Flow(4, max_batch=100)
+    y = torch.rand(4, 101, device="cuda")
+    with pytest.raises(mf.MFError):
+        f.loss_grad(y, torch.ones(101, device="cuda"))
+    with pytest.raises(mf.MFError):
+        f.set_params(np.zeros(f.param_count - 1, dtype=np.float32))
+    p = mf.Process(mf.Config(process="gg>ttxg"))
+    with pytest.raises(mf.MFError):
+        p.integrate(1, 1000, adapt=True, flow=mf.Flow(7, max_batch=64))
+    with pytest.raises(mf.MFError):
+        p.integrate(1, 1000, adapt=False, flow=f)
+
+
+def test_flow_sample_weights_match_oracle_integrand():
+    """w = f(x(y)) J(y) / q(y) for the flow's own points, against the oracle
+    integrand at the same mapped points (q from the flow, FP32)."""
+    p = mf.Process(mf.Config(process="gg>ttxg"))
+    p.integrate(3, 20000, adapt=True)
+    edges = torch.empty((7, 51), dtype=torch.float64, device="cuda")
+    p.integrate(1, 2, adapt=False, edges_out=edges, iter_offset=50)
+    f, mk, params = _flow_and_params(7, 0.3, seed=60)
+    w, y = p.weights(7, 1500, flow=f, want_y=True)
+    y = y.cpu().numpy().T.astype(np.float64)
+    # the flow's density at those points, from its forward direction
+    _, lq = f.forward(_dev32(y))
+    lq = lq.cpu().numpy().astype(np.float64)
+    E = edges.cpu().numpy()
+    xs, js = [], []
+    for yy in y:
+        x, jac, _ = oracle.vegas_map(E, yy)
+        xs.append(x)
+        js.append(jac)
+    ref = oracle.Oracle(oracle.Config(n_g=1)).integrand(np.array(xs)) * np.array(js) * np.exp(-lq)
+    got = w.cpu().numpy()
+    nz = ref != 0
+    assert nz.sum() > 500 and np.array_equal(got != 0, nz)
+    assert np.max(np.abs(got[nz] / ref[nz] - 1.0)) < 1e-3
+
+
+def test_trained_flow_is_a_consistent_proposal_on_gg_ttg():
+    """VEGAS adapts, the grid is frozen, the flow is trained on the method's own
+    weights and then used as the proposal: the integral agrees with VEGAS,
+    the loss falls, and the flow learns to avoid the region the cuts remove."""
+    p = mf.Process(mf.Config(process="gg>ttxg"))
+    p.integrate(5, 200000, adapt=True)
+    n_train = 400000
+    w, y = p.weights(1000, n_train, want_y=True)
+    f = mf.Flow(7, max_batch=16384)
+    losses = f.train(y, w.float(), epochs=8, batch=16384, lr=1e-3, lr_final=1e-5)
+    assert losses[-1] < losses[0] - 0.02, losses
+    n = 1_000_000
+    rv = p.integrate(2, n, adapt=False, iter_offset=2000)
+    rf = p.integrate(2, n, adapt=False, iter_offset=2000, flow=f)
+    assert abs(rf.integral - rv.integral) < 4.0 * np.hypot(rf.error, rv.error), (rf, rv)
+    assert rf.n_nonzero > 1.05 * rv.n_nonzero, (rf.n_nonzero, rv.n_nonzero)

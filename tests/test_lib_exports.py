@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every symbol include/mf.h declares (CPU only)."""
+"""The C-ABI library loads and exports every symbol the headers in include/ declare (CPU only)."""
 import os
 import re
 import subprocess
@@ -9,8 +9,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "mf.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:mf_status|void|int|const char\*)\s+(mf_\w+)\s*\(", text, re.M)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"^\s*(?:mf_status|void|int|int64_t|const char\*)\s+(mf_\w+)\s*\(", text, re.M))
+    return sorted(names)
 
 
 def test_header_declares_the_four_calls():
