@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -60,6 +62,72 @@ def cpu_baseline(seed: int, target_seconds: float = 12.0) -> dict:
                       f"gg->ttg FP64, OpenMP over events, {dt:.1f} s"}
 
 
+def _eff(stats: dict) -> dict:
+    return {"mean_over_max": stats["mean"] / stats["max"], "mean_over_q999": stats["mean"] / stats["quantile"]}
+
+
+def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_000) -> dict:
+    """g g -> t t~ g g (Delta R > 0.4): wall time from process creation to a
+    relative error of 1e-3, for plain VEGAS in FP64, plain VEGAS with FP32
+    amplitudes, and FP32 amplitudes with the learned proposal (VEGAS warm-up
+    5 x 1e6, on-policy variance training of the flow, then the flow mixed
+    with 20% uniform points on the frozen grid); plus the per-event relative
+    variance and the unweighting efficiency of each proposal on a fresh
+    sample of eval_events with the final grid."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+
+    def cfg(prec):
+        return mf.Config(process="gg>ttxgg", precision=prec, dr_min=0.4)
+
+    res = {}
+    for prec in ("fp64", "fp32"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = mf.Process(cfg(prec))
+        r = p.integrate(100, n_iter_events, target_rel_err=1e-3, adapt=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        w, _ = p.weights(1 << 30, eval_events)
+        st = mf.weight_stats(w)
+        del w
+        res[f"vegas_{prec}"] = {"time_to_1e-3_s": t, "iterations": r.n_iter_done, "events": r.n_events_total,
+                                "integral_pb": r.integral, "error_pb": r.error,
+                                "relative_variance_per_event": st["relvar"],
+                                "unweighting": _eff(st)}
+        del p
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = mf.Process(cfg("fp32"))
+    p.integrate(5, 1_000_000, adapt=True)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    f = mf.Flow(p.ndim, max_batch=65536)
+    steps, mix = 300, 0.2
+    rel = p.train_flow_online(f, steps, batch=65536, lr=5e-3, loss="variance", flow_mix=mix)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0 - t_warm
+    r = p.integrate(100, n_iter_events, target_rel_err=1e-3, adapt=False, flow=f, flow_mix=mix, iter_offset=1 << 24)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    wf, _ = p.weights(1 << 30, eval_events, flow=f, flow_mix=mix)
+    sf = mf.weight_stats(wf)
+    del wf
+    wv, _ = p.weights(1 << 30, eval_events)
+    sv = mf.weight_stats(wv)
+    del wv
+    res["fp32_flow"] = {"time_to_1e-3_s": t, "time_excluding_training_s": t - t_train, "warmup_s": t_warm,
+                        "training_s": t_train, "training_steps": steps, "training_batch": 65536,
+                        "iterations": r.n_iter_done, "events": r.n_events_total, "integral_pb": r.integral,
+                        "error_pb": r.error, "events_per_s": r.n_events_total / r.seconds,
+                        "batch_relative_variance_first_last": [float(np.mean(rel[:5])), float(np.mean(rel[-10:]))],
+                        "relative_variance_per_event": sf["relvar"],
+                        "relative_variance_per_event_vegas_same_grid": sv["relvar"],
+                        "unweighting": _eff(sf), "unweighting_vegas_same_grid": _eff(sv)}
+    return res
+
+
 def secondary(seed_events: int) -> dict:
     """Bounded extra measurements on the same GPU (reported beside the main line).
 
@@ -69,7 +137,6 @@ def secondary(seed_events: int) -> dict:
     * d sigma/d m_t on g g -> t t~ g at m_t = 171, 173, 175 GeV from 1e8
       pathwise-derivative events each, with a grid frozen from a VEGAS warm-up.
     """
-    import numpy as np
     import torch
 
     import paper_2105_10529_amd as mf
@@ -90,6 +157,7 @@ def secondary(seed_events: int) -> dict:
             "time_to_1e-3_s": tt.time_to_target, "iterations_to_1e-3": tt.n_iter_done,
             "events_to_1e-3": tt.n_events_total, "integral_at_1e-3_pb": tt.integral, "error_at_1e-3_pb": tt.error,
         }
+    out["ttgg_flow_vs_vegas"] = flow_comparison()
     grads = {}
     for mt in (171.0, 173.0, 175.0):
         p = mf.Process(mf.Config(process="gg>ttxg", m_t=mt))

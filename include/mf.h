@@ -143,8 +143,9 @@ typedef struct {
   void* stream;                   /* hipStream_t or NULL */
   struct mf_flow* flow;           /* NULL: VEGAS proposal.  Else the flow is the
                                      proposal on the frozen grid (adapt must be
-                                     0): z from Philox with key (seed, 1),
-                                     y = flow inverse of z, w = f J / q(y) */
+                                     0), see mf_weights */
+  double flow_mix;                /* with a flow: the fraction a of uniform
+                                     points in the proposal, in [0,1) */
 } mf_integrate_opts;
 
 typedef struct {
@@ -177,20 +178,28 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r);
  *  flow == NULL: y from Philox with counter (e, iter, call, 0) and key
  *                (cfg.seed, 0) -- the points of VEGAS iteration `iter` --
  *                and w = f(x(y)) J(y);
- *  flow != NULL: z from Philox with key (cfg.seed, 1), y = flow inverse of z
- *                (mf_flow.h), w = f(x(y)) J(y) / q(y).
+ *  flow != NULL: Philox numbers u with key (cfg.seed, 1); with a = flow_mix,
+ *                events e < floor(a n) take y = u, the others y = flow
+ *                inverse of u (mf_flow.h); w = f(x(y)) J(y) / (a + (1-a) q(y)),
+ *                the weight of the mixture of the uniform density and the
+ *                flow (unbiased for the fixed split: the two parts sample
+ *                their own densities in the proportions a : 1-a).
  *   y_out: device [ndim][n] FP32 copy of y, or NULL
  *   w_out: device [n] FP64 weights (pb)
  * This is how training samples for the flow are drawn and how the weight
  * distributions of the two proposals are compared.  The flow's dimension
- * must equal the process's.  Staging buffers of the handle grow to n. */
-mf_status mf_weights(mf_process* p, struct mf_flow* flow, uint64_t iter, int64_t n, float* y_out, double* w_out,
-                     void* stream);
+ * must equal the process's; flow_mix in [0,1).  Staging buffers of the
+ * handle grow to n. */
+mf_status mf_weights(mf_process* p, struct mf_flow* flow, double flow_mix, uint64_t iter, int64_t n, float* y_out,
+                     double* w_out, void* stream);
 
 /* Statistics of weights (device [n] FP64, n >= 1; they may be negative
  * where the interpolated PDFs dip below zero near x = 1):
- *   out: host [4] = mean, maximum, the q-quantile (the smallest weight with
- *        at least ceil(q n) weights <= it), number of non-zero weights.
+ *   out: host [5] = mean, maximum, the q-quantile (the smallest weight with
+ *        at least ceil(q n) weights <= it), number of non-zero weights, and
+ *        the relative variance per event mean(w^2)/mean(w)^2 - 1 (0 if the
+ *        mean is 0), so the Monte Carlo error of the mean of N such weights
+ *        is |mean| sqrt(that / N).
  * The quantile is exact (radix selection on order-preserving bit keys).  The
  * unweighting efficiency of a sample is mean / max (or mean / quantile).
  * MF_EINVAL for a NaN weight or q outside (0,1].  Synchronous. */

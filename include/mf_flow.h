@@ -55,6 +55,14 @@ extern "C" {
 
 typedef struct mf_flow mf_flow;
 
+typedef enum {
+  MF_FLOW_LOSS_KL = 0,       /* L = - sum w log q / sum w (forward KL) */
+  MF_FLOW_LOSS_VARIANCE = 1  /* gradient of log sum w^2 / q: the KL gradient with
+                                per-point weights w^2/q held fixed; the reported
+                                value is the relative variance per event of
+                                sampling q, n sum w^2/q / (sum w)^2 - 1 */
+} mf_flow_loss;
+
 typedef struct {
   int32_t ndim;       /* 2..16 */
   int32_t n_layers;   /* 1..8 */
@@ -101,16 +109,18 @@ mf_status mf_flow_forward(mf_flow* f, const float* y, int64_t n, float* z, float
  * point), same buffer conventions as mf_flow_forward. */
 mf_status mf_flow_inverse(mf_flow* f, const float* z, int64_t n, float* y, float* logq, void* stream);
 
-/* Loss L = - sum_i w_i log q(y_i) / sum_i w_i of one batch and its gradient
- * with respect to every parameter (the forward pass keeps the activations of
- * the batch, the backward pass runs through the PQ transforms and the
- * layers).  The gradient is kept in the handle for mf_flow_adam_step.
- *   y:    device [ndim][n] FP32;  w: device [n] FP32, >= 0 with a positive sum
+/* Loss of one batch of points y (uniform in the flow's space) with weights
+ * w (mf_flow_loss) and its gradient with respect to every parameter (the
+ * forward pass keeps the activations of the batch, the backward pass runs
+ * through the PQ transforms and the layers).  The gradient is kept in the
+ * handle for mf_flow_adam_step.
+ *   y:    device [ndim][n] FP32;  w: device [n] FP32 with a positive sum
  *   grad: device [param_count] FP32 copy of the gradient, or NULL
- *   loss: host, receives L (the call then synchronises `stream`), or NULL
- * 1 <= n <= max_batch, else MF_EINVAL. */
-mf_status mf_flow_loss_grad(mf_flow* f, const float* y, const float* w, int64_t n, float* grad, double* loss,
-                            void* stream);
+ *   loss: host, receives the loss value (the call then synchronises
+ *         `stream`), or NULL
+ * 1 <= n <= max_batch and a known loss kind, else MF_EINVAL. */
+mf_status mf_flow_loss_grad(mf_flow* f, const float* y, const float* w, int64_t n, int32_t loss_kind, float* grad,
+                            double* loss, void* stream);
 
 /* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) of the
  * FP32 masters with the gradient of the last mf_flow_loss_grad, followed by
@@ -124,13 +134,36 @@ typedef struct {
   double lr;          /* initial learning rate, > 0 */
   double lr_final;    /* learning rate after the last step (cosine decay) */
   void* stream;
+  int32_t loss;       /* mf_flow_loss */
 } mf_flow_train_opts;
 
 /* Train on n weighted points (mf_flow_loss_grad + mf_flow_adam_step per
- * batch, batches in order).  loss_per_epoch: host [epochs] mean batch loss,
- * or NULL.  Blocks until done. */
+ * batch, batches in order).  loss_per_epoch: host [epochs] mean batch loss
+ * value, or NULL.  Blocks until done. */
 mf_status mf_flow_train(mf_flow* f, const float* y, const float* w, int64_t n, const mf_flow_train_opts* o,
                         double* loss_per_epoch);
+
+typedef struct {
+  int32_t steps;         /* training steps, >= 1 */
+  int64_t batch;         /* points per step, 2..max_batch of the flow */
+  double lr;             /* initial learning rate, > 0 */
+  double lr_final;       /* learning rate after the last step (cosine decay) */
+  int32_t loss;          /* mf_flow_loss */
+  double flow_mix;       /* fraction a of uniform points in the sampling mixture, [0,1) */
+  uint64_t iter_offset;  /* Philox iteration word of the first step's batch */
+  void* stream;
+} mf_flow_online_opts;
+
+/* On-policy training on the integrand itself: each step draws a batch from
+ * the mixture q_m = a + (1 - a) q of the current flow (key word 1, iteration
+ * word iter_offset + step, as mf_weights), evaluates the integrand on the
+ * frozen grid of the process, and takes a step on the gradient of
+ * int p^2 / q_m (variance: per-point weights r^2 q/q_m with r = f J / q_m)
+ * or of the forward KL (weights r q/q_m), followed by Adam.
+ *   loss_per_step: host [steps], the relative variance per event of each
+ *   batch's weights r (n sum r^2 / (sum r)^2 - 1), or NULL.
+ * Blocks until done. */
+mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_online_opts* o, double* loss_per_step);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,12 @@ Rousselle, Gross, Novak, "Neural Importance Sampling" (ACM TOG 2019):
   C(y) = sum_{k<b} W_k (V_k + V_k+1)/2 + W_b (alpha V_b + alpha^2 (V_b+1 - V_b)/2);
 * log q(y) = sum over layers and transformed coordinates of log pdf;
 * training minimises the forward KL divergence on weighted samples,
-  L = - sum_i w_i log q(y_i) / sum_i w_i.
+  L = - sum_i w_i log q(y_i) / sum_i w_i, or the variance of the weights
+  under q: for points uniform in y, V = sum_i w_i^2 / q(y_i) estimates
+  n int p^2/q, and the gradient of log V is the KL gradient with the
+  per-point weights w_i^2 / q(y_i) (held fixed), normalised by their sum;
+* as a proposal the flow can be mixed with the uniform density,
+  q_mix = a + (1 - a) q, which bounds the weights by w / a.
 
 Everything here is FP64 with the analytic reverse-mode gradient written out
 step by step (pinned by central differences in the tests).
@@ -152,6 +157,28 @@ def inverse(params, mk, z, K=32):
 
 def loss(logq, w):
     return -np.sum(w * logq) / np.sum(w)
+
+
+def variance_weights(logq, w):
+    """Per-point weights w^2 / q whose weighted log-likelihood gradient is
+    the gradient of log sum_i w_i^2 / q(y_i)."""
+    return w * w * np.exp(-logq)
+
+
+def log_variance_loss(logq, w):
+    """log sum_i w_i^2 / q(y_i)."""
+    return float(np.log(np.sum(variance_weights(logq, w))))
+
+
+def relative_variance(logq, w):
+    """n sum_i w_i^2/q_i / (sum_i w_i)^2 - 1: the relative variance per event
+    of the estimator that samples q, estimated from points uniform in y."""
+    return float(w.size * np.sum(variance_weights(logq, w)) / np.sum(w) ** 2 - 1.0)
+
+
+def mixture_density(logq, a):
+    """a + (1 - a) q."""
+    return a + (1.0 - a) * np.exp(logq)
 
 
 def _pq_backward(gz, glp, W, V, N, b, alpha, pdf, y):

@@ -62,6 +62,7 @@ class _IntegrateOpts(ctypes.Structure):
         ("edges_out", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
         ("flow", ctypes.c_void_p),
+        ("flow_mix", ctypes.c_double),
     ]
 
 
@@ -81,6 +82,20 @@ class _FlowTrainOpts(ctypes.Structure):
         ("batch", ctypes.c_int64),
         ("lr", ctypes.c_double),
         ("lr_final", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("loss", ctypes.c_int32),
+    ]
+
+
+class _FlowOnlineOpts(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int32),
+        ("batch", ctypes.c_int64),
+        ("lr", ctypes.c_double),
+        ("lr_final", ctypes.c_double),
+        ("loss", ctypes.c_int32),
+        ("flow_mix", ctypes.c_double),
+        ("iter_offset", ctypes.c_uint64),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -106,7 +121,7 @@ EXPORTS = ("mf_process_create", "mf_process_destroy", "mf_process_ndim", "mf_las
            "mf_integrand_grad", "mf_vegas_refine", "mf_integrate", "mf_grad", "mf_weights", "mf_weight_stats",
            "mf_flow_create", "mf_flow_destroy", "mf_flow_ndim", "mf_flow_param_count", "mf_flow_masks",
            "mf_flow_set_params", "mf_flow_get_params", "mf_flow_forward", "mf_flow_inverse", "mf_flow_loss_grad",
-           "mf_flow_adam_step", "mf_flow_train")
+           "mf_flow_adam_step", "mf_flow_train", "mf_flow_train_online")
 
 _lib = None
 
@@ -137,7 +152,7 @@ def lib():
         L.mf_integrate.restype = i32
         L.mf_grad.argtypes = [P, ctypes.POINTER(_IntegrateOpts), P, P]
         L.mf_grad.restype = i32
-        L.mf_weights.argtypes = [P, P, ctypes.c_uint64, i64, P, P, P]
+        L.mf_weights.argtypes = [P, P, d, ctypes.c_uint64, i64, P, P, P]
         L.mf_weights.restype = i32
         L.mf_weight_stats.argtypes = [P, i64, d, P, P]
         L.mf_weight_stats.restype = i32
@@ -159,12 +174,14 @@ def lib():
         L.mf_flow_forward.restype = i32
         L.mf_flow_inverse.argtypes = [P, P, i64, P, P, P]
         L.mf_flow_inverse.restype = i32
-        L.mf_flow_loss_grad.argtypes = [P, P, P, i64, P, ctypes.POINTER(d), P]
+        L.mf_flow_loss_grad.argtypes = [P, P, P, i64, i32, P, ctypes.POINTER(d), P]
         L.mf_flow_loss_grad.restype = i32
         L.mf_flow_adam_step.argtypes = [P, d, P]
         L.mf_flow_adam_step.restype = i32
         L.mf_flow_train.argtypes = [P, P, P, i64, ctypes.POINTER(_FlowTrainOpts), P]
         L.mf_flow_train.restype = i32
+        L.mf_flow_train_online.argtypes = [P, P, ctypes.POINTER(_FlowOnlineOpts), P]
+        L.mf_flow_train_online.restype = i32
         _lib = L
     return _lib
 
@@ -287,10 +304,11 @@ class Process:
 
     def integrate(self, n_iter: int, n_events: int, target_rel_err: float = 0.0, warmup: int = 0, adapt: bool = True,
                   iter_offset: int = 0, edges_in=None, edges_out=None, stream=None,
-                  flow: "Flow | None" = None) -> IntegrationResult:
+                  flow: "Flow | None" = None, flow_mix: float = 0.0) -> IntegrationResult:
         """VEGAS integration entirely on the device -- mf_integrate (flow: learned proposal, frozen grid)."""
         o = _IntegrateOpts()
         o.flow = flow._h.value if flow is not None else None
+        o.flow_mix = flow_mix
         o.n_iter, o.n_events, o.target_rel_err = n_iter, n_events, target_rel_err
         o.warmup_iters_discarded, o.adapt, o.iter_offset = warmup, int(adapt), iter_offset
         o.edges_in = _dev_ptr(edges_in) if edges_in is not None else None
@@ -306,16 +324,28 @@ class Process:
         return IntegrationResult(r.integral, r.error, r.chi2_dof, k, r.n_events_total, r.n_nonzero, r.n_nonfinite,
                                  r.seconds, r.time_to_target, r.kernel_seconds, Ii[:k].copy(), Ie[:k].copy())
 
-    def weights(self, it: int, n: int, flow: "Flow | None" = None, want_y: bool = False, stream=None):
+    def weights(self, it: int, n: int, flow: "Flow | None" = None, want_y: bool = False, stream=None,
+                flow_mix: float = 0.0):
         """(w[n] float64, y[ndim][n] float32 or None) of one frozen-grid sample -- mf_weights."""
         import torch
 
         w = torch.empty(n, dtype=torch.float64, device="cuda")
         y = torch.empty((self.ndim, n), dtype=torch.float32, device="cuda") if want_y else None
-        _check(lib().mf_weights(self._h, flow._h.value if flow is not None else None, it, n,
+        _check(lib().mf_weights(self._h, flow._h.value if flow is not None else None, flow_mix, it, n,
                                 _dev_ptr(y, "float32") if y is not None else None, _dev_ptr(w),
                                 _stream_ptr(stream)))
         return w, y
+
+    def train_flow_online(self, flow: "Flow", steps: int, batch: int = 16384, lr: float = 1e-3,
+                          lr_final: float = 1e-5, loss: str = "variance", flow_mix: float = 0.1,
+                          iter_offset: int = 1 << 20, stream=None) -> np.ndarray:
+        """On-policy training of the flow on this integrand -- mf_flow_train_online.
+
+        Returns the relative variance per event of each step's batch."""
+        o = _FlowOnlineOpts(steps, batch, lr, lr_final, Flow.LOSSES[loss], flow_mix, iter_offset, _stream_ptr(stream))
+        out = np.zeros(steps)
+        _check(lib().mf_flow_train_online(self._h, flow._h, ctypes.byref(o), out.ctypes.data))
+        return out
 
     def grad(self, n_events: int, iter_offset: int = 0, edges_in=None, stream=None):
         """(values[10], errors[10]): sigma, d sigma/d m_t, d sigma/d theta_0..7 -- mf_grad."""
@@ -330,10 +360,10 @@ class Process:
 
 
 def weight_stats(w, q: float = 0.999, stream=None) -> dict:
-    """mean, max, q-quantile and non-zero count of non-negative device weights -- mf_weight_stats."""
-    out = np.zeros(4)
+    """mean, max, q-quantile, non-zero count and relative variance per event of device weights -- mf_weight_stats."""
+    out = np.zeros(5)
     _check(lib().mf_weight_stats(_dev_ptr(w), w.numel(), q, out.ctypes.data, _stream_ptr(stream)))
-    return {"mean": out[0], "max": out[1], "quantile": out[2], "nonzero": int(out[3])}
+    return {"mean": out[0], "max": out[1], "quantile": out[2], "nonzero": int(out[3]), "relvar": out[4]}
 
 
 class Flow:
@@ -418,23 +448,26 @@ class Flow:
         """(y, log q(y)) for z [ndim][n] float32 -- mf_flow_inverse."""
         return self._run(lib().mf_flow_inverse, z, stream)
 
-    def loss_grad(self, y, w, stream=None):
-        """(loss, gradient [param_count] float32 device tensor) of one batch -- mf_flow_loss_grad."""
+    LOSSES = {"kl": 0, "variance": 1}
+
+    def loss_grad(self, y, w, loss: str = "kl", stream=None):
+        """(loss value, gradient [param_count] float32 device tensor) of one batch -- mf_flow_loss_grad."""
         import torch
 
         g = torch.empty(self.param_count, dtype=torch.float32, device=y.device)
-        loss = ctypes.c_double()
+        val = ctypes.c_double()
         _check(lib().mf_flow_loss_grad(self._h, _dev_ptr(y, "float32"), _dev_ptr(w, "float32"), y.shape[1],
-                                       _dev_ptr(g, "float32"), ctypes.byref(loss), _stream_ptr(stream)))
-        return loss.value, g
+                                       self.LOSSES[loss], _dev_ptr(g, "float32"), ctypes.byref(val),
+                                       _stream_ptr(stream)))
+        return val.value, g
 
     def adam_step(self, lr: float, stream=None):
         _check(lib().mf_flow_adam_step(self._h, lr, _stream_ptr(stream)))
 
     def train(self, y, w, epochs: int, batch: int = 16384, lr: float = 1e-3, lr_final: float = 1e-5,
-              stream=None) -> np.ndarray:
-        """Mean batch loss per epoch -- mf_flow_train."""
-        o = _FlowTrainOpts(epochs, batch, lr, lr_final, _stream_ptr(stream))
+              loss: str = "kl", stream=None) -> np.ndarray:
+        """Mean batch loss value per epoch -- mf_flow_train."""
+        o = _FlowTrainOpts(epochs, batch, lr, lr_final, _stream_ptr(stream), self.LOSSES[loss])
         out = np.zeros(epochs)
         _check(lib().mf_flow_train(self._h, _dev_ptr(y, "float32"), _dev_ptr(w, "float32"), y.shape[1],
                                    ctypes.byref(o), out.ctypes.data))

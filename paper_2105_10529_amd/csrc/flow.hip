@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/mf_flow.h"
+#include "flow_internal.h"
 #include "status.h"
 
 namespace mf {
@@ -131,12 +132,13 @@ __device__ __forceinline__ Bin find_bin(const float* W, const float* V, float t,
 }
 
 // --------------------------------------------------------- coupling layer
-// One layer for events [64 blockIdx.x, +64): y is [d][n] and is transformed
-// in place (the kept coordinates are only read).  INVERSE selects the
-// sampling direction.  logq[e] is set (first layer) or accumulated.
+// One layer for events [64 blockIdx.x, +64): y is [d][ld] (n <= ld events
+// used) and is transformed in place (the kept coordinates are only read).
+// INVERSE selects the sampling direction.  logq[e] is set (first layer) or
+// accumulated.  The caches use row length n.
 template <bool INVERSE, bool CACHE>
-__global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict__ y, int64_t n, float* __restrict__ logq,
-                                                  int first, LayerCache C, int d) {
+__global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict__ y, int64_t n, int64_t ld,
+                                                  float* __restrict__ logq, int first, LayerCache C, int d) {
   __shared__ __attribute__((aligned(16))) bf16 h1[T * H];  // also the logits of one coordinate (FP32)
   __shared__ __attribute__((aligned(16))) bf16 h2[T * H];  // also the first-layer inputs
   bf16* xa = h2;                                           // [T][KA]
@@ -152,7 +154,7 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
     const int m = idx % T, i = idx / T;
     const int64_t e = e0 + m;
     float v = 0.0f;
-    if (i < L.dA && e < n) v = y[(int64_t)L.a_idx[i] * n + e];
+    if (i < L.dA && e < n) v = y[(int64_t)L.a_idx[i] * ld + e];
     const bf16 hi = (bf16)v;
     const bf16 lo = (bf16)(v - (float)hi);
     const int il = i + KLO;
@@ -167,7 +169,7 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
     for (int idx = tid; idx < T * d; idx += 256) {
       const int m = idx % T, j = idx / T;
       const int64_t e = e0 + m;
-      if (e < n) C.lin[(int64_t)j * n + e] = y[(int64_t)j * n + e];
+      if (e < n) C.lin[(int64_t)j * n + e] = y[(int64_t)j * ld + e];
     }
   }
   __syncthreads();
@@ -277,7 +279,7 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
       if (e < n) {
         float W[KB], V[KB + 1];
         pq_params(out + tid * LDO, W, V);
-        float* yp = y + (int64_t)L.b_idx[c] * n + e;
+        float* yp = y + (int64_t)L.b_idx[c] * ld + e;
         const float t = *yp;
         const Bin B = find_bin(W, V, t, INVERSE);
         const float dV = B.Vb1 - B.Vb;
@@ -419,42 +421,67 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int64_t k0 = kb; k0 < ke; k0 += 32) {
     // stage A: 64 x 32
+    // (16-byte loads where the eight elements are in range; the caller
+    // guarantees 16-byte aligned rows: base and leading dimension multiples
+    // of 8 elements)
     if (A_KC) {
       const int m = tid >> 2, k8 = (tid & 3) * 8;
       const int gm = m0 + m;
       bf16x8 v;
+      if (gm < g.M && k0 + k8 + 8 <= ke) {
+        v = *reinterpret_cast<const bf16x8*>(g.A + (int64_t)gm * g.lda + k0 + k8);
+      } else {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t gk = k0 + k8 + i;
-        v[i] = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.lda + gk] : (bf16)0.0f;
+        for (int i = 0; i < 8; ++i) {
+          const int64_t gk = k0 + k8 + i;
+          v[i] = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.lda + gk] : (bf16)0.0f;
+        }
       }
       *reinterpret_cast<bf16x8*>(As + m * GLD + k8) = v;
     } else {
       const int k = tid >> 3, m8 = (tid & 7) * 8;
       const int64_t gk = k0 + k;
+      bf16x8 v;
+      if (gk < ke && m0 + m8 + 8 <= g.M) {
+        v = *reinterpret_cast<const bf16x8*>(g.A + gk * g.lda + m0 + m8);
+      } else {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int gm = m0 + m8 + i;
-        As[(m8 + i) * GLD + k] = (gm < g.M && gk < ke) ? g.A[gk * g.lda + gm] : (bf16)0.0f;
+        for (int i = 0; i < 8; ++i) {
+          const int gm = m0 + m8 + i;
+          v[i] = (gm < g.M && gk < ke) ? g.A[gk * g.lda + gm] : (bf16)0.0f;
+        }
       }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) As[(m8 + i) * GLD + k] = v[i];
     }
     // stage B: 32 x 64, stored n-major
     if (B_NC) {
       const int k = tid >> 3, n8 = (tid & 7) * 8;
       const int64_t gk = k0 + k;
+      bf16x8 v;
+      if (gk < ke && n0 + n8 + 8 <= g.N) {
+        v = *reinterpret_cast<const bf16x8*>(g.B + gk * g.ldb + n0 + n8);
+      } else {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int gn = n0 + n8 + i;
-        Bs[(n8 + i) * GLD + k] = (gn < g.N && gk < ke) ? g.B[gk * g.ldb + gn] : (bf16)0.0f;
+        for (int i = 0; i < 8; ++i) {
+          const int gn = n0 + n8 + i;
+          v[i] = (gn < g.N && gk < ke) ? g.B[gk * g.ldb + gn] : (bf16)0.0f;
+        }
       }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[(n8 + i) * GLD + k] = v[i];
     } else {
       const int nn = tid >> 2, k8 = (tid & 3) * 8;
       const int gn = n0 + nn;
       bf16x8 v;
+      if (gn < g.N && k0 + k8 + 8 <= ke) {
+        v = *reinterpret_cast<const bf16x8*>(g.B + (int64_t)gn * g.ldb + k0 + k8);
+      } else {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t gk = k0 + k8 + i;
-        v[i] = (gn < g.N && gk < ke) ? g.B[(int64_t)gn * g.ldb + gk] : (bf16)0.0f;
+        for (int i = 0; i < 8; ++i) {
+          const int64_t gk = k0 + k8 + i;
+          v[i] = (gn < g.N && gk < ke) ? g.B[(int64_t)gn * g.ldb + gk] : (bf16)0.0f;
+        }
       }
       *reinterpret_cast<bf16x8*>(Bs + nn * GLD + k8) = v;
     }
@@ -491,16 +518,24 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 }
 
 // Column sums of X[rows][ld] (first ncols columns) over row chunk z into
-// part[z][ncols] (FP32, in row order).
-__global__ void k_colsum(const bf16* __restrict__ X, int64_t rows, int ncols, int64_t ld, int64_t rchunk,
-                         float* __restrict__ part) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= ncols) return;
-  const int64_t r0 = (int64_t)blockIdx.y * rchunk;
-  const int64_t r1 = r0 + rchunk < rows ? r0 + rchunk : rows;
+// part[z][ncols] (FP32): a block takes 64 columns, its four waves take every
+// fourth row of the chunk (64 lanes read 128 contiguous bytes), and the four
+// wave sums are added in order.
+constexpr int64_t CS_ROWS = 256;
+__global__ void __launch_bounds__(256) k_colsum(const bf16* __restrict__ X, int64_t rows, int ncols, int64_t ld,
+                                                float* __restrict__ part) {
+  __shared__ float acc[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
+  const int64_t r0 = (int64_t)blockIdx.y * CS_ROWS;
+  const int64_t r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
   float s = 0.0f;
-  for (int64_t r = r0; r < r1; ++r) s += (float)X[r * ld + col];
-  part[(int64_t)blockIdx.y * ncols + col] = s;
+  if (col < ncols)
+    for (int64_t r = r0 + wave; r < r1; r += 4) s += (float)X[r * ld + col];
+  acc[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && col < ncols)
+    part[(int64_t)blockIdx.y * ncols + col] = ((acc[0][lane] + acc[1][lane]) + acc[2][lane]) + acc[3][lane];
 }
 
 // out[m ldo + map(n)] = sum_z part[z][m][n] (+ part[z][m + fold][n] when
@@ -546,6 +581,34 @@ __global__ void k_wsum(const float* __restrict__ w, int64_t n, float* __restrict
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = (float)s[0];
+}
+// variance loss: per-point weights w^2 / q (held fixed in the backward pass)
+__global__ void k_variance_weights(const float* __restrict__ w, const float* __restrict__ logq, int64_t n,
+                                   float* __restrict__ weff) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) weff[e] = w[e] * w[e] * __expf(-logq[e]);
+}
+// relative variance per event of sampling q, from points uniform in y:
+// n sum w^2/q / (sum w)^2 - 1
+__global__ void k_relvar(const float* __restrict__ w, const float* __restrict__ weff, int64_t n,
+                         float* __restrict__ out) {
+  __shared__ double s1[256], s2[256];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    a += w[i];
+    b += weff[i];
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      s1[threadIdx.x] += s1[threadIdx.x + st];
+      s2[threadIdx.x] += s2[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)((double)n * s2[0] / (s1[0] * s1[0]) - 1.0);
 }
 __global__ void k_loss(const float* __restrict__ w, const float* __restrict__ logq, int64_t n,
                        const float* __restrict__ wsum, float* __restrict__ out) {
@@ -648,6 +711,7 @@ struct mf_flow {
   float* d_y = nullptr;     // [d][cap]
   float* d_gy = nullptr;    // [d][cap]
   float* d_lq = nullptr;    // [cap]
+  float* d_weff = nullptr;  // [cap] per-point loss weights of the variance loss
   bf16* d_go = nullptr;     // [cap][dBmax*NOP]
   bf16* d_ga2 = nullptr;    // [cap][H]
   bf16* d_ga1 = nullptr;    // [cap][H]
@@ -700,25 +764,25 @@ void weight_grad(mf_flow* f, const bf16* X, int64_t ldx, int M, int m_real, cons
 // Bias gradient: column sums of G [n][ldg] over events.
 void bias_grad(mf_flow* f, const bf16* G, int64_t ldg, int N, int gpad, int greal, int64_t n, float* out,
                hipStream_t s) {
-  const int Z = (int)((n + SPLITK_CHUNK - 1) / SPLITK_CHUNK);
-  hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256, Z), dim3(256), 0, s, G, n, N, ldg, SPLITK_CHUNK, f->d_part);
+  const int Z = (int)((n + CS_ROWS - 1) / CS_ROWS);
+  hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64, Z), dim3(256), 0, s, G, n, N, ldg, f->d_part);
   hipLaunchKernelGGL(k_reduce_grad, dim3((N + 255) / 256), dim3(256), 0, s, f->d_part, Z, 1, N, 1, gpad, greal, out,
                      N, 0);
 }
 
-void run_layers(mf_flow* f, float* y, int64_t n, float* logq, bool inverse, bool cache, hipStream_t s) {
+void run_layers(mf_flow* f, float* y, int64_t n, int64_t ld, float* logq, bool inverse, bool cache, hipStream_t s) {
   const unsigned nblk = (unsigned)((n + T - 1) / T);
   for (int k = 0; k < f->nl; ++k) {
     const int l = inverse ? f->nl - 1 - k : k;
     LayerCache C = cache ? f->cache[l] : LayerCache{};
     if (inverse)
-      hipLaunchKernelGGL((k_coupling<true, false>), dim3(nblk), dim3(256), 0, s, f->L[l], y, n, logq, k == 0 ? 1 : 0,
-                         C, f->d);
+      hipLaunchKernelGGL((k_coupling<true, false>), dim3(nblk), dim3(256), 0, s, f->L[l], y, n, ld, logq,
+                         k == 0 ? 1 : 0, C, f->d);
     else if (cache)
-      hipLaunchKernelGGL((k_coupling<false, true>), dim3(nblk), dim3(256), 0, s, f->L[l], y, n, logq, k == 0 ? 1 : 0,
-                         C, f->d);
+      hipLaunchKernelGGL((k_coupling<false, true>), dim3(nblk), dim3(256), 0, s, f->L[l], y, n, ld, logq,
+                         k == 0 ? 1 : 0, C, f->d);
     else
-      hipLaunchKernelGGL((k_coupling<false, false>), dim3(nblk), dim3(256), 0, s, f->L[l], y, n, logq,
+      hipLaunchKernelGGL((k_coupling<false, false>), dim3(nblk), dim3(256), 0, s, f->L[l], y, n, ld, logq,
                          k == 0 ? 1 : 0, C, f->d);
   }
 }
@@ -736,15 +800,23 @@ mf_status copy_points(mf_flow* f, const float* src, int64_t n, float* dst, hipSt
   return MF_OK;
 }
 
-mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w, int64_t n, float* loss_dev,
-                         hipStream_t s) {
+mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w_in, int64_t n, int kind,
+                         float* loss_dev, hipStream_t s) {
   const int d = f->d;
   hipError_t e = hipMemcpy2DAsync(f->d_y, sizeof(float) * n, y, sizeof(float) * ldy, sizeof(float) * n, d,
                                   hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return set_error(MF_EDEVICE, "batch copy: %s", hipGetErrorString(e));
+  run_layers(f, f->d_y, n, n, f->d_lq, false, true, s);
+  const float* w = w_in;
+  if (kind == MF_FLOW_LOSS_VARIANCE) {
+    hipLaunchKernelGGL(k_variance_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w_in, f->d_lq, n,
+                       f->d_weff);
+    w = f->d_weff;
+    hipLaunchKernelGGL(k_relvar, dim3(1), dim3(256), 0, s, w_in, f->d_weff, n, loss_dev);
+  }
   hipLaunchKernelGGL(k_wsum, dim3(1), dim3(256), 0, s, w, n, f->d_scal);
-  run_layers(f, f->d_y, n, f->d_lq, false, true, s);
-  hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, s, w, f->d_lq, n, f->d_scal, loss_dev);
+  if (kind != MF_FLOW_LOSS_VARIANCE)
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, s, w, f->d_lq, n, f->d_scal, loss_dev);
   e = hipMemsetAsync(f->d_gy, 0, sizeof(float) * d * n, s);
   if (e != hipSuccess) return set_error(MF_EDEVICE, "gradient clear: %s", hipGetErrorString(e));
   for (int l = f->nl - 1; l >= 0; --l) {
@@ -814,6 +886,21 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
 
 }  // namespace
 
+namespace mf {
+mf_status flow_apply(mf_flow* f, float* y, int64_t n, int64_t ld, float* logq, bool inverse, hipStream_t s) {
+  if (n <= 0) return MF_OK;
+  run_layers(f, y, n, ld, logq, inverse, false, s);
+  return launch_err("k_coupling");
+}
+mf_status flow_step(mf_flow* f, const float* y, int64_t ld, const float* w, int64_t n, float* loss_dev, double lr,
+                    hipStream_t s) {
+  if (n < 1 || n > f->cap) return set_error(MF_EINVAL, "batch must be in 1..%lld", (long long)f->cap);
+  mf_status st = loss_grad_impl(f, y, ld, w, n, MF_FLOW_LOSS_KL, loss_dev, s);
+  if (st != MF_OK) return st;
+  return mf_flow_adam_step(f, lr, s);
+}
+}  // namespace mf
+
 extern "C" {
 
 mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
@@ -867,7 +954,9 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
   // caches: xa, h1, h2, o, lin per layer
   size_t per_layer = sizeof(bf16) * (size_t)cap * (KA + 2 * H) + sizeof(float) * (size_t)cap * (dBmax * NOP + d);
   const int64_t Zmax = (cap + SPLITK_CHUNK - 1) / SPLITK_CHUNK;
-  f->part_cap = (size_t)Zmax * (size_t)std::max<int64_t>((int64_t)H * dBmax * NOP, (int64_t)H * H);
+  const int64_t Zcs = (cap + CS_ROWS - 1) / CS_ROWS;
+  f->part_cap = std::max((size_t)Zmax * (size_t)std::max<int64_t>((int64_t)H * dBmax * NOP, (int64_t)H * H),
+                         (size_t)Zcs * (size_t)std::max<int64_t>(dBmax * NOP, H));
   if (hipMalloc(&f->d_p, sizeof(float) * off) != hipSuccess || hipMalloc(&f->d_g, sizeof(float) * off) != hipSuccess ||
       hipMalloc(&f->d_m1, sizeof(float) * off) != hipSuccess || hipMalloc(&f->d_m2, sizeof(float) * off) != hipSuccess ||
       hipMalloc(&f->d_w16, sizeof(bf16) * w16) != hipSuccess || hipMalloc(&f->d_b3p, sizeof(float) * b3) != hipSuccess ||
@@ -875,6 +964,7 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
       hipMalloc(&f->d_y, sizeof(float) * d * cap) != hipSuccess ||
       hipMalloc(&f->d_gy, sizeof(float) * d * cap) != hipSuccess ||
       hipMalloc(&f->d_lq, sizeof(float) * cap) != hipSuccess ||
+      hipMalloc(&f->d_weff, sizeof(float) * cap) != hipSuccess ||
       hipMalloc(&f->d_go, sizeof(bf16) * cap * dBmax * NOP) != hipSuccess ||
       hipMalloc(&f->d_ga2, sizeof(bf16) * cap * H) != hipSuccess ||
       hipMalloc(&f->d_ga1, sizeof(bf16) * cap * H) != hipSuccess ||
@@ -938,6 +1028,7 @@ void mf_flow_destroy(mf_flow* f) {
   hipFree(f->d_y);
   hipFree(f->d_gy);
   hipFree(f->d_lq);
+  hipFree(f->d_weff);
   hipFree(f->d_go);
   hipFree(f->d_ga2);
   hipFree(f->d_ga1);
@@ -994,7 +1085,7 @@ mf_status mf_flow_forward(mf_flow* f, const float* y, int64_t n, float* z, float
   hipStream_t s = (hipStream_t)stream;
   mf_status st = copy_points(f, y, n, z, s);
   if (st != MF_OK) return st;
-  run_layers(f, z, n, logq, false, false, s);
+  run_layers(f, z, n, n, logq, false, false, s);
   return launch_err("k_coupling");
 }
 
@@ -1007,18 +1098,20 @@ mf_status mf_flow_inverse(mf_flow* f, const float* z, int64_t n, float* y, float
   hipStream_t s = (hipStream_t)stream;
   mf_status st = copy_points(f, z, n, y, s);
   if (st != MF_OK) return st;
-  run_layers(f, y, n, logq, true, false, s);
+  run_layers(f, y, n, n, logq, true, false, s);
   return launch_err("k_coupling");
 }
 
-mf_status mf_flow_loss_grad(mf_flow* f, const float* y, const float* w, int64_t n, float* grad, double* loss,
-                            void* stream) {
+mf_status mf_flow_loss_grad(mf_flow* f, const float* y, const float* w, int64_t n, int32_t loss_kind, float* grad,
+                            double* loss, void* stream) {
   clear_error();
   if (!f) return set_error(MF_EINVAL, "NULL flow");
   if (n < 1 || n > f->cap) return set_error(MF_EINVAL, "n must be in 1..%lld", (long long)f->cap);
   if (!y || !w) return set_error(MF_EINVAL, "NULL buffer");
+  if (loss_kind != MF_FLOW_LOSS_KL && loss_kind != MF_FLOW_LOSS_VARIANCE)
+    return set_error(MF_EINVAL, "unknown loss %d", loss_kind);
   hipStream_t s = (hipStream_t)stream;
-  mf_status st = loss_grad_impl(f, y, n, w, n, f->d_scal + 1, s);
+  mf_status st = loss_grad_impl(f, y, n, w, n, loss_kind, f->d_scal + 1, s);
   if (st != MF_OK) return st;
   if (grad && hipMemcpyAsync(grad, f->d_g, sizeof(float) * f->count, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return set_error(MF_EDEVICE, "gradient copy failed");
@@ -1051,6 +1144,8 @@ mf_status mf_flow_train(mf_flow* f, const float* y, const float* w, int64_t n, c
   if (o->batch < 1 || o->batch > f->cap) return set_error(MF_EINVAL, "batch must be in 1..%lld", (long long)f->cap);
   if (n < 1) return set_error(MF_EINVAL, "no training points");
   if (!(o->lr > 0.0) || !(o->lr_final >= 0.0)) return set_error(MF_EINVAL, "invalid learning rates");
+  if (o->loss != MF_FLOW_LOSS_KL && o->loss != MF_FLOW_LOSS_VARIANCE)
+    return set_error(MF_EINVAL, "unknown loss %d", o->loss);
   hipStream_t s = (hipStream_t)o->stream;
   const int64_t per_epoch = (n + o->batch - 1) / o->batch;
   const int64_t total = per_epoch * o->epochs;
@@ -1066,7 +1161,7 @@ mf_status mf_flow_train(mf_flow* f, const float* y, const float* w, int64_t n, c
       const int64_t off = b * o->batch;
       const int64_t nb = std::min<int64_t>(o->batch, n - off);
       // batch slice of the [d][n] points: rows of nb values with pitch n
-      mf_status st = loss_grad_impl(f, y + off, n, w + off, nb, d_loss + t, s);
+      mf_status st = loss_grad_impl(f, y + off, n, w + off, nb, o->loss, d_loss + t, s);
       if (st != MF_OK) return st;
       const double lr = o->lr_final + 0.5 * (o->lr - o->lr_final) * (1.0 + std::cos(M_PI * (double)t / (double)total));
       st = mf_flow_adam_step(f, lr, s);

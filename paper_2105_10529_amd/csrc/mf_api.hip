@@ -27,6 +27,7 @@
 
 #include "../../include/mf.h"
 #include "../../include/mf_flow.h"
+#include "flow_internal.h"
 #include "launch.h"
 #include "pipeline.h"
 #include "status.h"
@@ -157,12 +158,12 @@ __global__ void __launch_bounds__(256) k_stage_points(const double* __restrict__
 
 // Points of a frozen-grid sample: y from Philox (yin == NULL, key word 1 =
 // purpose) or from the caller (FP32, e.g. drawn by the flow); x = map(y), the
-// Jacobian (divided by exp(logq) when logq is given: the weight of a point
-// drawn from the density exp(logq) in y), bins, and optionally y as FP32.
+// Jacobian (divided by a + (1 - a) exp(logq) when logq is given: the weight
+// of a point drawn from that density in y), bins, and optionally y as FP32.
 __global__ void __launch_bounds__(256) k_sample_points(const double* __restrict__ edges_g, int d, int nb, uint64_t iter,
                                                        int64_t N, uint64_t seed, uint64_t purpose,
                                                        const float* __restrict__ yin, const float* __restrict__ logq,
-                                                       float* __restrict__ yout, double* __restrict__ x,
+                                                       double mix, float* __restrict__ yout, double* __restrict__ x,
                                                        double* __restrict__ jac, unsigned char* __restrict__ bins) {
   extern __shared__ double edges[];
   for (int i = threadIdx.x; i < d * (nb + 1); i += blockDim.x) edges[i] = edges_g[i];
@@ -185,7 +186,7 @@ __global__ void __launch_bounds__(256) k_sample_points(const double* __restrict_
       bins[(int64_t)j * N + e] = (unsigned char)b;
       if (yout) yout[(int64_t)j * N + e] = (float)y[j];
     }
-    if (logq) J *= exp(-(double)logq[e]);
+    if (logq) J /= mix + (1.0 - mix) * exp((double)logq[e]);
     jac[e] = J;
   }
 }
@@ -211,6 +212,49 @@ __global__ void k_weight(const double* __restrict__ f, const double* __restrict_
   if (e >= N) return;
   const double v = f[e] * jac[e];
   w[e] = isfinite(v) ? v : 0.0;
+}
+
+// Per-sample weights of an on-policy training step from points drawn from
+// the mixture q_m = a + (1 - a) q: with r = f J / q_m (the sample weight),
+// the gradient of int p^2 / q_m is -(1-a) E_qm[r^2 (q/q_m) grad log q] and
+// that of the forward KL is -(1-a) E_qm[r (q/q_m) grad log q]; out[e] is
+// r^2 q/q_m (variance) or r q/q_m (KL) in FP32, and r2[e] = r^2 for the
+// batch's relative-variance estimate.
+__global__ void k_online_weights(const double* __restrict__ f, const double* __restrict__ jac,
+                                 const float* __restrict__ logq, double mix, int64_t N, int variance,
+                                 float* __restrict__ out, float* __restrict__ rw, float* __restrict__ r2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  double r = f[e] * jac[e];
+  r = isfinite(r) ? r : 0.0;
+  const double q = exp((double)logq[e]);
+  const double share = q / (mix + (1.0 - mix) * q);
+  out[e] = (float)((variance ? r * r : r) * share);
+  rw[e] = (float)r;
+  r2[e] = (float)(r * r);
+}
+
+// relative variance per event of a batch of sample weights r:
+// n sum r^2 / (sum r)^2 - 1
+__global__ void k_batch_relvar(const float* __restrict__ r, const float* __restrict__ r2, int64_t n,
+                               float* __restrict__ out) {
+  __shared__ double s1[256], s2[256];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    a += r[i];
+    b += r2[i];
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      s1[threadIdx.x] += s1[threadIdx.x + st];
+      s2[threadIdx.x] += s2[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)((double)n * s2[0] / (s1[0] * s1[0]) - 1.0);
 }
 
 // Accumulation kernel: weights w*J into the same per-block partials as the
@@ -450,6 +494,8 @@ struct mf_process {
   unsigned char* d_sbins = nullptr;  // [ndim][cap]
   float* d_sy = nullptr;           // [ndim][cap] flow points (FP32)
   float* d_slq = nullptr;          // [cap] flow log-density
+  float* d_sz = nullptr;           // [ndim][cap] scratch for the flow's density pass
+  float* d_sw32 = nullptr;         // [3][cap] on-policy training weights
 };
 
 namespace {
@@ -508,14 +554,18 @@ mf_status ensure_stage(mf_process* p, int64_t n, hipStream_t s) {
   hipFree(p->d_sbins);
   hipFree(p->d_sy);
   hipFree(p->d_slq);
+  hipFree(p->d_sz);
+  hipFree(p->d_sw32);
   p->d_sx = p->d_sjac = p->d_sw = nullptr;
   p->d_sbins = nullptr;
-  p->d_sy = p->d_slq = nullptr;
+  p->d_sy = p->d_slq = p->d_sz = p->d_sw32 = nullptr;
   p->stage_cap = 0;
   const size_t d = (size_t)p->ndim, m = (size_t)n;
   if (hipMalloc(&p->d_sx, sizeof(double) * d * m) != hipSuccess || hipMalloc(&p->d_sjac, sizeof(double) * m) != hipSuccess ||
       hipMalloc(&p->d_sw, sizeof(double) * m) != hipSuccess || hipMalloc(&p->d_sbins, d * m) != hipSuccess ||
-      hipMalloc(&p->d_sy, sizeof(float) * d * m) != hipSuccess || hipMalloc(&p->d_slq, sizeof(float) * m) != hipSuccess) {
+      hipMalloc(&p->d_sy, sizeof(float) * d * m) != hipSuccess || hipMalloc(&p->d_slq, sizeof(float) * m) != hipSuccess ||
+      hipMalloc(&p->d_sz, sizeof(float) * d * m) != hipSuccess ||
+      hipMalloc(&p->d_sw32, sizeof(float) * 3 * m) != hipSuccess) {
     hipGetLastError();
     return fail(MF_ENOMEM, "staging buffers for %lld events", (long long)n);
   }
@@ -523,21 +573,32 @@ mf_status ensure_stage(mf_process* p, int64_t n, hipStream_t s) {
   return MF_OK;
 }
 
-// Points and Jacobians of one frozen-grid sample into the staging buffers
-// (flow: Philox z -> flow inverse -> y -> map; else Philox y -> map).
-mf_status stage_sample(mf_process* p, mf_flow* flow, uint64_t iter, int64_t n, float* yout, hipStream_t s) {
+// Points and Jacobians of one frozen-grid sample into the staging buffers.
+// VEGAS: Philox y -> map.  Flow with mixture fraction a: Philox numbers with
+// key word 1; events e < floor(a n) use them as y directly (their flow
+// density from a density pass on a copy), the others as z through the
+// flow's sampling direction; every weight is divided by a + (1 - a) q(y).
+mf_status stage_sample(mf_process* p, mf_flow* flow, double mix, uint64_t iter, int64_t n, float* yout,
+                       hipStream_t s) {
   const int d = p->ndim, nb = p->nb;
   const int nblk = blocks_for(n);
   const size_t lds = sizeof(double) * d * (nb + 1);
   if (flow) {
     hipLaunchKernelGGL(k_uniform_f32, dim3(nblk), dim3(256), 0, s, d, iter, n, p->cfg.seed, (uint64_t)1, p->d_sy);
-    mf_status st = mf_flow_inverse(flow, p->d_sy, n, p->d_sy, p->d_slq, s);
+    const int64_t nu = (int64_t)std::floor(mix * (double)n);
+    mf_status st = mf::flow_apply(flow, p->d_sy + nu, n - nu, n, p->d_slq + nu, true, s);
     if (st != MF_OK) return st;
+    if (nu > 0) {
+      HIP_TRY(hipMemcpy2DAsync(p->d_sz, sizeof(float) * nu, p->d_sy, sizeof(float) * n, sizeof(float) * nu, d,
+                               hipMemcpyDeviceToDevice, s));
+      st = mf::flow_apply(flow, p->d_sz, nu, nu, p->d_slq, false, s);
+      if (st != MF_OK) return st;
+    }
     hipLaunchKernelGGL(k_sample_points, dim3(nblk), dim3(256), lds, s, p->d_edges, d, nb, iter, n, p->cfg.seed,
-                       (uint64_t)1, p->d_sy, p->d_slq, yout, p->d_sx, p->d_sjac, p->d_sbins);
+                       (uint64_t)1, p->d_sy, p->d_slq, mix, yout, p->d_sx, p->d_sjac, p->d_sbins);
   } else {
     hipLaunchKernelGGL(k_sample_points, dim3(nblk), dim3(256), lds, s, p->d_edges, d, nb, iter, n, p->cfg.seed,
-                       (uint64_t)0, (const float*)nullptr, (const float*)nullptr, yout, p->d_sx, p->d_sjac,
+                       (uint64_t)0, (const float*)nullptr, (const float*)nullptr, 0.0, yout, p->d_sx, p->d_sjac,
                        p->d_sbins);
   }
   return check_stream_launch("k_sample_points");
@@ -643,6 +704,8 @@ void mf_process_destroy(mf_process* p) {
   hipFree(p->d_sbins);
   hipFree(p->d_sy);
   hipFree(p->d_slq);
+  hipFree(p->d_sz);
+  hipFree(p->d_sw32);
   delete p;
 }
 
@@ -706,6 +769,7 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   const size_t lds = vegas_lds_bytes(d, nb);
   if (o->flow) {
     if (o->adapt) return fail(MF_EINVAL, "the grid is frozen under a flow proposal (adapt must be 0)");
+    if (!(o->flow_mix >= 0.0 && o->flow_mix < 1.0)) return fail(MF_EINVAL, "flow_mix must be in [0,1)");
     if (mf_flow_ndim(o->flow) != d) return fail(MF_EINVAL, "flow dimension differs from the integrand's");
   }
   if (!p->L.fused || o->flow) {
@@ -729,7 +793,7 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
     HIP_TRY(hipEventRecord(ev[2 * it], s));
     if (o->flow) {
       const int64_t N = o->n_events;
-      mf_status sst = stage_sample(p, o->flow, iter, N, nullptr, s);
+      mf_status sst = stage_sample(p, o->flow, o->flow_mix, iter, N, nullptr, s);
       if (sst != MF_OK) return sst;
       p->L.integrand(p->dc, p->d_sx, N, p->d_sw, nblk, s);
       hipLaunchKernelGGL(k_stage_accumulate, dim3(nblk), dim3(256), 0, s, p->d_sw, p->d_sjac, p->d_sbins, d, nb, N,
@@ -818,10 +882,11 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   return MF_OK;
 }
 
-mf_status mf_weights(mf_process* p, mf_flow* flow, uint64_t iter, int64_t n, float* y_out, double* w_out,
-                     void* stream) {
+mf_status mf_weights(mf_process* p, mf_flow* flow, double flow_mix, uint64_t iter, int64_t n, float* y_out,
+                     double* w_out, void* stream) {
   mf::clear_error();
   if (!p) return fail(MF_EINVAL, "NULL process");
+  if (flow && !(flow_mix >= 0.0 && flow_mix < 1.0)) return fail(MF_EINVAL, "flow_mix must be in [0,1)");
   if (n < 0) return fail(MF_EINVAL, "negative event count");
   if (n == 0) return MF_OK;
   if (!w_out) return fail(MF_EINVAL, "NULL weight buffer");
@@ -829,12 +894,55 @@ mf_status mf_weights(mf_process* p, mf_flow* flow, uint64_t iter, int64_t n, flo
   hipStream_t s = (hipStream_t)stream;
   mf_status st = ensure_stage(p, n, s);
   if (st != MF_OK) return st;
-  st = stage_sample(p, flow, iter, n, y_out, s);
+  st = stage_sample(p, flow, flow_mix, iter, n, y_out, s);
   if (st != MF_OK) return st;
   const int nblk = blocks_for(n);
   p->L.integrand(p->dc, p->d_sx, n, p->d_sw, nblk, s);
   hipLaunchKernelGGL(k_weight, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->d_sw, p->d_sjac, n, w_out);
   return check_stream_launch("k_weight");
+}
+
+mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_online_opts* o, double* loss_per_step) {
+  mf::clear_error();
+  if (!p || !flow || !o) return fail(MF_EINVAL, "NULL argument");
+  if (mf_flow_ndim(flow) != p->ndim) return fail(MF_EINVAL, "flow dimension differs from the integrand's");
+  if (o->steps < 1) return fail(MF_EINVAL, "steps must be >= 1");
+  if (o->batch < 2) return fail(MF_EINVAL, "batch must be >= 2");
+  if (!(o->flow_mix >= 0.0 && o->flow_mix < 1.0)) return fail(MF_EINVAL, "flow_mix must be in [0,1)");
+  if (!(o->lr > 0.0) || !(o->lr_final >= 0.0)) return fail(MF_EINVAL, "invalid learning rates");
+  if (o->loss != MF_FLOW_LOSS_KL && o->loss != MF_FLOW_LOSS_VARIANCE) return fail(MF_EINVAL, "unknown loss %d", o->loss);
+  hipStream_t s = (hipStream_t)o->stream;
+  const int64_t n = o->batch;
+  mf_status st = ensure_stage(p, n, s);
+  if (st != MF_OK) return st;
+  float* d_loss = nullptr;
+  HIP_TRY(hipMalloc(&d_loss, sizeof(float) * 2 * o->steps));
+  struct Free {
+    float* q;
+    ~Free() { (void)hipFree(q); }
+  } guard{d_loss};
+  const int nblk = blocks_for(n);
+  float* wt = p->d_sw32;
+  float* rw = p->d_sw32 + n;
+  float* r2 = p->d_sw32 + 2 * n;
+  for (int t = 0; t < o->steps; ++t) {
+    st = stage_sample(p, flow, o->flow_mix, o->iter_offset + (uint64_t)t, n, nullptr, s);
+    if (st != MF_OK) return st;
+    p->L.integrand(p->dc, p->d_sx, n, p->d_sw, nblk, s);
+    hipLaunchKernelGGL(k_online_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->d_sw, p->d_sjac,
+                       p->d_slq, o->flow_mix, n, o->loss == MF_FLOW_LOSS_VARIANCE ? 1 : 0, wt, rw, r2);
+    hipLaunchKernelGGL(k_batch_relvar, dim3(1), dim3(256), 0, s, rw, r2, n, d_loss + 2 * t);
+    const double lr =
+        o->lr_final + 0.5 * (o->lr - o->lr_final) * (1.0 + std::cos(M_PI * (double)t / (double)o->steps));
+    st = mf::flow_step(flow, p->d_sy, n, wt, n, d_loss + 2 * t + 1, lr, s);
+    if (st != MF_OK) return st;
+  }
+  std::vector<float> hl(2 * (size_t)o->steps);
+  HIP_TRY(hipMemcpyAsync(hl.data(), d_loss, sizeof(float) * 2 * o->steps, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (loss_per_step)
+    for (int t = 0; t < o->steps; ++t) loss_per_step[t] = hl[2 * (size_t)t];
+  return MF_OK;
 }
 
 mf_status mf_grad(mf_process* p, const mf_integrate_opts* o, double* out, double* err) {

@@ -16,12 +16,14 @@ namespace {
 constexpr int SB = 256;
 constexpr int SMAXB = 1024;
 
-// per-block sum (in a fixed order), max, non-zero and invalid counts
+// per-block sum and sum of squares (in a fixed order), max, non-zero and
+// invalid counts
+constexpr int NS = 5;
 __global__ void __launch_bounds__(SB) k_wstat_partial(const double* __restrict__ w, int64_t n, double* __restrict__ part) {
-  __shared__ double ss[SB], sm[SB], sz[SB], sb[SB];
+  __shared__ double ss[SB], sm[SB], sz[SB], sb[SB], sq[SB];
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;
   const int64_t b0 = (int64_t)blockIdx.x * per, b1 = b0 + per < n ? b0 + per : n;
-  double s = 0.0, m = -INFINITY, z = 0.0, bad = 0.0;
+  double s = 0.0, m = -INFINITY, z = 0.0, bad = 0.0, q = 0.0;
   for (int64_t i = b0 + threadIdx.x; i < b1; i += SB) {
     const double v = w[i];
     if (isnan(v)) {
@@ -29,6 +31,7 @@ __global__ void __launch_bounds__(SB) k_wstat_partial(const double* __restrict__
       continue;
     }
     s += v;
+    q += v * v;
     m = v > m ? v : m;
     z += v != 0.0 ? 1.0 : 0.0;
   }
@@ -36,10 +39,12 @@ __global__ void __launch_bounds__(SB) k_wstat_partial(const double* __restrict__
   sm[threadIdx.x] = m;
   sz[threadIdx.x] = z;
   sb[threadIdx.x] = bad;
+  sq[threadIdx.x] = q;
   __syncthreads();
   for (int st = SB / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) {
       ss[threadIdx.x] += ss[threadIdx.x + st];
+      sq[threadIdx.x] += sq[threadIdx.x + st];
       sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
       sz[threadIdx.x] += sz[threadIdx.x + st];
       sb[threadIdx.x] += sb[threadIdx.x + st];
@@ -47,26 +52,29 @@ __global__ void __launch_bounds__(SB) k_wstat_partial(const double* __restrict__
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[4 * blockIdx.x + 0] = ss[0];
-    part[4 * blockIdx.x + 1] = sm[0];
-    part[4 * blockIdx.x + 2] = sz[0];
-    part[4 * blockIdx.x + 3] = sb[0];
+    part[NS * blockIdx.x + 0] = ss[0];
+    part[NS * blockIdx.x + 1] = sm[0];
+    part[NS * blockIdx.x + 2] = sz[0];
+    part[NS * blockIdx.x + 3] = sb[0];
+    part[NS * blockIdx.x + 4] = sq[0];
   }
 }
 
 __global__ void k_wstat_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
   if (threadIdx.x != 0) return;
-  double s = 0.0, m = -INFINITY, z = 0.0, bad = 0.0;
+  double s = 0.0, m = -INFINITY, z = 0.0, bad = 0.0, q = 0.0;
   for (int b = 0; b < nb; ++b) {
-    s += part[4 * b];
-    m = fmax(m, part[4 * b + 1]);
-    z += part[4 * b + 2];
-    bad += part[4 * b + 3];
+    s += part[NS * b];
+    m = fmax(m, part[NS * b + 1]);
+    z += part[NS * b + 2];
+    bad += part[NS * b + 3];
+    q += part[NS * b + 4];
   }
   out[0] = s;
   out[1] = m;
   out[2] = z;
   out[3] = bad;
+  out[4] = q;
 }
 
 // state: [0] prefix, [1] mask of the fixed high bits, [2] rank still to find
@@ -121,11 +129,11 @@ extern "C" mf_status mf_weight_stats(const double* w, int64_t n, double q, doubl
   const int nb = (int)(n < (int64_t)SMAXB * SB ? (n + SB - 1) / SB : SMAXB);
   double* part = nullptr;
   unsigned long long* st = nullptr;
-  if (hipMallocAsync((void**)&part, sizeof(double) * (4 * nb + 4), s) != hipSuccess ||
+  if (hipMallocAsync((void**)&part, sizeof(double) * (NS * nb + NS), s) != hipSuccess ||
       hipMallocAsync((void**)&st, sizeof(unsigned long long) * (256 + 3), s) != hipSuccess)
     return mf::set_error(MF_ENOMEM, "statistics buffers");
   hipLaunchKernelGGL(k_wstat_partial, dim3(nb), dim3(SB), 0, s, w, n, part);
-  hipLaunchKernelGGL(k_wstat_final, dim3(1), dim3(64), 0, s, part, nb, part + 4 * nb);
+  hipLaunchKernelGGL(k_wstat_final, dim3(1), dim3(64), 0, s, part, nb, part + NS * nb);
   // rank of the quantile: ceil(q n) - 1
   unsigned long long rank = (unsigned long long)std::ceil(q * (double)n);
   if (rank < 1) rank = 1;
@@ -139,10 +147,10 @@ extern "C" mf_status mf_weight_stats(const double* w, int64_t n, double q, doubl
     hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(SB), 0, s, w, n, st, shift, hist);
     hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(64), 0, s, hist, st, shift);
   }
-  double tot[4] = {0, 0, 0, 0};
+  double tot[NS] = {0, 0, 0, 0, 0};
   unsigned long long res[3] = {0, 0, 0};
   if (ret == MF_OK && (hipGetLastError() != hipSuccess ||
-                       hipMemcpyAsync(tot, part + 4 * nb, sizeof(tot), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                       hipMemcpyAsync(tot, part + NS * nb, sizeof(tot), hipMemcpyDeviceToHost, s) != hipSuccess ||
                        hipMemcpyAsync(res, st, sizeof(res), hipMemcpyDeviceToHost, s) != hipSuccess ||
                        hipStreamSynchronize(s) != hipSuccess))
     ret = MF_EDEVICE;
@@ -159,5 +167,7 @@ extern "C" mf_status mf_weight_stats(const double* w, int64_t n, double q, doubl
   std::memcpy(&qv, &bits, sizeof(qv));
   out[2] = qv;
   out[3] = tot[2];
+  const double m1 = tot[0] / (double)n, m2 = tot[4] / (double)n;
+  out[4] = m1 != 0.0 ? m2 / (m1 * m1) - 1.0 : 0.0;
   return MF_OK;
 }

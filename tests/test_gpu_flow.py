@@ -114,8 +114,9 @@ def _set(f, params):
     return params
 
 
-@pytest.mark.parametrize("d,n", [(10, 2000), (7, 1100)])
-def test_loss_gradient_matches_oracle_exact_forward(d, n):
+@pytest.mark.parametrize("d,n,loss", [(10, 2000, "kl"), (7, 1100, "kl"), (10, 2000, "variance"),
+                                      (7, 1100, "variance")])
+def test_loss_gradient_matches_oracle_exact_forward(d, n, loss):
     """One layer with BF16-exact forward arithmetic (dyadic parameters and
     inputs): the loss agrees to FP32 rounding and the gradient differs from
     the FP64 one only by the BF16 rounding of the backward pass itself."""
@@ -129,8 +130,12 @@ def test_loss_gradient_matches_oracle_exact_forward(d, n):
     g_ref = oflow.backward(params, mk, caches, w, K)
     z, lq = f.forward(_dev32(y))
     assert np.max(np.abs(lq.cpu().numpy() - lq_ref)) < 1e-4
-    L, g = f.loss_grad(_dev32(y), torch.from_numpy(w.astype(np.float32)).cuda())
-    L_ref = oflow.loss(lq_ref, w)
+    L, g = f.loss_grad(_dev32(y), torch.from_numpy(w.astype(np.float32)).cuda(), loss=loss)
+    if loss == "kl":
+        L_ref = oflow.loss(lq_ref, w)
+    else:
+        L_ref = oflow.relative_variance(lq_ref, w)
+        g_ref = oflow.backward(params, mk, caches, oflow.variance_weights(lq_ref, w), K)
     assert abs(L - L_ref) <= 1e-5 * max(1.0, abs(L_ref)), (L, L_ref)
     g_layers = f.unflatten(g.cpu().numpy())
     for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
@@ -233,6 +238,8 @@ def test_weight_stats_are_exact():
             assert s["max"] == w.max() and s["nonzero"] == np.count_nonzero(w)
             assert s["quantile"] == np.quantile(w, q, method="inverted_cdf"), (n, q)
             assert abs(s["mean"] - w.mean()) <= 1e-13 * max(abs(w.mean()), 1e-300)
+            if w.mean() != 0:
+                assert abs(s["relvar"] - (np.mean(w * w) / w.mean() ** 2 - 1)) <= 1e-10 * max(1.0, s["relvar"])
     w = -rng.lognormal(0.0, 1.0, 1001)
     s = mf.weight_stats(torch.from_numpy(w).cuda(), 0.25)
     assert s["quantile"] == np.quantile(w, 0.25, method="inverted_cdf") and s["max"] == w.max()
@@ -258,16 +265,24 @@ def test_invalid_flow_arguments():
         p.integrate(1, 1000, adapt=False, flow=f)
 
 
-def test_flow_sample_weights_match_oracle_integrand():
-    """w = f(x(y)) J(y) / q(y) for the flow's own points, against the oracle
-    integrand at the same mapped points (q from the flow, FP32)."""
+@pytest.mark.parametrize("mix", [0.0, 0.3])
+def test_flow_sample_weights_match_oracle_integrand(mix):
+    """w = f(x(y)) J(y) / (a + (1-a) q(y)) for the proposal's own points,
+    against the oracle integrand at the same mapped points (q from the flow,
+    FP32); the uniform part of the mixture takes the Philox numbers of key
+    word 1 as its points."""
     p = mf.Process(mf.Config(process="gg>ttxg"))
     p.integrate(3, 20000, adapt=True)
     edges = torch.empty((7, 51), dtype=torch.float64, device="cuda")
     p.integrate(1, 2, adapt=False, edges_out=edges, iter_offset=50)
     f, mk, params = _flow_and_params(7, 0.3, seed=60)
-    w, y = p.weights(7, 1500, flow=f, want_y=True)
+    n = 1500
+    w, y = p.weights(7, n, flow=f, want_y=True, flow_mix=mix)
     y = y.cpu().numpy().T.astype(np.float64)
+    nu = int(np.floor(mix * n))
+    u = oracle.event_uniforms(n, 7, 7, p.cfg.seed, purpose=1)
+    assert np.array_equal(y[:nu], u[:nu].astype(np.float32).astype(np.float64))
+    assert np.all(np.abs(y[nu:] - u[nu:]).max(axis=1) > 0)
     # the flow's density at those points, from its forward direction
     _, lq = f.forward(_dev32(y))
     lq = lq.cpu().numpy().astype(np.float64)
@@ -277,7 +292,7 @@ def test_flow_sample_weights_match_oracle_integrand():
         x, jac, _ = oracle.vegas_map(E, yy)
         xs.append(x)
         js.append(jac)
-    ref = oracle.Oracle(oracle.Config(n_g=1)).integrand(np.array(xs)) * np.array(js) * np.exp(-lq)
+    ref = oracle.Oracle(oracle.Config(n_g=1)).integrand(np.array(xs)) * np.array(js) / oflow.mixture_density(lq, mix)
     got = w.cpu().numpy()
     nz = ref != 0
     assert nz.sum() > 500 and np.array_equal(got != 0, nz)
@@ -300,3 +315,24 @@ def test_trained_flow_is_a_consistent_proposal_on_gg_ttg():
     rf = p.integrate(2, n, adapt=False, iter_offset=2000, flow=f)
     assert abs(rf.integral - rv.integral) < 4.0 * np.hypot(rf.error, rv.error), (rf, rv)
     assert rf.n_nonzero > 1.05 * rv.n_nonzero, (rf.n_nonzero, rv.n_nonzero)
+
+
+def test_variance_trained_flow_beats_vegas_on_gg_ttg():
+    """On-policy training on the variance of the weights, from the identity
+    flow on the adapted VEGAS grid: with the same number of events the flow's
+    error is below VEGAS's on the same grid, and at 4e7 events each the two
+    integrals agree within their errors (no bias from the learned proposal)."""
+    p = mf.Process(mf.Config(process="gg>ttxg"))
+    p.integrate(5, 1_000_000, adapt=True)
+    f = mf.Flow(7, max_batch=16384)
+    rel = p.train_flow_online(f, 300, batch=16384, lr=3e-3, loss="variance", flow_mix=0.1)
+    assert rel.shape == (300,) and np.all(np.isfinite(rel))
+    n = 10_000_000
+    rv = p.integrate(4, n, adapt=False, iter_offset=2000)
+    rf = p.integrate(4, n, adapt=False, iter_offset=2000, flow=f)
+    assert rf.error < rv.error, (rf.error, rv.error)
+    assert abs(rf.integral - rv.integral) < 3.0 * np.hypot(rf.error, rv.error), (rf.integral, rv.integral)
+    wv, _ = p.weights(3000, 2_000_000)
+    wf, _ = p.weights(3000, 2_000_000, flow=f)
+    sv, sf = mf.weight_stats(wv), mf.weight_stats(wf)
+    assert sf["relvar"] < sv["relvar"], (sf, sv)

@@ -103,3 +103,33 @@ def test_training_lowers_the_loss_on_a_peaked_target():
         flow.adam_step(params, flow.backward(params, mk, c, w, K), state, 3e-3, t)
     l1 = flow.loss(flow.forward(params, mk, y, K)[1], w)
     assert l0 == pytest.approx(0.0, abs=1e-12) and l1 < -0.5
+
+
+def test_variance_gradient_is_the_reweighted_kl_gradient():
+    """d log sum w^2/q = the KL gradient with weights w^2/q held fixed."""
+    mk, params = _setup(d=5, hidden=8, scale=0.5)
+    y = si.unit_points(64, 5, seed=12)
+    w = np.random.default_rng(13).exponential(size=64)
+    _, logq, caches = flow.forward(params, mk, y, K)
+    grads = flow.backward(params, mk, caches, flow.variance_weights(logq, w), K)
+    for name in ("W1", "b3"):
+        arr = params[2][name]
+        idx = (0, 1) if arr.ndim == 2 else (3,)
+        old = arr[idx]
+        h = 1e-6
+        arr[idx] = old + h
+        lp = flow.log_variance_loss(flow.forward(params, mk, y, K)[1], w)
+        arr[idx] = old - h
+        lm = flow.log_variance_loss(flow.forward(params, mk, y, K)[1], w)
+        arr[idx] = old
+        assert abs(grads[2][name][idx] - (lp - lm) / (2 * h)) < 1e-6 * max(1.0, abs(grads[2][name][idx]))
+
+
+def test_relative_variance_and_mixture_special_cases():
+    w = np.random.default_rng(14).exponential(size=1000)
+    # identity flow: the relative variance of uniform sampling
+    assert abs(flow.relative_variance(np.zeros(1000), w) - (w.var() / w.mean() ** 2)) < 1e-12
+    # q proportional to w gives zero variance
+    lq = np.log(w / w.mean())
+    assert abs(flow.relative_variance(lq, w)) < 1e-12
+    assert np.allclose(flow.mixture_density(np.log(np.full(3, 4.0)), 0.25), 0.25 + 0.75 * 4.0)
