@@ -14,10 +14,12 @@
 //   k_gemm          LDS-staged BF16 MFMA product with split-K for the weight
 //                   gradients and a LeakyReLU-derivative epilogue for the
 //                   activation gradients
-//   k_colsum / k_reduce_grad   ordered reductions into the FP32 gradient
+//   k_reduce_grad   ordered reduction of the split-K partials into the FP32
+//                   gradient
 //   k_adam          Adam on the FP32 masters and refresh of the BF16 copies
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -386,7 +388,10 @@ __global__ void __launch_bounds__(256) k_pq_backward(LayerDev L, LayerCache C, i
 // FP32 accumulation, tile 64 x 64 per workgroup, k-step 32 staged in LDS.
 //   A_KC: A(m,k) = A[m lda + k] (1) or A[k lda + m] (0)
 //   B_NC: B(k,n) = B[k ldb + n] (1) or B[n ldb + k] (0)
-//   EPI 0: FP32 store to Cf + z zs + m ldc + n (split-K partials)
+//   EPI 0: FP32 store to Cf + z zs + m ldc + n (split-K partials); with
+//          colsum set, row M of the partial receives the column sums of B
+//          over the chunk (one more MFMA per k-step with an all-ones A
+//          fragment in the first row of blocks)
 //   EPI 1: BF16 store to Cb[m ldc + n] of acc * (ref[m ldr + n] > 0 ? 1 : slope)
 struct GemmArgs {
   const bf16* A;
@@ -400,6 +405,7 @@ struct GemmArgs {
   bf16* Cb;
   const bf16* ref;
   int64_t ldc, ldr;
+  int colsum;
 };
 
 constexpr int GLD = 40;  // LDS row stride (bf16) of a staged 32-wide k slice
@@ -419,6 +425,11 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  f32x4 accs[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
+  const bool sums = EPI == 0 && g.colsum && blockIdx.y == 0 && wm == 0;
+  bf16x8 ones;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) ones[i] = (bf16)1.0f;
   for (int64_t k0 = kb; k0 < ke; k0 += 32) {
     // stage A: 64 x 32
     // (16-byte loads where the eight elements are in range; the caller
@@ -495,7 +506,18 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+    if (sums) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) accs[j] = mfma16(ones, b[j], accs[j]);
+    }
     __syncthreads();
+  }
+  if (sums && quad == 0) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gn = n0 + wn + 16 * j + row;
+      if (gn < g.N) g.Cf[(int64_t)blockIdx.z * g.zs + (int64_t)g.M * g.ldc + gn] = accs[j][0];
+    }
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -517,44 +539,33 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     }
 }
 
-// Column sums of X[rows][ld] (first ncols columns) over row chunk z into
-// part[z][ncols] (FP32): a block takes 64 columns, its four waves take every
-// fourth row of the chunk (64 lanes read 128 contiguous bytes), and the four
-// wave sums are added in order.
-constexpr int64_t CS_ROWS = 256;
-__global__ void __launch_bounds__(256) k_colsum(const bf16* __restrict__ X, int64_t rows, int ncols, int64_t ld,
-                                                float* __restrict__ part) {
-  __shared__ float acc[4][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = blockIdx.x * 64 + lane;
-  const int64_t r0 = (int64_t)blockIdx.y * CS_ROWS;
-  const int64_t r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
-  float s = 0.0f;
-  if (col < ncols)
-    for (int64_t r = r0 + wave; r < r1; r += 4) s += (float)X[r * ld + col];
-  acc[wave][lane] = s;
-  __syncthreads();
-  if (wave == 0 && col < ncols)
-    part[(int64_t)blockIdx.y * ncols + col] = ((acc[0][lane] + acc[1][lane]) + acc[2][lane]) + acc[3][lane];
-}
-
 // out[m ldo + map(n)] = sum_z part[z][m][n] (+ part[z][m + fold][n] when
-// fold > 0: the two halves of a split input) for m < m_real; the column map
-// drops the padding of groups of gpad columns to greal (gpad = 0: identity).
+// fold > 0: the two halves of a split input) for m < m_real, and
+// bias[map(n)] = sum_z part[z][M][n] (the column-sum row); partials have
+// M + 1 rows.  The column map drops the padding of groups of gpad columns to
+// greal (gpad = 0: identity).  Sums run over z in order.
 __global__ void k_reduce_grad(const float* __restrict__ part, int Z, int M, int N, int m_real, int gpad, int greal,
-                              float* __restrict__ out, int ldo, int fold) {
+                              float* __restrict__ out, int ldo, int fold, float* __restrict__ bias) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)m_real * N) return;
-  const int m = (int)(idx / N), nn = (int)(idx % N);
+  if (idx >= (int64_t)(m_real + 1) * N) return;
+  const int m = (int)(idx / N);
+  const int nn = (int)(idx % N);
   int col = nn;
   if (gpad) {
     if (nn % gpad >= greal) return;
     col = (nn / gpad) * greal + nn % gpad;
   }
+  const int64_t zs = (int64_t)(M + 1) * N;
+  if (m == m_real) {
+    float s = 0.0f;
+    for (int z = 0; z < Z; ++z) s += part[z * zs + (int64_t)M * N + nn];
+    bias[col] = s;
+    return;
+  }
   float s = 0.0f;
   for (int z = 0; z < Z; ++z) {
-    s += part[((int64_t)z * M + m) * N + nn];
-    if (fold) s += part[((int64_t)z * M + m + fold) * N + nn];
+    s += part[z * zs + (int64_t)m * N + nn];
+    if (fold) s += part[z * zs + (int64_t)(m + fold) * N + nn];
   }
   out[(int64_t)m * ldo + col] = s;
 }
@@ -570,13 +581,14 @@ __global__ void k_add_gx(LayerDev L, const float* __restrict__ gx, int64_t n, fl
 
 // sum of w over the batch (one block, fixed order) and the loss
 // -sum w logq / sum w
-__global__ void k_wsum(const float* __restrict__ w, int64_t n, float* __restrict__ out) {
-  __shared__ double s[256];
+constexpr int RB = 1024;  // threads of the single-block batch reductions
+__global__ void __launch_bounds__(RB) k_wsum(const float* __restrict__ w, int64_t n, float* __restrict__ out) {
+  __shared__ double s[RB];
   double a = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) a += w[i];
+  for (int64_t i = threadIdx.x; i < n; i += RB) a += w[i];
   s[threadIdx.x] = a;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = RB / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
     __syncthreads();
   }
@@ -590,18 +602,18 @@ __global__ void k_variance_weights(const float* __restrict__ w, const float* __r
 }
 // relative variance per event of sampling q, from points uniform in y:
 // n sum w^2/q / (sum w)^2 - 1
-__global__ void k_relvar(const float* __restrict__ w, const float* __restrict__ weff, int64_t n,
-                         float* __restrict__ out) {
-  __shared__ double s1[256], s2[256];
+__global__ void __launch_bounds__(RB) k_relvar(const float* __restrict__ w, const float* __restrict__ weff, int64_t n,
+                                               float* __restrict__ out) {
+  __shared__ double s1[RB], s2[RB];
   double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
+  for (int64_t i = threadIdx.x; i < n; i += RB) {
     a += w[i];
     b += weff[i];
   }
   s1[threadIdx.x] = a;
   s2[threadIdx.x] = b;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = RB / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) {
       s1[threadIdx.x] += s1[threadIdx.x + st];
       s2[threadIdx.x] += s2[threadIdx.x + st];
@@ -610,14 +622,14 @@ __global__ void k_relvar(const float* __restrict__ w, const float* __restrict__ 
   }
   if (threadIdx.x == 0) out[0] = (float)((double)n * s2[0] / (s1[0] * s1[0]) - 1.0);
 }
-__global__ void k_loss(const float* __restrict__ w, const float* __restrict__ logq, int64_t n,
-                       const float* __restrict__ wsum, float* __restrict__ out) {
-  __shared__ double s[256];
+__global__ void __launch_bounds__(RB) k_loss(const float* __restrict__ w, const float* __restrict__ logq, int64_t n,
+                                             const float* __restrict__ wsum, float* __restrict__ out) {
+  __shared__ double s[RB];
   double a = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) a += (double)w[i] * logq[i];
+  for (int64_t i = threadIdx.x; i < n; i += RB) a += (double)w[i] * logq[i];
   s[threadIdx.x] = a;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = RB / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
     __syncthreads();
   }
@@ -724,7 +736,8 @@ struct mf_flow {
 
 namespace {
 
-constexpr int64_t SPLITK_CHUNK = 1024;
+constexpr int64_t SPLITK_BLOCKS = 512;
+constexpr int64_t SPLITK_MIN = 256;
 
 mf_status launch_err(const char* what) {
   hipError_t e = hipGetLastError();
@@ -738,11 +751,25 @@ void gemm(const GemmArgs& a, int Z, hipStream_t s) {
   hipLaunchKernelGGL((k_gemm<A_KC, B_NC, EPI>), grid, dim3(256), 0, s, a);
 }
 
-// Weight gradient dW[in][out] = X^T G over the batch: X [n][ldx] (first M
-// columns), G [n][ldg] (first N columns), both BF16, split over events.
+// Number of event chunks of a weight-gradient product over n events with an
+// M x N output: enough workgroups to fill the chip (about SPLITK_BLOCKS),
+// chunks of at least SPLITK_MIN events.  Non-decreasing in n.
+int64_t splitk(int64_t n, int M, int N) {
+  const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+  int64_t z = (SPLITK_BLOCKS + tiles - 1) / tiles;
+  const int64_t zmax = (n + SPLITK_MIN - 1) / SPLITK_MIN;
+  z = z < zmax ? z : zmax;
+  return z < 1 ? 1 : z;
+}
+
+// Weight and bias gradients over the batch: dW[in][out] = X^T G and
+// db[out] = column sums of G, with X [n][ldx] (first M columns) and G
+// [n][ldg] (first N columns) in BF16, split over events.
 void weight_grad(mf_flow* f, const bf16* X, int64_t ldx, int M, int m_real, const bf16* G, int64_t ldg, int N,
-                 int gpad, int greal, int64_t n, float* out, int ldo, hipStream_t s, int fold = 0) {
-  const int Z = (int)((n + SPLITK_CHUNK - 1) / SPLITK_CHUNK);
+                 int gpad, int greal, int64_t n, float* out, int ldo, float* bias, hipStream_t s, int fold = 0) {
+  const int64_t Z = splitk(n, M, N);
+  const int64_t chunk = ((n + Z - 1) / Z + 31) / 32 * 32;
+  const int Zl = (int)((n + chunk - 1) / chunk);
   GemmArgs a{};
   a.A = X;
   a.lda = ldx;
@@ -751,23 +778,15 @@ void weight_grad(mf_flow* f, const bf16* X, int64_t ldx, int M, int m_real, cons
   a.M = M;
   a.N = N;
   a.K = n;
-  a.kchunk = SPLITK_CHUNK;
+  a.kchunk = chunk;
   a.Cf = f->d_part;
-  a.zs = (int64_t)M * N;
+  a.zs = (int64_t)(M + 1) * N;
   a.ldc = N;
-  gemm<0, 1, 0>(a, Z, s);
-  const int64_t tot = (int64_t)m_real * N;
-  hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, f->d_part, Z, M, N, m_real,
-                     gpad, greal, out, ldo, fold);
-}
-
-// Bias gradient: column sums of G [n][ldg] over events.
-void bias_grad(mf_flow* f, const bf16* G, int64_t ldg, int N, int gpad, int greal, int64_t n, float* out,
-               hipStream_t s) {
-  const int Z = (int)((n + CS_ROWS - 1) / CS_ROWS);
-  hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64, Z), dim3(256), 0, s, G, n, N, ldg, f->d_part);
-  hipLaunchKernelGGL(k_reduce_grad, dim3((N + 255) / 256), dim3(256), 0, s, f->d_part, Z, 1, N, 1, gpad, greal, out,
-                     N, 0);
+  a.colsum = 1;
+  gemm<0, 1, 0>(a, Zl, s);
+  const int64_t tot = (int64_t)(m_real + 1) * N;
+  hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, f->d_part, Zl, M, N, m_real,
+                     gpad, greal, out, ldo, fold, bias);
 }
 
 void run_layers(mf_flow* f, float* y, int64_t n, int64_t ld, float* logq, bool inverse, bool cache, hipStream_t s) {
@@ -812,11 +831,11 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     hipLaunchKernelGGL(k_variance_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w_in, f->d_lq, n,
                        f->d_weff);
     w = f->d_weff;
-    hipLaunchKernelGGL(k_relvar, dim3(1), dim3(256), 0, s, w_in, f->d_weff, n, loss_dev);
+    hipLaunchKernelGGL(k_relvar, dim3(1), dim3(RB), 0, s, w_in, f->d_weff, n, loss_dev);
   }
-  hipLaunchKernelGGL(k_wsum, dim3(1), dim3(256), 0, s, w, n, f->d_scal);
+  hipLaunchKernelGGL(k_wsum, dim3(1), dim3(RB), 0, s, w, n, f->d_scal);
   if (kind != MF_FLOW_LOSS_VARIANCE)
-    hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, s, w, f->d_lq, n, f->d_scal, loss_dev);
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(RB), 0, s, w, f->d_lq, n, f->d_scal, loss_dev);
   e = hipMemsetAsync(f->d_gy, 0, sizeof(float) * d * n, s);
   if (e != hipSuccess) return set_error(MF_EDEVICE, "gradient clear: %s", hipGetErrorString(e));
   for (int l = f->nl - 1; l >= 0; --l) {
@@ -832,8 +851,7 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     const int64_t tot = n * L.dB;
     hipLaunchKernelGGL(k_pq_backward, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L, C, n, f->d_gy, w,
                        f->d_scal, f->d_go);
-    bias_grad(f, f->d_go, NB, NB, NOP, NO, n, gb3, s);
-    weight_grad(f, C.h2, H, H, H, f->d_go, NB, NB, NOP, NO, n, gW3, nO, s);
+    weight_grad(f, C.h2, H, H, H, f->d_go, NB, NB, NOP, NO, n, gW3, nO, gb3, s);
     // ga2 = (go W3^T) * leaky'(h2): A = go [n][NB], B(k=o, n=j) = W3t[o][j]
     GemmArgs a{};
     a.A = f->d_go;
@@ -849,8 +867,7 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     a.ldc = H;
     a.ldr = H;
     gemm<1, 1, 1>(a, 1, s);
-    bias_grad(f, f->d_ga2, H, H, 0, 0, n, gb2, s);
-    weight_grad(f, C.h1, H, H, H, f->d_ga2, H, H, 0, 0, n, gW2, H, s);
+    weight_grad(f, C.h1, H, H, H, f->d_ga2, H, H, 0, 0, n, gW2, H, gb2, s);
     // ga1 = (ga2 W2^T) * leaky'(h1): B(k=j2, n=j1) = W2[j1][j2] = W2t[j2][j1]
     a.A = f->d_ga2;
     a.lda = H;
@@ -861,8 +878,7 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     a.Cb = f->d_ga1;
     a.ref = C.h1;
     gemm<1, 1, 1>(a, 1, s);
-    bias_grad(f, f->d_ga1, H, H, 0, 0, n, gb1, s);
-    weight_grad(f, C.xa, KA, KA, L.dA, f->d_ga1, H, H, 0, 0, n, gW1, H, s, KLO);
+    weight_grad(f, C.xa, KA, KA, L.dA, f->d_ga1, H, H, 0, 0, n, gW1, H, gb1, s, KLO);
     // gx = ga1 W1^T: B(k=j, n=i) = W1[i][j] = W1t[j][i]
     GemmArgs b{};
     b.A = f->d_ga1;
@@ -953,10 +969,8 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
   f->cap = cap;
   // caches: xa, h1, h2, o, lin per layer
   size_t per_layer = sizeof(bf16) * (size_t)cap * (KA + 2 * H) + sizeof(float) * (size_t)cap * (dBmax * NOP + d);
-  const int64_t Zmax = (cap + SPLITK_CHUNK - 1) / SPLITK_CHUNK;
-  const int64_t Zcs = (cap + CS_ROWS - 1) / CS_ROWS;
-  f->part_cap = std::max((size_t)Zmax * (size_t)std::max<int64_t>((int64_t)H * dBmax * NOP, (int64_t)H * H),
-                         (size_t)Zcs * (size_t)std::max<int64_t>(dBmax * NOP, H));
+  f->part_cap = (size_t)std::max({splitk(cap, H, (int)(dBmax * NOP)) * (H + 1) * dBmax * NOP,
+                                   splitk(cap, H, H) * (H + 1) * H, splitk(cap, KA, H) * (KA + 1) * H});
   if (hipMalloc(&f->d_p, sizeof(float) * off) != hipSuccess || hipMalloc(&f->d_g, sizeof(float) * off) != hipSuccess ||
       hipMalloc(&f->d_m1, sizeof(float) * off) != hipSuccess || hipMalloc(&f->d_m2, sizeof(float) * off) != hipSuccess ||
       hipMalloc(&f->d_w16, sizeof(bf16) * w16) != hipSuccess || hipMalloc(&f->d_b3p, sizeof(float) * b3) != hipSuccess ||

@@ -236,18 +236,18 @@ __global__ void k_online_weights(const double* __restrict__ f, const double* __r
 
 // relative variance per event of a batch of sample weights r:
 // n sum r^2 / (sum r)^2 - 1
-__global__ void k_batch_relvar(const float* __restrict__ r, const float* __restrict__ r2, int64_t n,
-                               float* __restrict__ out) {
-  __shared__ double s1[256], s2[256];
+__global__ void __launch_bounds__(1024) k_batch_relvar(const float* __restrict__ r, const float* __restrict__ r2,
+                                                       int64_t n, float* __restrict__ out) {
+  __shared__ double s1[1024], s2[1024];
   double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
     a += r[i];
     b += r2[i];
   }
   s1[threadIdx.x] = a;
   s2[threadIdx.x] = b;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = 512; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) {
       s1[threadIdx.x] += s1[threadIdx.x + st];
       s2[threadIdx.x] += s2[threadIdx.x + st];
@@ -931,7 +931,7 @@ mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_onlin
     p->L.integrand(p->dc, p->d_sx, n, p->d_sw, nblk, s);
     hipLaunchKernelGGL(k_online_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->d_sw, p->d_sjac,
                        p->d_slq, o->flow_mix, n, o->loss == MF_FLOW_LOSS_VARIANCE ? 1 : 0, wt, rw, r2);
-    hipLaunchKernelGGL(k_batch_relvar, dim3(1), dim3(256), 0, s, rw, r2, n, d_loss + 2 * t);
+    hipLaunchKernelGGL(k_batch_relvar, dim3(1), dim3(1024), 0, s, rw, r2, n, d_loss + 2 * t);
     const double lr =
         o->lr_final + 0.5 * (o->lr - o->lr_final) * (1.0 + std::cos(M_PI * (double)t / (double)o->steps));
     st = mf::flow_step(flow, p->d_sy, n, wt, n, d_loss + 2 * t + 1, lr, s);
