@@ -69,11 +69,14 @@ def _eff(stats: dict) -> dict:
 def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_000) -> dict:
     """g g -> t t~ g g (Delta R > 0.4): wall time from process creation to a
     relative error of 1e-3, for plain VEGAS in FP64, plain VEGAS with FP32
-    amplitudes, and FP32 amplitudes with the learned proposal (VEGAS warm-up
-    5 x 1e6, on-policy variance training of the flow, then the flow mixed
-    with 20% uniform points on the frozen grid); plus the per-event relative
-    variance and the unweighting efficiency of each proposal on a fresh
-    sample of eval_events with the final grid."""
+    amplitudes, and FP32 amplitudes with the learned proposal: VEGAS warm-up
+    5 x 1e6, on-policy variance training of the flow (65536 points per step,
+    sampled from the flow mixed with 20% uniform points on the frozen grid),
+    whose batches are themselves estimates of the integral (pooled per 50
+    steps and combined by inverse variance, stopping at 1e-3), then, if
+    needed, iterations of the trained proposal combined with that estimate.
+    Also the per-event relative variance and the unweighting efficiency of
+    each proposal on a fresh sample of eval_events with the final grid."""
     import torch
 
     import paper_2105_10529_amd as mf
@@ -104,11 +107,16 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
     f = mf.Flow(p.ndim, max_batch=65536)
-    steps, mix = 300, 0.2
-    rel = p.train_flow_online(f, steps, batch=65536, lr=5e-3, loss="variance", flow_mix=mix)
+    steps, mix, group = 300, 0.2, 50
+    rel, est = p.train_flow_online(f, steps, batch=65536, lr=5e-3, loss="variance", flow_mix=mix,
+                                   group_steps=group, target_rel_err=1e-3, with_estimate=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0 - t_warm
-    r = p.integrate(100, n_iter_events, target_rel_err=1e-3, adapt=False, flow=f, flow_mix=mix, iter_offset=1 << 24)
+    if est.time_to_target >= 0.0:
+        r = est
+    else:
+        r = p.integrate(100, n_iter_events, target_rel_err=1e-3, adapt=False, flow=f, flow_mix=mix,
+                        iter_offset=1 << 24, prior=est)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     wf, _ = p.weights(1 << 30, eval_events, flow=f, flow_mix=mix)
@@ -118,9 +126,12 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
     sv = mf.weight_stats(wv)
     del wv
     res["fp32_flow"] = {"time_to_1e-3_s": t, "time_excluding_training_s": t - t_train, "warmup_s": t_warm,
-                        "training_s": t_train, "training_steps": steps, "training_batch": 65536,
-                        "iterations": r.n_iter_done, "events": r.n_events_total, "integral_pb": r.integral,
-                        "error_pb": r.error, "events_per_s": r.n_events_total / r.seconds,
+                        "training_s": t_train, "training_steps_done": int(np.count_nonzero(rel)),
+                        "training_batch": 65536, "training_estimate_pb": [est.integral, est.error],
+                        "training_events": est.n_events_total,
+                        "iterations_after_training": r.n_iter_done if r is not est else 0,
+                        "events_after_training": r.n_events_total if r is not est else 0,
+                        "integral_pb": r.integral, "error_pb": r.error,
                         "batch_relative_variance_first_last": [float(np.mean(rel[:5])), float(np.mean(rel[-10:]))],
                         "relative_variance_per_event": sf["relvar"],
                         "relative_variance_per_event_vegas_same_grid": sv["relvar"],

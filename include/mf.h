@@ -129,7 +129,8 @@ mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w
  * before returning. */
 mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins, double alpha, void* stream);
 
-struct mf_flow; /* learned proposal, mf_flow.h */
+struct mf_flow;     /* learned proposal, mf_flow.h */
+struct mf_result_s; /* mf_result, below */
 
 typedef struct {
   int32_t n_iter;                 /* iterations, >= 1 */
@@ -146,9 +147,13 @@ typedef struct {
                                      0), see mf_weights */
   double flow_mix;                /* with a flow: the fraction a of uniform
                                      points in the proposal, in [0,1) */
+  const struct mf_result_s* prior; /* NULL, or an earlier estimate (integral,
+                                     error) that enters the inverse-variance
+                                     combination and the target test as one
+                                     more iteration */
 } mf_integrate_opts;
 
-typedef struct {
+typedef struct mf_result_s {
   double integral;          /* inverse-variance weighted mean (pb) */
   double error;             /* its standard error */
   double chi2_dof;          /* chi^2 per degree of freedom of the iterations */

@@ -152,6 +152,10 @@ typedef struct {
   double flow_mix;       /* fraction a of uniform points in the sampling mixture, [0,1) */
   uint64_t iter_offset;  /* Philox iteration word of the first step's batch */
   void* stream;
+  int32_t group_steps;   /* steps pooled into one estimate of the integral
+                            (0: all steps) */
+  double target_rel_err; /* stop once the combined estimate reaches this
+                            relative error (0: run all steps) */
 } mf_flow_online_opts;
 
 /* On-policy training on the integrand itself: each step draws a batch from
@@ -159,11 +163,22 @@ typedef struct {
  * word iter_offset + step, as mf_weights), evaluates the integrand on the
  * frozen grid of the process, and takes a step on the gradient of
  * int p^2 / q_m (variance: per-point weights r^2 q/q_m with r = f J / q_m)
- * or of the forward KL (weights r q/q_m), followed by Adam.
+ * or of the forward KL (weights r q/q_m), followed by Adam.  The sample
+ * weights r of every batch are unbiased estimates of the integral; the
+ * batches of each group of group_steps steps are pooled into one estimate
+ * and the groups are combined by inverse variance (as VEGAS combines its
+ * iterations), which can stop the training at target_rel_err.
  *   loss_per_step: host [steps], the relative variance per event of each
- *   batch's weights r (n sum r^2 / (sum r)^2 - 1), or NULL.
+ *                  batch's weights (n sum r^2 / (sum r)^2 - 1), 0 after an
+ *                  early stop, or NULL.
+ *   est:           host, receives the combined estimate (integral, error,
+ *                  chi2_dof, n_iter_done = groups, n_events_total, seconds,
+ *                  time_to_target; group estimates into iter_integral /
+ *                  iter_error when those are given, with room for
+ *                  ceil(steps / group_steps) values), or NULL.
  * Blocks until done. */
-mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_online_opts* o, double* loss_per_step);
+mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_online_opts* o, double* loss_per_step,
+                               mf_result* est);
 
 #ifdef __cplusplus
 }

@@ -63,6 +63,7 @@ class _IntegrateOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("flow", ctypes.c_void_p),
         ("flow_mix", ctypes.c_double),
+        ("prior", ctypes.c_void_p),
     ]
 
 
@@ -97,6 +98,8 @@ class _FlowOnlineOpts(ctypes.Structure):
         ("flow_mix", ctypes.c_double),
         ("iter_offset", ctypes.c_uint64),
         ("stream", ctypes.c_void_p),
+        ("group_steps", ctypes.c_int32),
+        ("target_rel_err", ctypes.c_double),
     ]
 
 
@@ -180,7 +183,7 @@ def lib():
         L.mf_flow_adam_step.restype = i32
         L.mf_flow_train.argtypes = [P, P, P, i64, ctypes.POINTER(_FlowTrainOpts), P]
         L.mf_flow_train.restype = i32
-        L.mf_flow_train_online.argtypes = [P, P, ctypes.POINTER(_FlowOnlineOpts), P]
+        L.mf_flow_train_online.argtypes = [P, P, ctypes.POINTER(_FlowOnlineOpts), P, ctypes.POINTER(_Result)]
         L.mf_flow_train_online.restype = i32
         _lib = L
     return _lib
@@ -304,11 +307,18 @@ class Process:
 
     def integrate(self, n_iter: int, n_events: int, target_rel_err: float = 0.0, warmup: int = 0, adapt: bool = True,
                   iter_offset: int = 0, edges_in=None, edges_out=None, stream=None,
-                  flow: "Flow | None" = None, flow_mix: float = 0.0) -> IntegrationResult:
-        """VEGAS integration entirely on the device -- mf_integrate (flow: learned proposal, frozen grid)."""
+                  flow: "Flow | None" = None, flow_mix: float = 0.0,
+                  prior: "IntegrationResult | None" = None) -> IntegrationResult:
+        """VEGAS integration entirely on the device -- mf_integrate (flow: learned proposal, frozen grid;
+        prior: an earlier estimate combined with the new iterations)."""
         o = _IntegrateOpts()
         o.flow = flow._h.value if flow is not None else None
         o.flow_mix = flow_mix
+        pr = None
+        if prior is not None:
+            pr = _Result()
+            pr.integral, pr.error = prior.integral, prior.error
+            o.prior = ctypes.addressof(pr)
         o.n_iter, o.n_events, o.target_rel_err = n_iter, n_events, target_rel_err
         o.warmup_iters_discarded, o.adapt, o.iter_offset = warmup, int(adapt), iter_offset
         o.edges_in = _dev_ptr(edges_in) if edges_in is not None else None
@@ -338,14 +348,27 @@ class Process:
 
     def train_flow_online(self, flow: "Flow", steps: int, batch: int = 16384, lr: float = 1e-3,
                           lr_final: float = 1e-5, loss: str = "variance", flow_mix: float = 0.1,
-                          iter_offset: int = 1 << 20, stream=None) -> np.ndarray:
+                          iter_offset: int = 1 << 20, stream=None, group_steps: int = 0, target_rel_err: float = 0.0,
+                          with_estimate: bool = False):
         """On-policy training of the flow on this integrand -- mf_flow_train_online.
 
-        Returns the relative variance per event of each step's batch."""
-        o = _FlowOnlineOpts(steps, batch, lr, lr_final, Flow.LOSSES[loss], flow_mix, iter_offset, _stream_ptr(stream))
+        Returns the relative variance per event of each step's batch, and with
+        with_estimate also the combined estimate of the integral from the
+        training batches (IntegrationResult)."""
+        o = _FlowOnlineOpts(steps, batch, lr, lr_final, Flow.LOSSES[loss], flow_mix, iter_offset, _stream_ptr(stream),
+                            group_steps, target_rel_err)
         out = np.zeros(steps)
-        _check(lib().mf_flow_train_online(self._h, flow._h, ctypes.byref(o), out.ctypes.data))
-        return out
+        r = _Result()
+        ng = -(-steps // (group_steps if group_steps > 0 else steps))
+        Ii, Ie = np.zeros(ng), np.zeros(ng)
+        r.iter_integral, r.iter_error = Ii.ctypes.data, Ie.ctypes.data
+        _check(lib().mf_flow_train_online(self._h, flow._h, ctypes.byref(o), out.ctypes.data, ctypes.byref(r)))
+        if not with_estimate:
+            return out
+        k = r.n_iter_done
+        est = IntegrationResult(r.integral, r.error, r.chi2_dof, k, r.n_events_total, r.n_nonzero, r.n_nonfinite,
+                                r.seconds, r.time_to_target, r.kernel_seconds, Ii[:k].copy(), Ie[:k].copy())
+        return out, est
 
     def grad(self, n_events: int, iter_offset: int = 0, edges_in=None, stream=None):
         """(values[10], errors[10]): sigma, d sigma/d m_t, d sigma/d theta_0..7 -- mf_grad."""

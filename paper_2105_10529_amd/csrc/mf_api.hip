@@ -234,10 +234,10 @@ __global__ void k_online_weights(const double* __restrict__ f, const double* __r
   r2[e] = (float)(r * r);
 }
 
-// relative variance per event of a batch of sample weights r:
-// n sum r^2 / (sum r)^2 - 1
+// relative variance per event of a batch of sample weights r,
+// n sum r^2 / (sum r)^2 - 1, and the sums (sum r, sum r^2) in FP64
 __global__ void __launch_bounds__(1024) k_batch_relvar(const float* __restrict__ r, const float* __restrict__ r2,
-                                                       int64_t n, float* __restrict__ out) {
+                                                       int64_t n, float* __restrict__ out, double* __restrict__ sums) {
   __shared__ double s1[1024], s2[1024];
   double a = 0.0, b = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 1024) {
@@ -254,7 +254,11 @@ __global__ void __launch_bounds__(1024) k_batch_relvar(const float* __restrict__
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = (float)((double)n * s2[0] / (s1[0] * s1[0]) - 1.0);
+  if (threadIdx.x == 0) {
+    out[0] = (float)((double)n * s2[0] / (s1[0] * s1[0]) - 1.0);
+    sums[0] = s1[0];
+    sums[1] = s2[0];
+  }
 }
 
 // Accumulation kernel: weights w*J into the same per-block partials as the
@@ -788,6 +792,10 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
     }
   } guard{ev};
   double sw = 0.0, swi = 0.0;
+  if (o->prior && o->prior->error > 0.0) {
+    sw = 1.0 / (o->prior->error * o->prior->error);
+    swi = o->prior->integral * sw;
+  }
   for (int it = 0; it < o->n_iter; ++it) {
     const uint64_t iter = o->iter_offset + (uint64_t)it;
     HIP_TRY(hipEventRecord(ev[2 * it], s));
@@ -844,6 +852,12 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   // combination of the iteration estimates (inverse-variance weights)
   double W = 0.0, WI = 0.0, nz = 0.0, bad = 0.0;
   int k = 0;
+  const bool has_prior = o->prior && o->prior->error > 0.0;
+  if (has_prior) {
+    W = 1.0 / (o->prior->error * o->prior->error);
+    WI = o->prior->integral * W;
+    ++k;
+  }
   for (int it = 0; it < done; ++it) {
     const double* q = rec.data() + (size_t)REC * it;
     nz += q[4];
@@ -857,6 +871,7 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   }
   double mean = W > 0.0 ? WI / W : 0.0;
   double chi2 = 0.0;
+  if (has_prior) chi2 += (o->prior->integral - mean) * (o->prior->integral - mean) / (o->prior->error * o->prior->error);
   for (int it = o->warmup_iters_discarded; it < done; ++it) {
     const double* q = rec.data() + (size_t)REC * it;
     if (q[1] > 0.0) chi2 += (q[0] - mean) * (q[0] - mean) / (q[1] * q[1]);
@@ -902,8 +917,39 @@ mf_status mf_weights(mf_process* p, mf_flow* flow, double flow_mix, uint64_t ite
   return check_stream_launch("k_weight");
 }
 
-mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_online_opts* o, double* loss_per_step) {
+namespace {
+// Inverse-variance combination of iteration estimates (integral, error),
+// optionally starting from a prior estimate; chi^2 per degree of freedom.
+struct Combo {
+  double W = 0.0, WI = 0.0;
+  std::vector<double> I, E;
+  void add(double i, double e) {
+    I.push_back(i);
+    E.push_back(e);
+    if (e > 0.0) {
+      W += 1.0 / (e * e);
+      WI += i / (e * e);
+    }
+  }
+  double mean() const { return W > 0.0 ? WI / W : 0.0; }
+  double error() const { return W > 0.0 ? std::sqrt(1.0 / W) : 0.0; }
+  double chi2_dof() const {
+    double m = mean(), c = 0.0;
+    int k = 0;
+    for (size_t j = 0; j < I.size(); ++j)
+      if (E[j] > 0.0) {
+        c += (I[j] - m) * (I[j] - m) / (E[j] * E[j]);
+        ++k;
+      }
+    return k > 1 ? c / (k - 1) : 0.0;
+  }
+};
+}  // namespace
+
+mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_online_opts* o, double* loss_per_step,
+                               mf_result* est) {
   mf::clear_error();
+  auto t0 = std::chrono::steady_clock::now();
   if (!p || !flow || !o) return fail(MF_EINVAL, "NULL argument");
   if (mf_flow_ndim(flow) != p->ndim) return fail(MF_EINVAL, "flow dimension differs from the integrand's");
   if (o->steps < 1) return fail(MF_EINVAL, "steps must be >= 1");
@@ -911,37 +957,90 @@ mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_onlin
   if (!(o->flow_mix >= 0.0 && o->flow_mix < 1.0)) return fail(MF_EINVAL, "flow_mix must be in [0,1)");
   if (!(o->lr > 0.0) || !(o->lr_final >= 0.0)) return fail(MF_EINVAL, "invalid learning rates");
   if (o->loss != MF_FLOW_LOSS_KL && o->loss != MF_FLOW_LOSS_VARIANCE) return fail(MF_EINVAL, "unknown loss %d", o->loss);
+  if (o->group_steps < 0 || !(o->target_rel_err >= 0.0)) return fail(MF_EINVAL, "invalid grouping or target");
   hipStream_t s = (hipStream_t)o->stream;
   const int64_t n = o->batch;
+  const int group = o->group_steps > 0 ? o->group_steps : o->steps;
   mf_status st = ensure_stage(p, n, s);
   if (st != MF_OK) return st;
   float* d_loss = nullptr;
+  double* d_sums = nullptr;
   HIP_TRY(hipMalloc(&d_loss, sizeof(float) * 2 * o->steps));
+  if (hipMalloc(&d_sums, sizeof(double) * 2 * o->steps) != hipSuccess) {
+    (void)hipFree(d_loss);
+    return fail(MF_ENOMEM, "training statistics");
+  }
   struct Free {
     float* q;
-    ~Free() { (void)hipFree(q); }
-  } guard{d_loss};
+    double* r;
+    ~Free() {
+      (void)hipFree(q);
+      (void)hipFree(r);
+    }
+  } guard{d_loss, d_sums};
   const int nblk = blocks_for(n);
   float* wt = p->d_sw32;
   float* rw = p->d_sw32 + n;
   float* r2 = p->d_sw32 + 2 * n;
+  Combo combo;
+  std::vector<double> hs(2 * (size_t)o->steps);
+  double time_to_target = -1.0;
+  int done = 0, g0 = 0;
   for (int t = 0; t < o->steps; ++t) {
     st = stage_sample(p, flow, o->flow_mix, o->iter_offset + (uint64_t)t, n, nullptr, s);
     if (st != MF_OK) return st;
     p->L.integrand(p->dc, p->d_sx, n, p->d_sw, nblk, s);
     hipLaunchKernelGGL(k_online_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->d_sw, p->d_sjac,
                        p->d_slq, o->flow_mix, n, o->loss == MF_FLOW_LOSS_VARIANCE ? 1 : 0, wt, rw, r2);
-    hipLaunchKernelGGL(k_batch_relvar, dim3(1), dim3(1024), 0, s, rw, r2, n, d_loss + 2 * t);
+    hipLaunchKernelGGL(k_batch_relvar, dim3(1), dim3(1024), 0, s, rw, r2, n, d_loss + 2 * t, d_sums + 2 * t);
     const double lr =
         o->lr_final + 0.5 * (o->lr - o->lr_final) * (1.0 + std::cos(M_PI * (double)t / (double)o->steps));
     st = mf::flow_step(flow, p->d_sy, n, wt, n, d_loss + 2 * t + 1, lr, s);
     if (st != MF_OK) return st;
+    done = t + 1;
+    if (done - g0 == group || done == o->steps) {
+      // the group's estimate: all its batches pooled (each batch is an unbiased
+      // sample of the integral from the flow as it was at that step)
+      HIP_TRY(hipMemcpyAsync(hs.data() + 2 * (size_t)g0, d_sums + 2 * g0, sizeof(double) * 2 * (done - g0),
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double S1 = 0.0, S2 = 0.0;
+      for (int k = g0; k < done; ++k) {
+        S1 += hs[2 * (size_t)k];
+        S2 += hs[2 * (size_t)k + 1];
+      }
+      const double N = (double)(done - g0) * (double)n;
+      const double I = S1 / N, var = (S2 / N - I * I) / (N - 1.0);
+      combo.add(I, std::sqrt(var > 0.0 ? var : 0.0));
+      g0 = done;
+      if (o->target_rel_err > 0.0 && combo.mean() != 0.0 &&
+          combo.error() / std::fabs(combo.mean()) <= o->target_rel_err) {
+        time_to_target = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        break;
+      }
+    }
   }
   std::vector<float> hl(2 * (size_t)o->steps);
-  HIP_TRY(hipMemcpyAsync(hl.data(), d_loss, sizeof(float) * 2 * o->steps, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hl.data(), d_loss, sizeof(float) * 2 * done, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (loss_per_step)
-    for (int t = 0; t < o->steps; ++t) loss_per_step[t] = hl[2 * (size_t)t];
+    for (int t = 0; t < o->steps; ++t) loss_per_step[t] = t < done ? hl[2 * (size_t)t] : 0.0;
+  if (est) {
+    est->integral = combo.mean();
+    est->error = combo.error();
+    est->chi2_dof = combo.chi2_dof();
+    est->n_iter_done = (int32_t)combo.I.size();
+    est->n_events_total = (int64_t)done * n;
+    est->n_nonzero = 0;
+    est->n_nonfinite = 0;
+    est->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    est->time_to_target = time_to_target;
+    est->kernel_seconds = 0.0;
+    for (size_t j = 0; j < combo.I.size(); ++j) {
+      if (est->iter_integral) est->iter_integral[j] = combo.I[j];
+      if (est->iter_error) est->iter_error[j] = combo.E[j];
+    }
+  }
   return MF_OK;
 }
 

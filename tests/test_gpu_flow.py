@@ -336,3 +336,27 @@ def test_variance_trained_flow_beats_vegas_on_gg_ttg():
     wf, _ = p.weights(3000, 2_000_000, flow=f)
     sv, sf = mf.weight_stats(wv), mf.weight_stats(wf)
     assert sf["relvar"] < sv["relvar"], (sf, sv)
+
+
+def test_training_batches_estimate_the_integral():
+    """The on-policy training batches are unbiased samples: their grouped,
+    inverse-variance combined estimate agrees with VEGAS, and the flow's later
+    iterations combined with it (as a prior) give a smaller error than either."""
+    p = mf.Process(mf.Config(process="gg>ttxg"))
+    p.integrate(5, 1_000_000, adapt=True)
+    f = mf.Flow(7, max_batch=16384)
+    _, est = p.train_flow_online(f, 120, batch=16384, lr=3e-3, loss="variance", flow_mix=0.1, group_steps=40,
+                                 with_estimate=True)
+    assert est.n_iter_done == 3 and est.n_events_total == 120 * 16384
+    assert np.allclose(1.0 / est.error ** 2, np.sum(1.0 / est.iter_error ** 2))
+    rv = p.integrate(4, 5_000_000, adapt=False, iter_offset=2000)
+    assert abs(est.integral - rv.integral) < 4.0 * np.hypot(est.error, rv.error), (est, rv)
+    rf = p.integrate(1, 2_000_000, adapt=False, iter_offset=3000, flow=f, flow_mix=0.1)
+    rc = p.integrate(1, 2_000_000, adapt=False, iter_offset=3000, flow=f, flow_mix=0.1, prior=est)
+    assert abs(1.0 / rc.error ** 2 - (1.0 / rf.error ** 2 + 1.0 / est.error ** 2)) < 1e-9 / rc.error ** 2
+    assert rc.error < min(rf.error, est.error)
+    # early stop at a target the training reaches
+    f2 = mf.Flow(7, max_batch=16384)
+    _, e2 = p.train_flow_online(f2, 400, batch=16384, lr=3e-3, flow_mix=0.1, group_steps=20, target_rel_err=3e-3,
+                                with_estimate=True)
+    assert e2.time_to_target > 0 and e2.error / e2.integral <= 3e-3 and e2.n_events_total < 400 * 16384
