@@ -139,6 +139,55 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
     return res
 
 
+BF16_MFMA_PEAK = 2.5e15  # MI355X dense BF16 matrix-core FLOP/s
+
+
+def flow_flops_per_event(masks) -> int:
+    """Algorithmic flops of one pass of the coupling flow per event: the three
+    dense layers of every coupling layer (2 flops per multiply-add, unpadded
+    widths); the PQ transform is not counted."""
+    h, no = 256, 65
+    tot = 0
+    for m in masks:
+        da, db = int((~m).sum()), int(m.sum())
+        tot += 2 * (da * h + h * h + h * db * no)
+    return tot
+
+
+def flow_roofline(n: int = 10_000_000) -> dict:
+    """The flow's sampling direction (six coupling-layer launches) on n points
+    of the 10-dimensional g g -> t t~ g g space with seeded random parameters,
+    timed with HIP events on the launch stream; achieved BF16 matrix-core
+    FLOP/s from the algorithmic count against the dense BF16 peak."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+    import seeded_inputs as si
+
+    f = mf.Flow(10, max_batch=64)
+    mk = f.masks()
+    shapes = [(int((~m).sum()), 256, int(m.sum()) * 65) for m in mk]
+    f.set_params(mf.Flow.flatten(si.flow_params(shapes, seed=7, scale_out=0.3)))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(si.BASE_SEED)
+    z = torch.rand((10, n), dtype=torch.float32, device="cuda", generator=g)
+    f.inverse(z)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    ev0.record(stream)
+    for _ in range(reps):
+        f.inverse(z, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    sec = ev0.elapsed_time(ev1) * 1e-3 / reps
+    fpe = flow_flops_per_event(mk)
+    return {"events": n, "ms_per_pass": 1e3 * sec, "ms_per_layer_launch": 1e3 * sec / len(mk),
+            "events_per_s": n / sec, "flops_per_event": fpe, "achieved_tflops": fpe * n / sec / 1e12,
+            "peak_tflops": BF16_MFMA_PEAK / 1e12, "frac": fpe * n / sec / BF16_MFMA_PEAK,
+            "kernel": "k_coupling<true,false> (sampling direction, 64 events per workgroup)"}
+
+
 def secondary(seed_events: int) -> dict:
     """Bounded extra measurements on the same GPU (reported beside the main line).
 
@@ -169,6 +218,7 @@ def secondary(seed_events: int) -> dict:
             "events_to_1e-3": tt.n_events_total, "integral_at_1e-3_pb": tt.integral, "error_at_1e-3_pb": tt.error,
         }
     out["ttgg_flow_vs_vegas"] = flow_comparison()
+    out["flow_roofline"] = flow_roofline()
     grads = {}
     for mt in (171.0, 173.0, 175.0):
         p = mf.Process(mf.Config(process="gg>ttxg", m_t=mt))
@@ -196,6 +246,8 @@ def main() -> int:
     ap.add_argument("--workload", choices=("ttg", "ttgg"), default="ttg",
                     help="ttg: g g -> t t~ g FP64 (the reported workload); ttgg: g g -> t t~ g g with FP32 "
                          "amplitudes (profiling runs)")
+    ap.add_argument("--flow-only", action="store_true",
+                    help="only run the g g -> t t~ g g learned-proposal comparison and the flow roofline (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (to calibrate HBM counters) and exit")
     args = ap.parse_args()
@@ -217,6 +269,9 @@ def main() -> int:
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n * 8}), flush=True)
+        return 0
+    if args.flow_only:
+        print(json.dumps({"ttgg_flow_vs_vegas": flow_comparison(), "flow_roofline": flow_roofline()}), flush=True)
         return 0
     if args.workload == "ttgg":
         p = mf.Process(mf.Config(process="gg>ttxgg", precision="fp32", dr_min=0.4))
