@@ -529,12 +529,13 @@ def make_autograd_integrand(process: "Process"):
                 raise ValueError("theta differs from the process configuration")
             w, dw = process.integrand_grad(u.detach())
             ctx.save_for_backward(dw)
+            ctx.devices = (m_t.device, theta.device)
             return w
 
         @staticmethod
         def backward(ctx, g):
             (dw,) = ctx.saved_tensors
             gd = dw @ g.to(dw.dtype)  # [9]
-            return None, gd[0].to(torch.float64), gd[1:].to(torch.float64)
+            return None, gd[0].to(ctx.devices[0], torch.float64), gd[1:].to(ctx.devices[1], torch.float64)
 
     return MfIntegrand
