@@ -46,6 +46,7 @@ constexpr float SLOPE = 0.01f;
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct LayerDev {
@@ -133,6 +134,28 @@ __device__ __forceinline__ Bin find_bin(const float* W, const float* V, float t,
   return r;
 }
 
+// Epilogue of a transposed dense layer: acc[jt][mt][i] is feature
+// 64 wave + 16 jt + 4 quad + i of event 16 mt + row; adds the bias, applies
+// the LeakyReLU, rounds to BF16 and stores the four features with one 8-byte
+// write into the permuted [T][H] activation tile.
+__device__ __forceinline__ void store_features(bf16* h, const f32x4 (&acc)[4][4], const float* __restrict__ bias,
+                                               int wave, int row, int quad) {
+#pragma unroll
+  for (int jt = 0; jt < 4; ++jt) {
+    const int f0 = 64 * wave + 16 * jt + 4 * quad;
+    float bb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bb[i] = bias[f0 + i];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      bf16x4 v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = (bf16)leaky(acc[jt][mt][i] + bb[i]);
+      *reinterpret_cast<bf16x4*>(h + hs(16 * mt + row, f0)) = v;
+    }
+  }
+}
+
 // --------------------------------------------------------- coupling layer
 // One layer for events [64 blockIdx.x, +64): y is [d][ld] (n <= ld events
 // used) and is transformed in place (the kept coordinates are only read).
@@ -176,59 +199,50 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
   }
   __syncthreads();
 
-  // dense layer 1: [T x KA] . [KA x H]; wave w owns hidden columns [64w, 64w+64)
+  // Dense layers 1 and 2 are computed transposed, D[feature][event] =
+  // W^T X^T: the weight rows are the A fragments (16-byte loads from the
+  // [out][in] copies), the activations in LDS the B fragments, and each lane
+  // ends with four consecutive features of one event, stored as one 8-byte
+  // LDS write after bias and activation.  Wave w owns features [64w, 64w+64).
   {
-    bf16x8 a[4];
+    f32x4 acc[4][4];
+    bf16x8 a[4], b[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = 16 * r + row;
-      a[r] = *reinterpret_cast<const bf16x8*>(xa + m * KA + ((quad ^ (m & 3)) << 3));
+    for (int jt = 0; jt < 4; ++jt)
+      a[jt] = *reinterpret_cast<const bf16x8*>(L.W1t + (64 * wave + 16 * jt + row) * KA + 8 * quad);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      const int m = 16 * mt + row;
+      b[mt] = *reinterpret_cast<const bf16x8*>(xa + m * KA + ((quad ^ (m & 3)) << 3));
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int col = 64 * wave + 16 * c + row;
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(L.W1t + col * KA + 8 * quad);
-      const float bias = L.b1[64 * wave + 16 * c + row];
+    for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        acc = mfma16(a[r], b, acc);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) h1[hs(16 * r + 4 * quad + i, col)] = (bf16)leaky(acc[i] + bias);
-      }
-    }
+      for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = mfma16(a[jt], b[mt], f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+    store_features(h1, acc, L.b1, wave, row, quad);
   }
   __syncthreads();
-
-  // dense layer 2: [T x H] . [H x H]
   {
     f32x4 acc[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const bf16* W2 = L.W2t + (64 * wave + row) * H + 8 * quad;
+#pragma unroll
     for (int ks = 0; ks < H / 32; ++ks) {
       bf16x8 a[4], b[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        a[r] = *reinterpret_cast<const bf16x8*>(h1 + hs(16 * r + row, 32 * ks + 8 * quad));
+      for (int jt = 0; jt < 4; ++jt) a[jt] = *reinterpret_cast<const bf16x8*>(W2 + 16 * jt * H + 32 * ks);
 #pragma unroll
-      for (int c = 0; c < 4; ++c)
-        b[c] = *reinterpret_cast<const bf16x8*>(L.W2t + (64 * wave + 16 * c + row) * H + 32 * ks + 8 * quad);
+      for (int mt = 0; mt < 4; ++mt)
+        b[mt] = *reinterpret_cast<const bf16x8*>(h1 + hs(16 * mt + row, 32 * ks + 8 * quad));
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = mfma16(a[r], b[c], acc[r][c]);
+        for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = mfma16(a[jt], b[mt], acc[jt][mt]);
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int col = 64 * wave + 16 * c + row;
-      const float bias = L.b2[col];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) h2[hs(16 * r + 4 * quad + i, col)] = (bf16)leaky(acc[r][c][i] + bias);
-    }
+    store_features(h2, acc, L.b2, wave, row, quad);
   }
   __syncthreads();
   if (CACHE) {
@@ -244,34 +258,63 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
     __syncthreads();
   }
 
-  // dense layer 3 and the PQ transform, one transformed coordinate at a time
+  // The 65th logit of every transformed coordinate at once: one more MFMA
+  // tile per wave, D[coordinate][event] for the wave's 16 events, with the
+  // weight rows of the coordinates' last outputs as A fragments (rows past
+  // d_B are zero).  Kept in LDS after the logits of one coordinate.
+  float* last = out + T * LDO;  // [T][16]
+  {
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    const bool live = row < L.dB;
+    const bf16* wl = L.W3t + ((int64_t)(live ? row : 0) * NOP + 2 * KB) * H + 8 * quad;
+#pragma unroll
+    for (int ks = 0; ks < H / 32; ++ks) {
+      bf16x8 a = *reinterpret_cast<const bf16x8*>(wl + 32 * ks);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a[i] = live ? a[i] : (bf16)0.0f;
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(h2 + hs(16 * wave + row, 32 * ks + 8 * quad));
+      acc = mfma16(a, b, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) last[(16 * wave + row) * 16 + 4 * quad + i] = acc[i];
+  }
+  __syncthreads();
+
+  // dense layer 3 and the PQ transform, one transformed coordinate at a time:
+  // the 64 leading logits of a coordinate are four 16-column MFMA tiles, one
+  // per wave over all 64 events (each wave streams only its own weight
+  // columns).
   float lq = 0.0f;
   for (int c = 0; c < L.dB; ++c) {
     {
-      f32x4 acc[5];
+      f32x4 acc[4];
 #pragma unroll
-      for (int t = 0; t < 5; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      const bf16* W3 = L.W3t + (int64_t)c * NOP * H;
+      for (int r = 0; r < 4; ++r) acc[r] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      // all eight weight fragments of this wave's columns are requested first
+      const bf16* W3 = L.W3t + ((int64_t)c * NOP + 16 * wave + row) * H + 8 * quad;
+      bf16x8 bw[H / 32];
+#pragma unroll
+      for (int ks = 0; ks < H / 32; ++ks) bw[ks] = *reinterpret_cast<const bf16x8*>(W3 + 32 * ks);
+#pragma unroll
       for (int ks = 0; ks < H / 32; ++ks) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(h2 + hs(16 * wave + row, 32 * ks + 8 * quad));
 #pragma unroll
-        for (int t = 0; t < 5; ++t) {
-          const bf16x8 b = *reinterpret_cast<const bf16x8*>(W3 + (16 * t + row) * H + 32 * ks + 8 * quad);
-          acc[t] = mfma16(a, b, acc[t]);
+        for (int r = 0; r < 4; ++r) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(h2 + hs(16 * r + row, 32 * ks + 8 * quad));
+          acc[r] = mfma16(a, bw[ks], acc[r]);
         }
       }
+      const int col = 16 * wave + row;
+      const float bias = L.b3p[c * NOP + col];
 #pragma unroll
-      for (int t = 0; t < 5; ++t) {
-        const int col = 16 * t + row;
-        const float bias = L.b3p[c * NOP + col];
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[(16 * wave + 4 * quad + i) * LDO + col] = acc[t][i] + bias;
-      }
+        for (int i = 0; i < 4; ++i) out[(16 * r + 4 * quad + i) * LDO + col] = acc[r][i] + bias;
+      if (tid < T) out[tid * LDO + 2 * KB] = last[tid * 16 + c] + L.b3p[c * NOP + 2 * KB];
     }
     __syncthreads();
     if (CACHE) {
-      for (int idx = tid; idx < T * NOP; idx += 256) {
-        const int m = idx / NOP, col = idx % NOP;
+      for (int idx = tid; idx < T * NO; idx += 256) {
+        const int m = idx / NO, col = idx % NO;
         const int64_t e = e0 + m;
         if (e < n) C.o[(e * L.dB + c) * NOP + col] = out[m * LDO + col];
       }
