@@ -156,6 +156,101 @@ __device__ __forceinline__ void store_features(bf16* h, const f32x4 (&acc)[4][4]
   }
 }
 
+// The PQ transform of one coordinate with four lanes per event: lane part p
+// holds the bins [8p, 8p+8) and the vertices [8p, 8p+8] of the 2K+1 logits
+// o (in LDS); maxima, sums and the bin's owner are combined with shuffles
+// inside each aligned group of four lanes.  Same bin rule as find_bin: the
+// largest k >= 1 whose left edge (running width, or running area for the
+// sampling direction) is <= t, else 0.  Every lane of the group returns the
+// result (y or z) and the density.
+template <bool INVERSE>
+__device__ __forceinline__ void pq_quad(const float* o, float t, int p, int lane, float& res, float& pdf) {
+  constexpr int KP = KB / 4;
+  float w[KP], v[KP + 1];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) w[k] = o[KP * p + k];
+#pragma unroll
+  for (int k = 0; k <= KP; ++k) v[k] = o[KB + KP * p + k];
+  float mw = w[0];
+#pragma unroll
+  for (int k = 1; k < KP; ++k) mw = fmaxf(mw, w[k]);
+  mw = fmaxf(mw, __shfl_xor(mw, 1));
+  mw = fmaxf(mw, __shfl_xor(mw, 2));
+  float sw = 0.0f;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    w[k] = __expf(w[k] - mw);
+    sw += w[k];
+  }
+  sw += __shfl_xor(sw, 1);
+  sw += __shfl_xor(sw, 2);
+  const float isw = 1.0f / sw;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) w[k] *= isw;
+  float mv = v[0];
+#pragma unroll
+  for (int k = 1; k <= KP; ++k) mv = fmaxf(mv, v[k]);
+  mv = fmaxf(mv, __shfl_xor(mv, 1));
+  mv = fmaxf(mv, __shfl_xor(mv, 2));
+#pragma unroll
+  for (int k = 0; k <= KP; ++k) v[k] = __expf(v[k] - mv);
+  float nl = 0.0f;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) nl += 0.5f * (v[k] + v[k + 1]) * w[k];
+  nl += __shfl_xor(nl, 1);
+  nl += __shfl_xor(nl, 2);
+  const float inl = 1.0f / nl;
+#pragma unroll
+  for (int k = 0; k <= KP; ++k) v[k] *= inl;
+  // exclusive offsets of the running width and area at the part's first bin
+  float sp = 0.0f, ap = 0.0f;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    sp += w[k];
+    ap += 0.5f * (v[k] + v[k + 1]) * w[k];
+  }
+  const int base = lane & ~3;
+  const float s0 = __shfl(sp, base), s1 = __shfl(sp, base + 1), s2 = __shfl(sp, base + 2);
+  const float a0 = __shfl(ap, base), a1 = __shfl(ap, base + 1), a2 = __shfl(ap, base + 2);
+  float S = (p > 0 ? s0 : 0.0f) + (p > 1 ? s1 : 0.0f) + (p > 2 ? s2 : 0.0f);
+  float A = (p > 0 ? a0 : 0.0f) + (p > 1 ? a1 : 0.0f) + (p > 2 ? a2 : 0.0f);
+  int bl = -1;
+  float Sb = 0.0f, Ab = 0.0f, Wb = w[0], Vb = v[0], Vb1 = v[1];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int kg = KP * p + k;
+    const bool take = kg == 0 || (INVERSE ? A : S) <= t;
+    bl = take ? kg : bl;
+    Sb = take ? S : Sb;
+    Ab = take ? A : Ab;
+    Wb = take ? w[k] : Wb;
+    Vb = take ? v[k] : Vb;
+    Vb1 = take ? v[k + 1] : Vb1;
+    S += w[k];
+    A += 0.5f * (v[k] + v[k + 1]) * w[k];
+  }
+  int b = bl;
+  b = max(b, __shfl_xor(b, 1));
+  b = max(b, __shfl_xor(b, 2));
+  const float dV = Vb1 - Vb;
+  float r, q;
+  if (!INVERSE) {
+    const float al = fminf(fmaxf((t - Sb) / Wb, 0.0f), 1.0f);
+    r = Ab + Wb * (al * Vb + 0.5f * al * al * dV);
+    q = Vb + al * dV;
+  } else {
+    const float cc = (t - Ab) / Wb;
+    const float disc = fmaxf(Vb * Vb + 2.0f * dV * cc, 0.0f);
+    float al = 2.0f * cc / (Vb + sqrtf(disc));
+    al = fminf(fmaxf(al, 0.0f), 1.0f);
+    r = Sb + al * Wb;
+    q = Vb + al * dV;
+  }
+  const int owner = base + b / KP;
+  res = __shfl(r, owner);
+  pdf = __shfl(q, owner);
+}
+
 // --------------------------------------------------------- coupling layer
 // One layer for events [64 blockIdx.x, +64): y is [d][ld] (n <= ld events
 // used) and is transformed in place (the kept coordinates are only read).
@@ -319,36 +414,23 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
         if (e < n) C.o[(e * L.dB + c) * NOP + col] = out[m * LDO + col];
       }
     }
-    if (tid < T) {
-      const int64_t e = e0 + tid;
-      if (e < n) {
-        float W[KB], V[KB + 1];
-        pq_params(out + tid * LDO, W, V);
-        float* yp = y + (int64_t)L.b_idx[c] * ld + e;
-        const float t = *yp;
-        const Bin B = find_bin(W, V, t, INVERSE);
-        const float dV = B.Vb1 - B.Vb;
-        float res, pdf;
-        if (!INVERSE) {
-          const float al = fminf(fmaxf((t - B.S) / B.Wb, 0.0f), 1.0f);
-          res = B.A + B.Wb * (al * B.Vb + 0.5f * al * al * dV);
-          pdf = B.Vb + al * dV;
-        } else {
-          const float cc = (t - B.A) / B.Wb;
-          const float disc = fmaxf(B.Vb * B.Vb + 2.0f * dV * cc, 0.0f);
-          float al = 2.0f * cc / (B.Vb + sqrtf(disc));
-          al = fminf(fmaxf(al, 0.0f), 1.0f);
-          res = B.S + al * B.Wb;
-          pdf = B.Vb + al * dV;
-        }
+    {
+      const int m = tid >> 2, part = tid & 3;
+      const int64_t e = e0 + m;
+      const bool live = e < n;
+      float* yp = y + (int64_t)L.b_idx[c] * ld + (live ? e : e0);
+      const float t = live ? *yp : 0.5f;
+      float res, pdf;
+      pq_quad<INVERSE>(out + m * LDO, t, part, lane, res, pdf);
+      if (live && part == 0) {
         *yp = res;
         lq += __logf(pdf);
       }
     }
     __syncthreads();
   }
-  if (tid < T) {
-    const int64_t e = e0 + tid;
+  if ((tid & 3) == 0) {
+    const int64_t e = e0 + (tid >> 2);
     if (e < n) logq[e] = first ? lq : logq[e] + lq;
   }
 }
