@@ -66,15 +66,19 @@ def _eff(stats: dict) -> dict:
     return {"mean_over_max": stats["mean"] / stats["max"], "mean_over_q999": stats["mean"] / stats["quantile"]}
 
 
-def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_000) -> dict:
+def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_000, steps: int = 60,
+                    flow_iter_events: int = 4_000_000, vegas: bool = True) -> dict:
     """g g -> t t~ g g (Delta R > 0.4): wall time from process creation to a
     relative error of 1e-3, for plain VEGAS in FP64, plain VEGAS with FP32
     amplitudes, and FP32 amplitudes with the learned proposal: VEGAS warm-up
-    5 x 1e6, on-policy variance training of the flow (65536 points per step,
-    sampled from the flow mixed with 20% uniform points on the frozen grid),
-    whose batches are themselves estimates of the integral (pooled per 50
-    steps and combined by inverse variance, stopping at 1e-3), then, if
-    needed, iterations of the trained proposal combined with that estimate.
+    5 x 1e6, `steps` on-policy variance-training steps of the flow (65536
+    points per step, sampled from the flow mixed with 20% uniform points on
+    the frozen grid), whose batches are themselves estimates of the integral
+    (pooled per 50 steps and combined by inverse variance, stopping at 1e-3),
+    then iterations of flow_iter_events points of the trained proposal
+    combined with that estimate until 1e-3 (60 steps is the fastest setting
+    measured: more training lowers the variance a little but costs more time
+    than it saves).
     Also the per-event relative variance and the unweighting efficiency of
     each proposal on a fresh sample of eval_events with the final grid."""
     import torch
@@ -85,7 +89,7 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
         return mf.Config(process="gg>ttxgg", precision=prec, dr_min=0.4)
 
     res = {}
-    for prec in ("fp64", "fp32"):
+    for prec in (("fp64", "fp32") if vegas else ()):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         p = mf.Process(cfg(prec))
@@ -107,7 +111,7 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
     f = mf.Flow(p.ndim, max_batch=65536)
-    steps, mix, group = 300, 0.2, 50
+    mix, group = 0.2, 50
     rel, est = p.train_flow_online(f, steps, batch=65536, lr=5e-3, loss="variance", flow_mix=mix,
                                    group_steps=group, target_rel_err=1e-3, with_estimate=True)
     torch.cuda.synchronize()
@@ -115,7 +119,7 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
     if est.time_to_target >= 0.0:
         r = est
     else:
-        r = p.integrate(100, n_iter_events, target_rel_err=1e-3, adapt=False, flow=f, flow_mix=mix,
+        r = p.integrate(100, flow_iter_events, target_rel_err=1e-3, adapt=False, flow=f, flow_mix=mix,
                         iter_offset=1 << 24, prior=est)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
