@@ -156,6 +156,47 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
     return res
 
 
+def fp32_subsample_check(n: int = 100_000) -> dict:
+    """g g -> t t~ g g with FP32 amplitudes against the FP64 oracle on a
+    subsample of n events of one VEGAS iteration on an adapted grid: the same
+    Philox events through the same grid, per-event relative error of the
+    weights and the relative error of their mean (the FP64 GPU path is
+    reported beside it)."""
+    import torch
+
+    import oracle
+    import paper_2105_10529_amd as mf
+
+    p32 = mf.Process(mf.Config(process="gg>ttxgg", precision="fp32", dr_min=0.4))
+    p32.integrate(5, 1_000_000, adapt=True)
+    edges = torch.empty((10, 51), dtype=torch.float64, device="cuda")
+    p32.integrate(1, 2, adapt=False, edges_out=edges, iter_offset=1 << 20)
+    p64 = mf.Process(mf.Config(process="gg>ttxgg", precision="fp64", dr_min=0.4))
+    p64.integrate(1, 2, adapt=False, edges_in=edges, iter_offset=1 << 20)
+    it = 777
+    w32 = p32.weights(it, n)[0].cpu().numpy()
+    w64 = p64.weights(it, n)[0].cpu().numpy()
+    E = edges.cpu().numpy()
+    u = oracle.event_uniforms(n, 10, it, p32.cfg.seed, 0)
+    xs = np.empty_like(u)
+    jac = np.empty(n)
+    for i in range(n):
+        xs[i], jac[i], _ = oracle.vegas_map(E, u[i])
+    t0 = time.perf_counter()
+    ref = oracle.Oracle(oracle.Config(n_g=2, dr_min=0.4)).integrand(xs) * jac
+    t_orc = time.perf_counter() - t0
+    nz = ref != 0.0
+    r32 = np.abs(w32[nz] - ref[nz]) / np.abs(ref[nz])
+    r64 = np.abs(w64[nz] - ref[nz]) / np.abs(ref[nz])
+    return {"events": n, "nonzero": int(nz.sum()), "same_zero_pattern": bool(np.array_equal(w32 != 0, nz)),
+            "fp32_per_event_rel_err_max": float(r32.max()), "fp32_per_event_rel_err_median": float(np.median(r32)),
+            "fp32_per_event_rel_err_q999": float(np.quantile(r32, 0.999)),
+            "fp32_integral_rel_err": float(abs(w32.mean() - ref.mean()) / abs(ref.mean())),
+            "fp64_per_event_rel_err_max": float(r64.max()),
+            "fp64_integral_rel_err": float(abs(w64.mean() - ref.mean()) / abs(ref.mean())),
+            "oracle_seconds": t_orc, "oracle_threads": oracle.max_threads()}
+
+
 BF16_MFMA_PEAK = 2.5e15  # MI355X dense BF16 matrix-core FLOP/s
 
 
@@ -234,6 +275,7 @@ def secondary(seed_events: int) -> dict:
             "time_to_1e-3_s": tt.time_to_target, "iterations_to_1e-3": tt.n_iter_done,
             "events_to_1e-3": tt.n_events_total, "integral_at_1e-3_pb": tt.integral, "error_at_1e-3_pb": tt.error,
         }
+    out["ttgg_fp32_vs_oracle_subsample"] = fp32_subsample_check()
     out["ttgg_flow_vs_vegas"] = flow_comparison()
     out["flow_roofline"] = flow_roofline()
     grads = {}

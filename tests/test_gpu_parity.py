@@ -252,3 +252,16 @@ def test_autograd_function_routes_the_kernel_derivatives():
         assert abs(got - rdw.mean()) <= 1e-10 * max(abs(rdw.mean()), np.abs(rdw).max() / x.shape[0]), k
     with pytest.raises(ValueError):
         F.apply(to_dev_soa(x), torch.tensor(MT + 1.0, dtype=torch.float64), th)
+
+
+def test_fp32_subsample_of_an_adapted_iteration_matches_the_oracle():
+    """The Philox events of one iteration on an adapted g g -> t t~ g g grid:
+    FP32-amplitude weights within 1e-5 of the FP64 oracle per event (same
+    events, same grid, same cut decisions) and FP64 weights within 1e-11."""
+    import bench
+
+    r = bench.fp32_subsample_check(4000)
+    assert r["same_zero_pattern"] and r["nonzero"] > 1000, r
+    assert r["fp32_per_event_rel_err_max"] <= 1e-5, r
+    assert r["fp64_per_event_rel_err_max"] <= 1e-11, r
+    assert r["fp32_integral_rel_err"] <= 1e-6, r
