@@ -61,12 +61,16 @@ struct LayerDev {
   const float* b3p;  // [dB*NOP]
 };
 
+// Training caches of one layer.  The activations are kept event-contiguous
+// ([feature][ldn], ldn = the batch rounded up to 8) because their only
+// consumers are the weight-gradient products, which reduce over events.
 struct LayerCache {
-  bf16* xa;    // [n][KA]  inputs of the first dense layer (hi | lo)
-  bf16* h1;    // [n][H]
-  bf16* h2;    // [n][H]
-  float* o;    // [n][dB][NOP] logits
-  float* lin;  // [d][n]   layer input
+  bf16* xa;     // [KA][ldn] inputs of the first dense layer (hi | lo)
+  bf16* h1;     // [H][ldn]
+  bf16* h2;     // [H][ldn]
+  float* o;     // [n][dB][NOP] logits
+  float* lin;   // [d][n]   layer input
+  int64_t ldn;  // leading dimension of the event-contiguous caches
 };
 
 __device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -281,8 +285,8 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
     xa[m * KA + (((i >> 3) ^ (m & 3)) << 3) + (i & 7)] = hi;
     xa[m * KA + (((il >> 3) ^ (m & 3)) << 3) + (il & 7)] = lo;
     if (CACHE && e < n) {
-      C.xa[e * KA + i] = hi;
-      C.xa[e * KA + il] = lo;
+      C.xa[i * C.ldn + e] = hi;
+      C.xa[il * C.ldn + e] = lo;
     }
   }
   if (CACHE) {
@@ -341,14 +345,27 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
   }
   __syncthreads();
   if (CACHE) {
-    // 16-byte chunks, un-permuted, rows of H contiguous
-    for (int idx = tid; idx < T * (H / 8); idx += 256) {
-      const int m = idx / (H / 8), ch = idx % (H / 8);
-      const int64_t e = e0 + m;
+    // event-contiguous copies: eight events of one feature per 16-byte store
+    for (int idx = tid; idx < H * (T / 8); idx += 256) {
+      const int ch = idx % (T / 8), f = idx / (T / 8);
+      const int m0 = 8 * ch;
+      const int64_t e = e0 + m0;
       if (e >= n) continue;
-      const int src = m * H + ((ch ^ (m & 15)) << 3);
-      *reinterpret_cast<bf16x8*>(C.h1 + e * H + 8 * ch) = *reinterpret_cast<const bf16x8*>(h1 + src);
-      *reinterpret_cast<bf16x8*>(C.h2 + e * H + 8 * ch) = *reinterpret_cast<const bf16x8*>(h2 + src);
+      bf16x8 v1, v2;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        v1[i] = h1[hs(m0 + i, f)];
+        v2[i] = h2[hs(m0 + i, f)];
+      }
+      if (e + 8 <= n) {
+        *reinterpret_cast<bf16x8*>(C.h1 + (int64_t)f * C.ldn + e) = v1;
+        *reinterpret_cast<bf16x8*>(C.h2 + (int64_t)f * C.ldn + e) = v2;
+      } else {
+        for (int i = 0; e + i < n; ++i) {
+          C.h1[(int64_t)f * C.ldn + e + i] = v1[i];
+          C.h2[(int64_t)f * C.ldn + e + i] = v2[i];
+        }
+      }
     }
     __syncthreads();
   }
@@ -436,18 +453,22 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
 }
 
 // ------------------------------------------------------------ PQ backward
-// For event e and transformed coordinate c (thread e + n c): given the
-// gradient gz of the loss with respect to the layer output at that coordinate
-// (g[j][e]) and glp = dL/dlog q = -w_e / sum w, replaces g[j][e] by the
-// gradient with respect to the layer input and writes the gradient with
-// respect to the 2K+1 logits (BF16, padded to NOP with zeros).
+// For event e = 256 blockIdx.x + threadIdx.x and transformed coordinate
+// c = blockIdx.y: given the gradient gz of the loss with respect to the layer
+// output at that coordinate (g[j][e]) and glp = dL/dlog q = -w_e / sum w,
+// replaces g[j][e] by the gradient with respect to the layer input and writes
+// the gradient with respect to the 2K+1 logits (BF16, padded to NOP with
+// zeros), row-major per event and event-contiguous per logit (through an LDS
+// tile, 16-byte stores).
 __global__ void __launch_bounds__(256) k_pq_backward(LayerDev L, LayerCache C, int64_t n, float* __restrict__ g,
                                                      const float* __restrict__ w, const float* __restrict__ wsum,
-                                                     bf16* __restrict__ go) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * L.dB) return;
-  const int c = (int)(idx / n);
-  const int64_t e = idx % n;
+                                                     bf16* __restrict__ go, bf16* __restrict__ goT) {
+  __shared__ __attribute__((aligned(16))) bf16 tile[NOP][256 + 8];
+  const int c = blockIdx.y;
+  const int64_t eb = (int64_t)blockIdx.x * 256;
+  const int64_t e = eb + threadIdx.x;
+  const bool live = e < n;
+  if (live) {
   const int j = L.b_idx[c];
   const float* o = C.o + (e * L.dB + c) * NOP;
   float ol[NO];
@@ -496,16 +517,42 @@ __global__ void __launch_bounds__(256) k_pq_backward(LayerDev L, LayerCache C, i
     GW[k] -= SG * 0.5f * (V[k] + V[k + 1]);
     SW += W[k] * GW[k];
   }
+  // row-major for the activation-gradient product, event-contiguous for the
+  // weight-gradient product
   bf16* dst = go + e * ((int64_t)L.dB * NOP) + (int64_t)c * NOP;
 #pragma unroll
-  for (int k = 0; k < KB; ++k) dst[k] = (bf16)(W[k] * (GW[k] - SW));
+  for (int k = 0; k < KB; ++k) {
+    const bf16 v = (bf16)(W[k] * (GW[k] - SW));
+    dst[k] = v;
+    tile[k][threadIdx.x] = v;
+  }
 #pragma unroll
   for (int k = 0; k <= KB; ++k) {
     const float wl = k > 0 ? W[k - 1] : 0.0f, wr = k < KB ? W[k] : 0.0f;
-    dst[KB + k] = (bf16)(V[k] * (GV[k] - SG * 0.5f * (wl + wr)));
+    const bf16 v = (bf16)(V[k] * (GV[k] - SG * 0.5f * (wl + wr)));
+    dst[KB + k] = v;
+    tile[KB + k][threadIdx.x] = v;
   }
 #pragma unroll
-  for (int k = NO; k < NOP; ++k) dst[k] = (bf16)0.0f;
+  for (int k = NO; k < NOP; ++k) {
+    dst[k] = (bf16)0.0f;
+    tile[k][threadIdx.x] = (bf16)0.0f;
+  }
+  }
+  __syncthreads();
+  // event-contiguous copy: 8 events of one logit per 16-byte store
+  bf16* dstT = goT + (int64_t)c * NOP * C.ldn;
+  for (int ch = threadIdx.x; ch < NOP * 32; ch += 256) {
+    const int k = ch / 32, e8 = 8 * (ch % 32);
+    const int64_t ee = eb + e8;
+    if (ee >= n) continue;
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(&tile[k][e8]);
+    if (ee + 8 <= n) {
+      *reinterpret_cast<bf16x8*>(dstT + (int64_t)k * C.ldn + ee) = v;
+    } else {
+      for (int i = 0; ee + i < n; ++i) dstT[(int64_t)k * C.ldn + ee + i] = v[i];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -517,7 +564,8 @@ __global__ void __launch_bounds__(256) k_pq_backward(LayerDev L, LayerCache C, i
 //          colsum set, row M of the partial receives the column sums of B
 //          over the chunk (one more MFMA per k-step with an all-ones A
 //          fragment in the first row of blocks)
-//   EPI 1: BF16 store to Cb[m ldc + n] of acc * (ref[m ldr + n] > 0 ? 1 : slope)
+//   EPI 1: BF16 store to Cb[m ldc + n] of acc * (ref[m ref_rs + n ref_cs] > 0 ? 1 : slope),
+//          and of the same values to CbT[n ldt + m] (event-contiguous copy)
 struct GemmArgs {
   const bf16* A;
   int64_t lda;
@@ -529,7 +577,9 @@ struct GemmArgs {
   int64_t zs;
   bf16* Cb;
   const bf16* ref;
-  int64_t ldc, ldr;
+  int64_t ldc, ref_rs, ref_cs;
+  bf16* CbT;
+  int64_t ldt;
   int colsum;
 };
 
@@ -650,15 +700,36 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     for (int j = 0; j < 2; ++j) {
       const int gn = n0 + wn + 16 * j + row;
       if (gn >= g.N) continue;
+      const int gm0 = m0 + wm + 16 * i + 4 * quad;
+      if (gm0 >= g.M) continue;
+      if (EPI == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + 16 * i + 4 * quad + r;
-        if (gm >= g.M) continue;
-        if (EPI == 0) {
-          g.Cf[(int64_t)blockIdx.z * g.zs + (int64_t)gm * g.ldc + gn] = acc[i][j][r];
+        for (int r = 0; r < 4; ++r)
+          if (gm0 + r < g.M) g.Cf[(int64_t)blockIdx.z * g.zs + (int64_t)(gm0 + r) * g.ldc + gn] = acc[i][j][r];
+      } else {
+        // the four sign references of rows gm0..gm0+3 (event-contiguous when
+        // ref_rs == 1: one 8-byte load)
+        bf16x4 rv;
+        if (g.ref_rs == 1 && gm0 + 4 <= g.M) {
+          rv = *reinterpret_cast<const bf16x4*>(g.ref + (int64_t)gn * g.ref_cs + gm0);
         } else {
-          const float s = (float)g.ref[(int64_t)gm * g.ldr + gn] > 0.0f ? 1.0f : SLOPE;
-          g.Cb[(int64_t)gm * g.ldc + gn] = (bf16)(acc[i][j][r] * s);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int gm = gm0 + r < g.M ? gm0 + r : gm0;
+            rv[r] = g.ref[(int64_t)gm * g.ref_rs + (int64_t)gn * g.ref_cs];
+          }
+        }
+        bf16x4 t;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float s = (float)rv[r] > 0.0f ? 1.0f : SLOPE;
+          t[r] = (bf16)(acc[i][j][r] * s);
+          if (gm0 + r < g.M) g.Cb[(int64_t)(gm0 + r) * g.ldc + gn] = t[r];
+        }
+        if (gm0 + 4 <= g.M) {
+          *reinterpret_cast<bf16x4*>(g.CbT + (int64_t)gn * g.ldt + gm0) = t;
+        } else {
+          for (int r = 0; gm0 + r < g.M; ++r) g.CbT[(int64_t)gn * g.ldt + gm0 + r] = t[r];
         }
       }
     }
@@ -852,6 +923,9 @@ struct mf_flow {
   bf16* d_go = nullptr;     // [cap][dBmax*NOP]
   bf16* d_ga2 = nullptr;    // [cap][H]
   bf16* d_ga1 = nullptr;    // [cap][H]
+  bf16* d_goT = nullptr;    // [dBmax*NOP][capp]  event-contiguous copies
+  bf16* d_ga2T = nullptr;   // [H][capp]
+  bf16* d_ga1T = nullptr;   // [H][capp]
   float* d_gx = nullptr;    // [cap][KA]
   float* d_part = nullptr;  // split-K partials
   size_t part_cap = 0;
@@ -888,18 +962,18 @@ int64_t splitk(int64_t n, int M, int N) {
 }
 
 // Weight and bias gradients over the batch: dW[in][out] = X^T G and
-// db[out] = column sums of G, with X [n][ldx] (first M columns) and G
-// [n][ldg] (first N columns) in BF16, split over events.
-void weight_grad(mf_flow* f, const bf16* X, int64_t ldx, int M, int m_real, const bf16* G, int64_t ldg, int N,
-                 int gpad, int greal, int64_t n, float* out, int ldo, float* bias, hipStream_t s, int fold = 0) {
+// db[out] = column sums of G, from the event-contiguous BF16 copies
+// XT [M][ldn] and GT [N][ldn], split over events.
+void weight_grad(mf_flow* f, const bf16* XT, int64_t ldn, int M, int m_real, const bf16* GT, int N, int gpad,
+                 int greal, int64_t n, float* out, int ldo, float* bias, hipStream_t s, int fold = 0) {
   const int64_t Z = splitk(n, M, N);
   const int64_t chunk = ((n + Z - 1) / Z + 31) / 32 * 32;
   const int Zl = (int)((n + chunk - 1) / chunk);
   GemmArgs a{};
-  a.A = X;
-  a.lda = ldx;
-  a.B = G;
-  a.ldb = ldg;
+  a.A = XT;  // A(m, k) = XT[m ldn + k]
+  a.lda = ldn;
+  a.B = GT;  // B(k, n) = GT[n ldn + k]
+  a.ldb = ldn;
   a.M = M;
   a.N = N;
   a.K = n;
@@ -908,7 +982,7 @@ void weight_grad(mf_flow* f, const bf16* X, int64_t ldx, int M, int m_real, cons
   a.zs = (int64_t)(M + 1) * N;
   a.ldc = N;
   a.colsum = 1;
-  gemm<0, 1, 0>(a, Zl, s);
+  gemm<1, 0, 0>(a, Zl, s);
   const int64_t tot = (int64_t)(m_real + 1) * N;
   hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, f->d_part, Zl, M, N, m_real,
                      gpad, greal, out, ldo, fold, bias);
@@ -950,6 +1024,8 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
   hipError_t e = hipMemcpy2DAsync(f->d_y, sizeof(float) * n, y, sizeof(float) * ldy, sizeof(float) * n, d,
                                   hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return set_error(MF_EDEVICE, "batch copy: %s", hipGetErrorString(e));
+  const int64_t ldn = (n + 7) / 8 * 8;
+  for (int l = 0; l < f->nl; ++l) f->cache[l].ldn = ldn;
   run_layers(f, f->d_y, n, n, f->d_lq, false, true, s);
   const float* w = w_in;
   if (kind == MF_FLOW_LOSS_VARIANCE) {
@@ -973,10 +1049,9 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     float* gb2 = gW2 + (int64_t)H * H;
     float* gW3 = gb2 + H;
     float* gb3 = gW3 + (int64_t)H * nO;
-    const int64_t tot = n * L.dB;
-    hipLaunchKernelGGL(k_pq_backward, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L, C, n, f->d_gy, w,
-                       f->d_scal, f->d_go);
-    weight_grad(f, C.h2, H, H, H, f->d_go, NB, NB, NOP, NO, n, gW3, nO, gb3, s);
+    hipLaunchKernelGGL(k_pq_backward, dim3((unsigned)((n + 255) / 256), L.dB), dim3(256), 0, s, L, C, n, f->d_gy, w,
+                       f->d_scal, f->d_go, f->d_goT);
+    weight_grad(f, C.h2, ldn, H, H, f->d_goT, NB, NOP, NO, n, gW3, nO, gb3, s);
     // ga2 = (go W3^T) * leaky'(h2): A = go [n][NB], B(k=o, n=j) = W3t[o][j]
     GemmArgs a{};
     a.A = f->d_go;
@@ -988,11 +1063,14 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     a.K = NB;
     a.kchunk = NB;
     a.Cb = f->d_ga2;
+    a.CbT = f->d_ga2T;
+    a.ldt = ldn;
     a.ref = C.h2;
+    a.ref_rs = 1;
+    a.ref_cs = ldn;
     a.ldc = H;
-    a.ldr = H;
     gemm<1, 1, 1>(a, 1, s);
-    weight_grad(f, C.h1, H, H, H, f->d_ga2, H, H, 0, 0, n, gW2, H, gb2, s);
+    weight_grad(f, C.h1, ldn, H, H, f->d_ga2T, H, 0, 0, n, gW2, H, gb2, s);
     // ga1 = (ga2 W2^T) * leaky'(h1): B(k=j2, n=j1) = W2[j1][j2] = W2t[j2][j1]
     a.A = f->d_ga2;
     a.lda = H;
@@ -1001,9 +1079,10 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     a.K = H;
     a.kchunk = H;
     a.Cb = f->d_ga1;
+    a.CbT = f->d_ga1T;
     a.ref = C.h1;
     gemm<1, 1, 1>(a, 1, s);
-    weight_grad(f, C.xa, KA, KA, L.dA, f->d_ga1, H, H, 0, 0, n, gW1, H, gb1, s, KLO);
+    weight_grad(f, C.xa, ldn, KA, L.dA, f->d_ga1T, H, 0, 0, n, gW1, H, gb1, s, KLO);
     // gx = ga1 W1^T: B(k=j, n=i) = W1[i][j] = W1t[j][i]
     GemmArgs b{};
     b.A = f->d_ga1;
@@ -1093,7 +1172,9 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
   const int64_t cap = cfg->max_batch;
   f->cap = cap;
   // caches: xa, h1, h2, o, lin per layer
-  size_t per_layer = sizeof(bf16) * (size_t)cap * (KA + 2 * H) + sizeof(float) * (size_t)cap * (dBmax * NOP + d);
+  const int64_t capp = (cap + 7) / 8 * 8;
+  size_t per_layer = sizeof(bf16) * (size_t)capp * (KA + 2 * H) + sizeof(float) * (size_t)cap * (dBmax * NOP + d);
+  per_layer = (per_layer + 255) / 256 * 256;  // every layer's caches start 256-byte aligned
   f->part_cap = (size_t)std::max({splitk(cap, H, (int)(dBmax * NOP)) * (H + 1) * dBmax * NOP,
                                    splitk(cap, H, H) * (H + 1) * H, splitk(cap, KA, H) * (KA + 1) * H});
   if (hipMalloc(&f->d_p, sizeof(float) * off) != hipSuccess || hipMalloc(&f->d_g, sizeof(float) * off) != hipSuccess ||
@@ -1107,6 +1188,9 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
       hipMalloc(&f->d_go, sizeof(bf16) * cap * dBmax * NOP) != hipSuccess ||
       hipMalloc(&f->d_ga2, sizeof(bf16) * cap * H) != hipSuccess ||
       hipMalloc(&f->d_ga1, sizeof(bf16) * cap * H) != hipSuccess ||
+      hipMalloc(&f->d_goT, sizeof(bf16) * capp * dBmax * NOP) != hipSuccess ||
+      hipMalloc(&f->d_ga2T, sizeof(bf16) * capp * H) != hipSuccess ||
+      hipMalloc(&f->d_ga1T, sizeof(bf16) * capp * H) != hipSuccess ||
       hipMalloc(&f->d_gx, sizeof(float) * cap * KA) != hipSuccess ||
       hipMalloc(&f->d_part, sizeof(float) * f->part_cap) != hipSuccess ||
       hipMalloc(&f->d_scal, sizeof(float) * 4) != hipSuccess) {
@@ -1141,15 +1225,16 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     L.b2 = L.b1 + H + (int64_t)H * H;
     LayerCache& C = f->cache[l];
     C.xa = (bf16*)cm;
-    cm += sizeof(bf16) * cap * KA;
+    cm += sizeof(bf16) * capp * KA;
     C.h1 = (bf16*)cm;
-    cm += sizeof(bf16) * cap * H;
+    cm += sizeof(bf16) * capp * H;
     C.h2 = (bf16*)cm;
-    cm += sizeof(bf16) * cap * H;
+    cm += sizeof(bf16) * capp * H;
+    C.ldn = capp;
     C.o = (float*)cm;
     cm += sizeof(float) * cap * dBmax * NOP;
     C.lin = (float*)cm;
-    cm += sizeof(float) * cap * d;
+    cm = (char*)f->d_cachemem + per_layer * (size_t)(l + 1);
   }
   *out = f;
   return MF_OK;
@@ -1171,6 +1256,9 @@ void mf_flow_destroy(mf_flow* f) {
   hipFree(f->d_go);
   hipFree(f->d_ga2);
   hipFree(f->d_ga1);
+  hipFree(f->d_goT);
+  hipFree(f->d_ga2T);
+  hipFree(f->d_ga1T);
   hipFree(f->d_gx);
   hipFree(f->d_part);
   hipFree(f->d_scal);
