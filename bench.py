@@ -43,17 +43,19 @@ def flops_per_event(m: int) -> int:
     return gen_me.flop_count(m)["total"]
 
 
-def cpu_baseline(seed: int, target_seconds: float = 12.0) -> dict:
-    """The FP64 oracle on the host cores, on the first events of the same stream."""
+def cpu_baseline(seed: int, target_seconds: float = 15.0) -> dict:
+    """The FP64 oracle on the host cores, on the first events of the same stream
+    (sized from a short calibration run to take about target_seconds)."""
     import oracle
 
     orc = oracle.Oracle(oracle.Config(n_g=1))
     edges = oracle.uniform_edges(7)
-    n = 2000
+    orc.vegas_iteration(edges, 0, 2000, seed, purpose=0)  # thread start-up
+    n = 50_000
     t0 = time.perf_counter()
     orc.vegas_iteration(edges, 0, n, seed, purpose=0)
     dt = time.perf_counter() - t0
-    n = int(max(2000, min(2_000_000, n * target_seconds / max(dt, 1e-3))))
+    n = int(max(n, min(10_000_000, n * target_seconds / max(dt, 1e-3))))
     t0 = time.perf_counter()
     orc.vegas_iteration(edges, 0, n, seed, purpose=0)
     dt = time.perf_counter() - t0

@@ -210,6 +210,15 @@ mf_status mf_weights(mf_process* p, struct mf_flow* flow, double flow_mix, uint6
  * MF_EINVAL for a NaN weight or q outside (0,1].  Synchronous. */
 mf_status mf_weight_stats(const double* w, int64_t n, double q, double* out, void* stream);
 
+/* Vector-Jacobian product of per-event derivatives with an upstream
+ * gradient (the backward step of an autograd function over
+ * mf_integrand_grad):
+ *   dw:  device [k][n] FP64 (e.g. the dw of mf_integrand_grad, k = 9)
+ *   g:   device [n] FP64 upstream gradient of the per-event weights
+ *   out: device [k] FP64, out[j] = sum_e dw[j][e] g[e] (ordered, reproducible)
+ * k in 1..64, n >= 1.  Takes a small stream-ordered scratch allocation. */
+mf_status mf_vjp(const double* dw, int32_t k, const double* g, int64_t n, double* out, void* stream);
+
 /* Pathwise Monte Carlo estimate of sigma and its parameter derivatives with
  * a frozen grid (the current grid of the handle, or o->edges_in): events as
  * in mf_integrate with iteration word o->iter_offset, o->n_events events.

@@ -124,7 +124,7 @@ EXPORTS = ("mf_process_create", "mf_process_destroy", "mf_process_ndim", "mf_las
            "mf_integrand_grad", "mf_vegas_refine", "mf_integrate", "mf_grad", "mf_weights", "mf_weight_stats",
            "mf_flow_create", "mf_flow_destroy", "mf_flow_ndim", "mf_flow_param_count", "mf_flow_masks",
            "mf_flow_set_params", "mf_flow_get_params", "mf_flow_forward", "mf_flow_inverse", "mf_flow_loss_grad",
-           "mf_flow_adam_step", "mf_flow_train", "mf_flow_train_online")
+           "mf_flow_adam_step", "mf_flow_train", "mf_flow_train_online", "mf_vjp")
 
 _lib = None
 
@@ -159,6 +159,8 @@ def lib():
         L.mf_weights.restype = i32
         L.mf_weight_stats.argtypes = [P, i64, d, P, P]
         L.mf_weight_stats.restype = i32
+        L.mf_vjp.argtypes = [P, i32, P, i64, P, P]
+        L.mf_vjp.restype = i32
         L.mf_flow_create.argtypes = [ctypes.POINTER(_FlowConfig), ctypes.POINTER(P)]
         L.mf_flow_create.restype = i32
         L.mf_flow_destroy.argtypes = [P]
@@ -382,6 +384,16 @@ class Process:
         return out, err
 
 
+def vjp(dw, g, stream=None):
+    """out[j] = sum_e dw[j][e] g[e] on the device -- mf_vjp."""
+    import torch
+
+    k, n = dw.shape
+    out = torch.empty(k, dtype=torch.float64, device=dw.device)
+    _check(lib().mf_vjp(_dev_ptr(dw), k, _dev_ptr(g), n, _dev_ptr(out), _stream_ptr(stream)))
+    return out
+
+
 def weight_stats(w, q: float = 0.999, stream=None) -> dict:
     """mean, max, q-quantile, non-zero count and relative variance per event of device weights -- mf_weight_stats."""
     out = np.zeros(5)
@@ -535,7 +547,7 @@ def make_autograd_integrand(process: "Process"):
         @staticmethod
         def backward(ctx, g):
             (dw,) = ctx.saved_tensors
-            gd = dw @ g.to(dw.dtype)  # [9]
+            gd = vjp(dw, g.to(dw.dtype).contiguous())  # [9], mf_vjp
             return None, gd[0].to(ctx.devices[0], torch.float64), gd[1:].to(ctx.devices[1], torch.float64)
 
     return MfIntegrand

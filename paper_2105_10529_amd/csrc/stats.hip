@@ -118,7 +118,53 @@ __global__ void k_radix_pick(const unsigned long long* __restrict__ hist, unsign
   state[2] = k - below;
 }
 
+// out[k] = sum_e dw[k][e] g[e]: per-block partial sums in a fixed order, then
+// one block adds the partials in order.
+__global__ void __launch_bounds__(SB) k_vjp_partial(const double* __restrict__ dw, int k, const double* __restrict__ g,
+                                                   int64_t n, double* __restrict__ part) {
+  __shared__ double sh[SB];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = b0 + per < n ? b0 + per : n;
+  for (int r = 0; r < k; ++r) {
+    double a = 0.0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += SB) a += dw[(int64_t)r * n + i] * g[i];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int st = SB / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * k + r] = sh[0];
+    __syncthreads();
+  }
+}
+__global__ void k_vjp_final(const double* __restrict__ part, int nb, int k, double* __restrict__ out) {
+  const int r = threadIdx.x;
+  if (r >= k) return;
+  double a = 0.0;
+  for (int b = 0; b < nb; ++b) a += part[(int64_t)b * k + r];
+  out[r] = a;
+}
+
 }  // namespace
+
+extern "C" mf_status mf_vjp(const double* dw, int32_t k, const double* g, int64_t n, double* out, void* stream) {
+  mf::clear_error();
+  if (!dw || !g || !out) return mf::set_error(MF_EINVAL, "NULL argument");
+  if (k < 1 || k > 64) return mf::set_error(MF_EINVAL, "k must be in 1..64");
+  if (n < 1) return mf::set_error(MF_EINVAL, "n must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = (int)(n < (int64_t)SMAXB * SB ? (n + SB - 1) / SB : SMAXB);
+  double* part = nullptr;
+  if (hipMallocAsync((void**)&part, sizeof(double) * nb * k, s) != hipSuccess)
+    return mf::set_error(MF_ENOMEM, "partial sums");
+  hipLaunchKernelGGL(k_vjp_partial, dim3(nb), dim3(SB), 0, s, dw, k, g, n, part);
+  hipLaunchKernelGGL(k_vjp_final, dim3(1), dim3(64), 0, s, part, nb, k, out);
+  const hipError_t e = hipGetLastError();
+  (void)hipFreeAsync(part, s);
+  if (e != hipSuccess) return mf::set_error(MF_EDEVICE, "vjp launch: %s", hipGetErrorString(e));
+  return MF_OK;
+}
 
 extern "C" mf_status mf_weight_stats(const double* w, int64_t n, double q, double* out, void* stream) {
   mf::clear_error();

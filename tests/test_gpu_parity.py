@@ -265,3 +265,13 @@ def test_fp32_subsample_of_an_adapted_iteration_matches_the_oracle():
     assert r["fp32_per_event_rel_err_max"] <= 1e-5, r
     assert r["fp64_per_event_rel_err_max"] <= 1e-11, r
     assert r["fp32_integral_rel_err"] <= 1e-6, r
+
+
+def test_vjp_is_the_ordered_contraction():
+    rng = np.random.default_rng(91)
+    for k, n in ((9, 1), (9, 1000), (3, 300001)):
+        dw = rng.normal(size=(k, n))
+        g = rng.normal(size=n)
+        got = mf.vjp(torch.from_numpy(dw).cuda(), torch.from_numpy(g).cuda()).cpu().numpy()
+        ref = dw @ g
+        assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(dw).sum(axis=1).max())
