@@ -360,3 +360,20 @@ def test_training_batches_estimate_the_integral():
     _, e2 = p.train_flow_online(f2, 400, batch=16384, lr=3e-3, flow_mix=0.1, group_steps=20, target_rel_err=3e-3,
                                 with_estimate=True)
     assert e2.time_to_target > 0 and e2.error / e2.integral <= 3e-3 and e2.n_events_total < 400 * 16384
+
+
+def test_training_is_bitwise_reproducible():
+    """Fixed-order reductions everywhere (no atomics): two identical on-policy
+    trainings from the identity flow give bit-identical parameters and
+    estimates."""
+    p = mf.Process(mf.Config(process="gg>ttxg"))
+    p.integrate(3, 200_000, adapt=True)
+    res = []
+    for _ in range(2):
+        f = mf.Flow(7, max_batch=8192)
+        rel, est = p.train_flow_online(f, 20, batch=8192, lr=3e-3, flow_mix=0.1, group_steps=10,
+                                       with_estimate=True)
+        res.append((f.get_params(), rel, est.integral, est.error))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.array_equal(res[0][1], res[1][1])
+    assert res[0][2] == res[1][2] and res[0][3] == res[1][3]
