@@ -71,10 +71,15 @@ typedef struct {
   int64_t max_batch;  /* largest n accepted by mf_flow_loss_grad (sizes the
                          per-layer activation caches: about
                          n_layers * max_batch * (2 KB + 0.3 KB * ndim) bytes) */
+  uint64_t seed;      /* Philox key word 0 of the initial weights */
 } mf_flow_config;
 
-/* Create a flow with all parameters zero (the identity map) on the current
- * device.  MF_EINVAL for sizes outside the ranges above, MF_ENOTSUP for
+/* Create a flow on the current device.  Initial parameters: the weights of
+ * the first two dense layers of every coupling layer uniform in
+ * +-sqrt(6 / fan_in), drawn from Philox4x64-10 with counter (parameter index,
+ * 0, 0, 0) and key (seed, 3); all biases and the output layers zero, so the
+ * flow is the identity map (log q = 0) while every parameter receives a
+ * gradient.  MF_EINVAL for sizes outside the ranges above, MF_ENOTSUP for
  * another hidden width or bin count, MF_ENOMEM on allocation failure. */
 mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out);
 

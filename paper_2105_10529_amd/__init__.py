@@ -74,6 +74,7 @@ class _FlowConfig(ctypes.Structure):
         ("hidden", ctypes.c_int32),
         ("bins", ctypes.c_int32),
         ("max_batch", ctypes.c_int64),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -407,8 +408,8 @@ class Flow:
     HIDDEN = 256
     BINS = 32
 
-    def __init__(self, ndim: int, n_layers: int = 6, max_batch: int = 16384):
-        c = _FlowConfig(ndim, n_layers, self.HIDDEN, self.BINS, max_batch)
+    def __init__(self, ndim: int, n_layers: int = 6, max_batch: int = 16384, seed: int = 2105105290):
+        c = _FlowConfig(ndim, n_layers, self.HIDDEN, self.BINS, max_batch, seed)
         h = ctypes.c_void_p()
         _check(lib().mf_flow_create(ctypes.byref(c), ctypes.byref(h)))
         self._h = h

@@ -27,6 +27,7 @@
 
 #include "../../include/mf_flow.h"
 #include "flow_internal.h"
+#include "pipeline.h"
 #include "status.h"
 
 namespace mf {
@@ -40,7 +41,7 @@ constexpr int KA = 32;        // first-layer k width: inputs split as BF16 hi (k
 constexpr int KLO = 16;       // offset of the low parts
 constexpr int T = 64;         // events per workgroup of the layer kernel
 constexpr int LDO = NOP + 1;  // LDS row stride (floats) of one coordinate's logits
-constexpr int MAXD = 16;
+constexpr int FMAXD = 16;
 constexpr int MAXL = 8;
 constexpr float SLOPE = 0.01f;
 
@@ -51,8 +52,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct LayerDev {
   int dA, dB;
-  int a_idx[MAXD];
-  int b_idx[MAXD];
+  int a_idx[FMAXD];
+  int b_idx[FMAXD];
   const bf16* W1t;   // [H][KA]      (W1 transposed, at k = i and k = KLO + i)
   const float* b1;   // [H]
   const bf16* W2t;   // [H][H]       (W2 transposed)
@@ -891,6 +892,28 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, floa
   s.b3p[(r / NO) * NOP + r % NO] = v;
 }
 
+// Initial parameters: the weights of the first two dense layers of every
+// coupling layer uniform in +-sqrt(6 / fan_in) from Philox4x64-10 (counter
+// (index, 0, 0, 0), key (seed, 3)); biases and the output layer zero, so the
+// flow starts as the identity map while every layer's gradient is live.
+__global__ void k_init_params(float* __restrict__ p, int64_t count, uint64_t seed, SegTable S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  int l = 0;
+  while (l + 1 < S.nl && i >= S.l[l + 1].off) ++l;
+  const SegLayer& s = S.l[l];
+  const int64_t r = i - s.off, nW1 = (int64_t)s.dA * H, nW2 = (int64_t)H * H;
+  float a = 0.0f;
+  if (r < nW1) a = sqrtf(6.0f / (float)s.dA);
+  else if (r >= nW1 + H && r < nW1 + H + nW2) a = sqrtf(6.0f / (float)H);
+  float v = 0.0f;
+  if (a > 0.0f) {
+    const U4 q = philox4x64_10((uint64_t)i, 0, 0, 0, seed, 3);
+    v = (float)((2.0 * u01(q.x0) - 1.0) * a);
+  }
+  p[i] = v;
+}
+
 }  // namespace flow
 }  // namespace mf
 
@@ -1127,8 +1150,8 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
   clear_error();
   if (!cfg || !out) return set_error(MF_EINVAL, "NULL argument");
   *out = nullptr;
-  if (cfg->ndim < 2 || cfg->ndim > MAXD) return set_error(MF_EINVAL, "ndim must be in 2..%d", MAXD);
-  static_assert(MAXD - 1 <= KLO, "kept coordinates must fit the high half of the first-layer inputs");
+  if (cfg->ndim < 2 || cfg->ndim > FMAXD) return set_error(MF_EINVAL, "ndim must be in 2..%d", FMAXD);
+  static_assert(FMAXD - 1 <= KLO, "kept coordinates must fit the high half of the first-layer inputs");
   if (cfg->n_layers < 1 || cfg->n_layers > MAXL) return set_error(MF_EINVAL, "n_layers must be in 1..%d", MAXL);
   if (cfg->hidden != H) return set_error(MF_ENOTSUP, "only hidden width %d is built", H);
   if (cfg->bins != KB) return set_error(MF_ENOTSUP, "only %d bins are built", KB);
@@ -1197,8 +1220,7 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     hipGetLastError();
     return cleanup(set_error(MF_ENOMEM, "flow allocation failed"));
   }
-  if (hipMemset(f->d_p, 0, sizeof(float) * off) != hipSuccess ||
-      hipMemset(f->d_g, 0, sizeof(float) * off) != hipSuccess ||
+  if (hipMemset(f->d_g, 0, sizeof(float) * off) != hipSuccess ||
       hipMemset(f->d_m1, 0, sizeof(float) * off) != hipSuccess ||
       hipMemset(f->d_m2, 0, sizeof(float) * off) != hipSuccess ||
       hipMemset(f->d_w16, 0, sizeof(bf16) * w16) != hipSuccess ||
@@ -1236,6 +1258,10 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     C.lin = (float*)cm;
     cm = (char*)f->d_cachemem + per_layer * (size_t)(l + 1);
   }
+  hipLaunchKernelGGL(k_init_params, dim3((unsigned)((off + 255) / 256)), dim3(256), 0, 0, f->d_p, off, cfg->seed,
+                     f->seg);
+  if (refresh(f, nullptr, 0, 0.0f, 1.0f, 1.0f) != MF_OK || hipDeviceSynchronize() != hipSuccess)
+    return cleanup(set_error(MF_EDEVICE, "flow parameter initialisation failed"));
   *out = f;
   return MF_OK;
 }

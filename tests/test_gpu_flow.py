@@ -55,12 +55,34 @@ def test_masks_and_layout_match_oracle():
         assert f.param_count == n
 
 
-def test_zero_parameters_give_the_identity():
-    f = mf.Flow(7, max_batch=64)
+def test_new_flow_is_the_identity_with_live_hidden_layers():
+    """At creation the output layers are zero (identity map, log q = 0) and the
+    hidden weights are random, so every layer's gradient is non-zero."""
+    f = mf.Flow(7, max_batch=512)
     y = si.unit_points(1000, 7, seed=11)
     z, lq = f.forward(_dev32(y))
     assert np.max(np.abs(z.cpu().numpy().T - y.astype(np.float32))) < 2e-7
     assert np.all(lq.cpu().numpy() == 0.0)
+    layers = f.unflatten(f.get_params())
+    for p in layers:
+        assert np.all(p["W3"] == 0) and np.all(p["b3"] == 0) and np.all(p["b1"] == 0)
+        bound = np.sqrt(6.0 / p["W1"].shape[0])
+        assert 0.5 * bound < np.abs(p["W1"]).max() <= bound and np.abs(p["W2"]).max() <= np.sqrt(6.0 / 256)
+    # the output layer learns at once (hidden activations are non-zero); after
+    # one update the gradient reaches the hidden layers
+    w = np.exp(-np.sum((y[:512] - 0.3) ** 2, axis=1) / 0.05)
+    yd, wd = _dev32(y[:512]), torch.from_numpy(w.astype(np.float32)).cuda()
+    _, g = f.loss_grad(yd, wd)
+    for gl in f.unflatten(g.cpu().numpy()):
+        assert np.abs(gl["W3"]).max() > 0 and np.abs(gl["b3"]).max() > 0
+    f.adam_step(1e-3)
+    _, g = f.loss_grad(yd, wd)
+    for gl in f.unflatten(g.cpu().numpy()):
+        for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            assert np.abs(gl[k]).max() > 0, k
+    fa, fb, fc = mf.Flow(7, max_batch=64), mf.Flow(7, max_batch=64), mf.Flow(7, max_batch=64, seed=5)
+    assert np.array_equal(fa.get_params(), fb.get_params())
+    assert not np.array_equal(fa.get_params(), fc.get_params())
 
 
 @pytest.mark.parametrize("d,n", [(10, 3001), (4, 3000), (13, 700)])
@@ -377,3 +399,30 @@ def test_training_is_bitwise_reproducible():
     assert np.array_equal(res[0][0], res[1][0])
     assert np.array_equal(res[0][1], res[1][1])
     assert res[0][2] == res[1][2] and res[0][3] == res[1][3]
+
+
+def test_flow_learns_a_correlated_target_a_separable_grid_cannot():
+    """Two diagonal ridges in 4 dimensions: every one-dimensional marginal is
+    flat, so a separable (VEGAS) grid cannot improve on uniform sampling.
+    The flow, trained on uniform points with these weights, samples them with
+    a much smaller relative variance and an unbiased mean."""
+    d, s2 = 4, 0.05 ** 2
+
+    def target(y):
+        return torch.exp(-((y[0] - y[1]) ** 2) / (2 * s2) - ((y[2] + y[3] - 1.0) ** 2) / (2 * s2))
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(si.BASE_SEED)
+    y = torch.rand((d, 200_000), dtype=torch.float32, device="cuda", generator=g)
+    w = target(y.double()).float()
+    f = mf.Flow(d, max_batch=16384)
+    f.train(y, w, epochs=30, batch=16384, lr=3e-3, lr_final=1e-5)
+    u = torch.rand((d, 400_000), dtype=torch.float32, device="cuda", generator=g)
+    pu = target(u.double())
+    rel_uniform = float(pu.var() / pu.mean() ** 2)
+    yq, lq = f.inverse(u)
+    r = target(yq.double()) / torch.exp(lq.double())
+    rel_flow = float(r.var() / r.mean() ** 2)
+    assert rel_flow < 0.2 * rel_uniform, (rel_flow, rel_uniform)
+    err = float(np.sqrt(pu.var().item() / pu.numel() + r.var().item() / r.numel()))
+    assert abs(r.mean().item() - pu.mean().item()) < 4 * err, (r.mean().item(), pu.mean().item(), err)
