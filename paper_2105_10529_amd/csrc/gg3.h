@@ -1,0 +1,370 @@
+// g g -> t t~ g g g: staged evaluation of the integrand (HIP, gfx950).
+//
+// With 120 colour orderings and 128 helicity states per event the partial
+// amplitudes of one event do not fit in registers next to the colour
+// quadratic form, so the evaluation of a batch of points is split:
+//
+//  1. k_g3_select: kinematics, cuts and PDFs of every point (FP64); the
+//     weight without |M|^2 is kept, and the indices of the events that pass
+//     the cuts are compacted into a list, so the amplitudes run on passing
+//     events only.
+//  2. k_g3_amp: per passing event (one lane each), the colour-ordered partial
+//     amplitudes of a group of polarisation states (generated per-ordering
+//     Berends-Giele code, amp_gg_m5), streamed to an HBM buffer laid out as
+//     [slice][ordering / 4][event][ordering % 4].
+//  3. k_g3_colour: the colour sum |M|^2 = sum_states Re(A^dagger C A) with
+//     the exact 120 x 120 colour matrix on the matrix cores
+//     (v_mfma_f32_16x16x4_f32): per slice, Z = C A for a tile of 32 events,
+//     then the dot product A . Z in the epilogue; the operand values loaded
+//     for the product are the ones the dot product needs, so each amplitude
+//     is read once.
+//
+// This is the event weight of Sec. 2.1 (phase space -> matrix element) with
+// the colour-ordered amplitudes and colour matrix of Sec. 2.2, evaluated in
+// the three-kernel order above; the result of each event does not depend on
+// the lane or the position in the compacted list that evaluates it.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "amp.h"
+#include "gen/amp_gg_m5.h"
+#include "launch.h"
+#include "pipeline.h"
+
+namespace mf {
+namespace g3 {
+
+constexpr int NG = 3;
+constexpr int NF = AMP_M5_NF;          // 120 orderings
+constexpr int NQ = AMP_M5_NQ;          // 32 groups of four (padded to 128)
+constexpr int STATES = AMP_M5_STATES;  // 64 = 2 antitop helicities x 2^5 gluon polarisations
+constexpr int SP = 8;                  // states per amplitude pass
+constexpr int SLICES = SP * 4;         // (state, top helicity, re/im) per pass
+constexpr int AWAVE = 64;              // amplitude kernel block: one wave (LDS tables per wave)
+constexpr int CT = 32;                 // events per colour tile (two 16-column MFMA blocks)
+constexpr int CBLOCK = 256;            // colour kernel block: 4 waves x 8 slices
+constexpr int CMAX_BLOCKS = 512;       // two 65-KB-LDS blocks per CU
+constexpr int64_t NCMAX = 131072;      // passing events per chunk (fills 256 CUs x 2 waves x 4 SIMDs)
+
+// Workspace owned by the process handle (grown on demand, freed with it).
+struct Ws {
+  int64_t cap_n = 0;  // points: idx, wpre
+  int64_t ld = 0;     // chunk columns of the amplitude buffer (multiple of AWAVE)
+  size_t amp_bytes = 0;
+  int* d_idx = nullptr;
+  int* d_count = nullptr;
+  double* d_wpre = nullptr;
+  double* d_me = nullptr;  // [ld] colour-summed |M|^2 numerators of the chunk
+  void* d_amp = nullptr;   // [SLICES][NQ][ld][4] amplitude type
+};
+
+// Kinematics, cuts and the event weight without |M|^2 (same steps and
+// factors as event_weight for the g g channel).
+__device__ __forceinline__ bool kinematics(const DevCfg& c, const double* x, double& shat_k, V4<double>* gl,
+                                           V4<double>& top, V4<double>& atop, double& wps) {
+  const double x1 = x[0], x2 = x[1];
+  const double shat = x1 * x2 * c.s;
+  const double thr = 4.0 * c.mt * c.mt;
+  bool ok = shat > thr;
+  shat_k = ok ? shat : thr * (1.0 + 1e-3);
+  wps = phase_space<double>(NG, x, shat_k, c.mt, gl, top, atop);
+  ok = ok && (wps > 0.0);
+  return ok && pass_cuts(c, NG, gl, 0.5 * log(x1 / x2));
+}
+
+__global__ void k_g3_zero(int* count) { *count = 0; }
+
+__global__ void __launch_bounds__(BLOCK) k_g3_select(DevCfg c, const double* __restrict__ u, int64_t n,
+                                                     double* __restrict__ w, double* __restrict__ wpre,
+                                                     int* __restrict__ idx, int* __restrict__ count) {
+  const int64_t e0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const bool live = e0 < n;
+  const int64_t e = live ? e0 : n - 1;
+  double x[MAXD];
+#pragma unroll
+  for (int j = 0; j < MAXD; ++j)
+    if (j < c.ndim) x[j] = u[(int64_t)j * n + e];
+  double shat_k, wps;
+  V4<double> gl[NG], top, atop;
+  bool ok = kinematics(c, x, shat_k, gl, top, atop, wps);
+  const double pre = c.norm / (2.0 * shat_k * x[0] * x[1]) * wps *
+                     (hermite_x(c.pdfc, x_position(c, x[0])) * hermite_x(c.pdfc, x_position(c, x[1])));
+  ok = ok && live && isfinite(pre) && pre != 0.0;
+  if (live) {
+    w[e] = 0.0;
+    wpre[e] = ok ? pre : 0.0;
+  }
+  // compaction: one atomic per wave, ranks from the ballot
+  const unsigned long long b = __ballot(ok);
+  const int lane = threadIdx.x & 63;
+  const int rank = __popcll(b & ((1ull << lane) - 1ull));
+  int base = 0;
+  if (lane == 0 && b != 0ull) base = atomicAdd(count, __popcll(b));
+  base = __shfl(base, 0);
+  if (ok) idx[base + rank] = (int)e;
+}
+
+// One colour-ordered partial amplitude for both top helicities: the gluon
+// currents J(a..b) of every contiguous range of positions (Berends-Giele,
+// three- and four-gluon vertices), the top-line spinor currents of every
+// suffix closed by the top propagator, and the final contraction with
+// ubar(top) (the same steps, in the same order of terms, as the per-ordering
+// amplitudes of the smaller processes).  Jp/kp: external current and
+// momentum at each position; g[r]: propagator factor of range r in
+// AMP_M5_RANGE order; iq[j]: factor of the suffix starting at position j + 1.
+template <class R>
+__device__ __forceinline__ void ordering_amp(const V4<R> (&Jp)[5], const V4<R> (&kp)[5], const R (&g)[10],
+                                             const R (&iq)[4], const Sp<R>& V, const V4<R>& pb, R MT,
+                                             const Sp<R>* UB, C2<R>& A0, C2<R>& A1) {
+  V4<R> J[5][5], P[5][5];
+#pragma unroll
+  for (int a = 0; a < 5; ++a) {
+    J[a][a] = Jp[a];
+    P[a][a] = kp[a];
+  }
+  int r = 0;  // range index in AMP_M5_RANGE order: by length, then start
+#pragma unroll
+  for (int len = 2; len <= 5; ++len)
+#pragma unroll
+  for (int a = 0; a + len <= 5; ++a, ++r) {
+    const int b = a + len - 1;
+    P[a][b] = P[a][b - 1] + kp[b];
+    V4<R> t3 = v3(J[a][a], J[a + 1][b], P[a][a], P[a + 1][b]);
+#pragma unroll
+    for (int j = a + 1; j < b; ++j) t3 = t3 + v3(J[a][j], J[j + 1][b], P[a][j], P[j + 1][b]);
+    if (b - a >= 2) {
+      V4<R> t4 = w4(J[a][a], J[a + 1][a + 1], J[a + 2][b]);
+      bool first = true;
+#pragma unroll
+      for (int j = a; j < b - 1; ++j)
+#pragma unroll
+        for (int l = j + 1; l < b; ++l) {
+          if (first) {
+            first = false;
+            continue;
+          }
+          t4 = t4 + w4(J[a][j], J[j + 1][l], J[l + 1][b]);
+        }
+      J[a][b] = g[r] * (t3 - t4);
+    } else {
+      J[a][b] = g[r] * t3;
+    }
+  }
+  Sp<R> S[6];
+  S[5] = V;
+#pragma unroll
+  for (int a = 4; a >= 1; --a) {
+    Sp<R> acc = slash(J[a][a], S[a + 1]);
+#pragma unroll
+    for (int j = a + 1; j < 5; ++j) acc = acc + slash(J[a][j], S[j + 1]);
+    S[a] = prop(R(-1.0) * (pb + P[a][4]), MT, iq[a - 1], acc);
+  }
+  Sp<R> F = slash(J[0][0], S[1]);
+#pragma unroll
+  for (int j = 1; j < 5; ++j) F = F + slash(J[0][j], S[j + 1]);
+  A0 = ubar_dot(UB[0], F);
+  A1 = ubar_dot(UB[1], F);
+}
+
+// Partial amplitudes of states s0 .. s0 + SP - 1 for the passing events
+// idx[0 .. nc-1] of this chunk, written to
+//   amp[((slice * NQ + ordering / 4) * ld + j) * 4 + ordering % 4]
+// with slice = ((state - s0) * 2 + top helicity) * 2 + (0: re, 1: im) and
+// j the event's column (orderings 120..127 are written as zeros).  Lanes
+// past nc recompute the last event into columns below ld, never read as
+// results.  The propagator factors of every gluon subset are formed in FP64
+// from the FP64 momenta and kept per lane in LDS, indexed by subset.
+template <class R>
+__global__ void __launch_bounds__(AWAVE) k_g3_amp(DevCfg c, const double* __restrict__ u, int64_t n,
+                                                  const int* __restrict__ idx, int64_t nc, int s0,
+                                                  R* __restrict__ amp, int64_t ld) {
+  // Per-lane tables (each lane reads only its own column, so no barriers):
+  __shared__ R gtab[32][AWAVE];        // -1 / P_S^2 for gluon subsets S (>= 2 gluons)
+  __shared__ R qtab[32][AWAVE];        // -1 / ((p_tb + P_S)^2 - m_t^2) for S != all
+  __shared__ V4<R> etab[10][AWAVE];    // polarisation vectors: gluon i, polarisation p at 2 i + p
+  __shared__ V4<R> ktab[5][AWAVE];     // gluon momenta in the amplitude type
+  __shared__ Sp<R> vtab[2][AWAVE];     // v(antitop) for both helicities
+  const int lane = threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * AWAVE + lane;
+  const int64_t e = idx[j < nc ? j : nc - 1];
+  double x[MAXD];
+#pragma unroll
+  for (int k = 0; k < MAXD; ++k)
+    if (k < c.ndim) x[k] = u[(int64_t)k * n + e];
+  double shat_k, wps;
+  V4<double> gl[NG], top, atop;
+  (void)kinematics(c, x, shat_k, gl, top, atop, wps);
+  // external states as in me_gg: incoming beams as outgoing momenta with
+  // fixed linear polarisations, final gluons with lin_pols, top spinors of
+  // both helicities
+  const double E = 0.5 * sqrt(shat_k);
+  V4<double> K[NG + 2];
+  V4<R> Ep[NG + 2][2];
+  K[0] = V4<double>{-E, 0.0, 0.0, -E};
+  K[1] = V4<double>{-E, 0.0, 0.0, E};
+  const R z = R(0.0), o = R(1.0);
+  Ep[0][0] = V4<R>{z, o, z, z};
+  Ep[0][1] = V4<R>{z, z, o, z};
+  Ep[1][0] = V4<R>{z, o, z, z};
+  Ep[1][1] = V4<R>{z, z, o, z};
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    K[2 + i] = gl[i];
+    lin_pols(cvt4<R>(K[2 + i]), Ep[2 + i]);
+  }
+  for (int S = 1; S < 32; ++S) {
+    V4<double> P{0.0, 0.0, 0.0, 0.0};
+    bool firstk = true;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+      if ((S >> i) & 1) {
+        P = firstk ? K[i] : P + K[i];
+        firstk = false;
+      }
+    gtab[S][lane] = __popc(S) >= 2 ? cvt<R>(-1.0 / mdot(P, P)) : R(0.0);
+    qtab[S][lane] = S != 31 ? cvt<R>(-1.0 / (2.0 * mdot(atop, P) + mdot(P, P))) : R(0.0);
+  }
+  const R MT = cvt<R>(c.mt);
+  const V4<R> t = cvt4<R>(top), PB = cvt4<R>(atop);
+  const Sp<R> UB[2] = {ubar_spinor(t, MT, -1), ubar_spinor(t, MT, 1)};
+  vtab[0][lane] = v_spinor(PB, MT, -1);
+  vtab[1][lane] = v_spinor(PB, MT, 1);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    ktab[i][lane] = cvt4<R>(K[i]);
+    etab[2 * i][lane] = Ep[i][0];
+    etab[2 * i + 1][lane] = Ep[i][1];
+  }
+  const int64_t sstride = (int64_t)NQ * ld * 4;
+  R* out = amp + j * 4;
+#pragma unroll 1
+  for (int st = s0; st < s0 + SP; ++st) {
+    const int ht = st >> 5, hg = st & 31;
+    const Sp<R> V = vtab[ht][lane];
+    R* o4 = out + (int64_t)((st - s0) * 4) * sstride;
+#pragma unroll 1
+    for (int k = 0; k < NF; ++k) {
+      V4<R> Jp[5], kp[5];
+      R gr[10], iq[4];
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        const int sg = AMP_M5_SIGMA[k][i];
+        Jp[i] = etab[2 * sg + ((hg >> (4 - sg)) & 1)][lane];
+        kp[i] = ktab[sg][lane];
+      }
+#pragma unroll
+      for (int r = 0; r < 10; ++r) gr[r] = gtab[AMP_M5_GMASK[k][r]][lane];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) iq[r] = qtab[AMP_M5_QMASK[k][r]][lane];
+      C2<R> a0, a1;
+      ordering_amp<R>(Jp, kp, gr, iq, V, PB, MT, UB, a0, a1);
+      R* p = o4 + (int64_t)(k >> 2) * ld * 4 + (k & 3);
+      p[0] = a0.re;
+      p[sstride] = a0.im;
+      p[2 * sstride] = a1.re;
+      p[3 * sstride] = a1.im;
+    }
+    // zero padding of the orderings NF .. 4 NQ - 1
+#pragma unroll 1
+    for (int k = NF; k < 4 * NQ; ++k) {
+      R* p = o4 + (int64_t)(k >> 2) * ld * 4 + (k & 3);
+      p[0] = R(0.0);
+      p[sstride] = R(0.0);
+      p[2 * sstride] = R(0.0);
+      p[3 * sstride] = R(0.0);
+    }
+  }
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 load_f4(const float* p) { return *reinterpret_cast<const f4*>(p); }
+
+// Colour sum of one pass over the SLICES slices of the buffer for the nc
+// events of the chunk.  C in LDS in A-operand order: entry
+// ((rb * 8 + s) * 64 + l) * 4 + r holds C[16 rb + l % 16][16 s + 4 (l / 16) + r]
+// (zero beyond the 120 orderings).  For the MFMA step (s, r) lane l supplies
+// that entry and B[16 s + 4 (l / 16) + r][event l % 16], so the four lanes
+// groups cover colour indices 16 s .. 16 s + 15 over the four r; the result
+// lane l holds Z[16 rb + 4 (l / 16) + i][event l % 16], whose matching
+// amplitudes are the B values the lane loaded for s = rb.
+// first: the pass overwrites me[]; last: it also writes the event weights.
+__global__ void __launch_bounds__(CBLOCK) k_g3_colour(const float* __restrict__ amp, int64_t ld, int64_t nc,
+                                                      int first, int last, double* __restrict__ me,
+                                                      const int* __restrict__ idx, const double* __restrict__ wpre,
+                                                      double* __restrict__ w, double inv_den) {
+  __shared__ float cs[8 * 8 * 64 * 4];
+  __shared__ double part[CBLOCK / 64][CT];
+  for (int i = threadIdx.x; i < 8 * 8 * 64 * 4; i += CBLOCK) {
+    const int r = i & 3, l = (i >> 2) & 63, s = (i >> 8) & 7, rb = i >> 11;
+    const int row = 16 * rb + (l & 15), col = 16 * s + 4 * (l >> 4) + r;
+    cs[i] = (row < NF && col < NF) ? AMP_M5_COLOUR[row * NF + col] : 0.0f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
+  const int64_t ntile = (nc + CT - 1) / CT;
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t c0 = tile * CT;
+    double sum[2] = {0.0, 0.0};
+#pragma unroll 1
+    for (int sl = wave * (SLICES / 4); sl < (wave + 1) * (SLICES / 4); ++sl) {
+      const float* base = amp + (int64_t)sl * NQ * ld * 4;
+      f4 bv[8][2];
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          bv[s][cb] = load_f4(base + ((int64_t)(4 * s + g) * ld + c0 + 16 * cb + c16) * 4);
+      float acc[2] = {0.0f, 0.0f};
+#pragma unroll
+      for (int rb = 0; rb < 8; ++rb) {
+        f4 zz[2] = {f4{0.0f, 0.0f, 0.0f, 0.0f}, f4{0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const f4 a = *reinterpret_cast<const f4*>(&cs[((rb * 8 + s) * 64 + lane) * 4]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+              zz[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], bv[s][cb][r], zz[cb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[cb] = fmaf(zz[cb][i], bv[rb][cb][i], acc[cb]);
+      }
+      sum[0] += (double)acc[0];
+      sum[1] += (double)acc[1];
+    }
+    // the four lane groups hold disjoint rows of the same events
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      sum[cb] += __shfl_xor(sum[cb], 16);
+      sum[cb] += __shfl_xor(sum[cb], 32);
+    }
+    if (g == 0) {
+      part[wave][c16] = sum[0];
+      part[wave][16 + c16] = sum[1];
+    }
+    __syncthreads();
+    if (threadIdx.x < CT) {
+      const int64_t col = c0 + threadIdx.x;
+      if (col < nc) {
+        double v = part[0][threadIdx.x];
+#pragma unroll
+        for (int q = 1; q < CBLOCK / 64; ++q) v += part[q][threadIdx.x];
+        if (!first) v += me[col];
+        me[col] = v;
+        if (last) {
+          const int e = idx[col];
+          const double we = wpre[e] * (v * inv_den);
+          w[e] = isfinite(we) ? we : 0.0;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace g3
+}  // namespace mf

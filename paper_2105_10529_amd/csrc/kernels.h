@@ -297,6 +297,8 @@ Launchers make_launchers() {
   };
   L.integrand_grad = nullptr;
   L.grad_vegas = nullptr;
+  L.integrand_ws = nullptr;
+  L.ws_free = nullptr;
   if constexpr (GRAD != 0) {
     L.integrand_grad = [](const DevCfg& c, const double* u, int64_t n, double* w, double* dw, int nblk,
                           hipStream_t s) {

@@ -73,6 +73,12 @@ struct Launchers {
   void (*integrand_grad)(const DevCfg&, const double*, int64_t, double*, double*, int, hipStream_t);
   void (*vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, int, size_t, hipStream_t);
   void (*grad_vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, size_t, hipStream_t);
+  // Multi-kernel integrand with a workspace held by the process handle
+  // (*ws, created on first use, released with ws_free); used instead of
+  // `integrand` when set.  Synchronises the stream (it reads the number of
+  // events that pass the cuts).
+  hipError_t (*integrand_ws)(const DevCfg&, const double*, int64_t, double*, void**, hipStream_t);
+  void (*ws_free)(void*);
 };
 
 // One per built instance: g g -> t t~ + ng g in FP64 / FP32 amplitudes, and
@@ -85,5 +91,6 @@ Launchers launchers_gg2_f64();
 Launchers launchers_gg2_f32();
 Launchers launchers_uu_f64();
 Launchers launchers_dd_f64();
+Launchers launchers_gg3_f32();
 
 }  // namespace mf

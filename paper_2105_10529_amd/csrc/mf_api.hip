@@ -500,6 +500,7 @@ struct mf_process {
   float* d_slq = nullptr;          // [cap] flow log-density
   float* d_sz = nullptr;           // [ndim][cap] scratch for the flow's density pass
   float* d_sw32 = nullptr;         // [3][cap] on-policy training weights
+  void* ws = nullptr;              // workspace of a multi-kernel integrand (Launchers::integrand_ws)
 };
 
 namespace {
@@ -539,6 +540,7 @@ Launchers pick_launchers(int ng, int ch, int prec) {
   if (ch == 2) return launchers_dd_f64();
   if (ng == 0) return f32 ? launchers_gg0_f32() : launchers_gg0_f64();
   if (ng == 1) return f32 ? launchers_gg1_f32() : launchers_gg1_f64();
+  if (ng == 3) return launchers_gg3_f32();
   return f32 ? launchers_gg2_f32() : launchers_gg2_f64();
 }
 
@@ -546,6 +548,19 @@ mf_status check_stream_launch(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MF_EDEVICE, "%s launch: %s", what, hipGetErrorString(e));
   return MF_OK;
+}
+
+// The integrand of the process on n mapped points (single-kernel or staged).
+mf_status run_integrand(mf_process* p, const double* x, int64_t n, double* w, hipStream_t s) {
+  if (p->L.integrand_ws) {
+    hipError_t e = p->L.integrand_ws(p->dc, x, n, w, &p->ws, s);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      return fail(MF_ENOMEM, "integrand workspace allocation failed");
+    if (e != hipSuccess) return fail(MF_EDEVICE, "integrand: %s", hipGetErrorString(e));
+    return MF_OK;
+  }
+  p->L.integrand(p->dc, x, n, w, blocks_for(n), s);
+  return check_stream_launch("k_integrand");
 }
 
 // Grow the staging buffers of the handle to n events.
@@ -632,7 +647,8 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
   double mu = cfg->mu > 0.0 ? cfg->mu : cfg->m_t;
   if (!(mu >= PDF_Q0 && mu <= PDF_QMAX)) return fail(MF_ERANGE, "scale %g outside the PDF grid", mu);
   const int ng = n_final_gluons(cfg->process);
-  if (ng == 3) return fail(MF_ENOTSUP, "g g -> t t~ g g g is not built");
+  if (ng == 3 && cfg->precision != MF_PREC_FP32_AMP)
+    return fail(MF_ENOTSUP, "g g -> t t~ g g g is built with FP32 amplitudes only");
   if (channel_of(cfg->process) != 0 && cfg->precision != MF_PREC_FP64)
     return fail(MF_ENOTSUP, "quark channels are built in FP64 only");
   for (int i = 0; i < 20; i += 5)
@@ -710,6 +726,7 @@ void mf_process_destroy(mf_process* p) {
   hipFree(p->d_slq);
   hipFree(p->d_sz);
   hipFree(p->d_sw32);
+  if (p->ws && p->L.ws_free) p->L.ws_free(p->ws);
   delete p;
 }
 
@@ -719,10 +736,7 @@ mf_status mf_integrand(mf_process* p, const double* u, int64_t n, double* w, voi
   if (n < 0) return fail(MF_EINVAL, "negative event count");
   if (n == 0) return MF_OK;
   if (!u || !w) return fail(MF_EINVAL, "NULL buffer");
-  hipStream_t s = (hipStream_t)stream;
-  const int nblk = blocks_for(n);
-  p->L.integrand(p->dc, u, n, w, nblk, s);
-  return check_stream_launch("k_integrand");
+  return run_integrand(p, u, n, w, (hipStream_t)stream);
 }
 
 mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w, double* dw, void* stream) {
@@ -803,7 +817,8 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
       const int64_t N = o->n_events;
       mf_status sst = stage_sample(p, o->flow, o->flow_mix, iter, N, nullptr, s);
       if (sst != MF_OK) return sst;
-      p->L.integrand(p->dc, p->d_sx, N, p->d_sw, nblk, s);
+      sst = run_integrand(p, p->d_sx, N, p->d_sw, s);
+      if (sst != MF_OK) return sst;
       hipLaunchKernelGGL(k_stage_accumulate, dim3(nblk), dim3(256), 0, s, p->d_sw, p->d_sjac, p->d_sbins, d, nb, N,
                          p->d_part, p->pstride);
     } else if (p->L.fused) {
@@ -812,7 +827,8 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
       const int64_t N = o->n_events;
       hipLaunchKernelGGL(k_stage_points, dim3(nblk), dim3(256), sizeof(double) * d * (nb + 1), s, p->d_edges, d, nb,
                          iter, N, p->cfg.seed, p->d_sx, p->d_sjac, p->d_sbins);
-      p->L.integrand(p->dc, p->d_sx, N, p->d_sw, nblk, s);
+      mf_status sst = run_integrand(p, p->d_sx, N, p->d_sw, s);
+      if (sst != MF_OK) return sst;
       hipLaunchKernelGGL(k_stage_accumulate, dim3(nblk), dim3(256), 0, s, p->d_sw, p->d_sjac, p->d_sbins, d, nb, N,
                          p->d_part, p->pstride);
     }
@@ -911,8 +927,8 @@ mf_status mf_weights(mf_process* p, mf_flow* flow, double flow_mix, uint64_t ite
   if (st != MF_OK) return st;
   st = stage_sample(p, flow, flow_mix, iter, n, y_out, s);
   if (st != MF_OK) return st;
-  const int nblk = blocks_for(n);
-  p->L.integrand(p->dc, p->d_sx, n, p->d_sw, nblk, s);
+  st = run_integrand(p, p->d_sx, n, p->d_sw, s);
+  if (st != MF_OK) return st;
   hipLaunchKernelGGL(k_weight, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->d_sw, p->d_sjac, n, w_out);
   return check_stream_launch("k_weight");
 }
@@ -989,7 +1005,8 @@ mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_onlin
   for (int t = 0; t < o->steps; ++t) {
     st = stage_sample(p, flow, o->flow_mix, o->iter_offset + (uint64_t)t, n, nullptr, s);
     if (st != MF_OK) return st;
-    p->L.integrand(p->dc, p->d_sx, n, p->d_sw, nblk, s);
+    st = run_integrand(p, p->d_sx, n, p->d_sw, s);
+    if (st != MF_OK) return st;
     hipLaunchKernelGGL(k_online_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->d_sw, p->d_sjac,
                        p->d_slq, o->flow_mix, n, o->loss == MF_FLOW_LOSS_VARIANCE ? 1 : 0, wt, rw, r2);
     hipLaunchKernelGGL(k_batch_relvar, dim3(1), dim3(1024), 0, s, rw, r2, n, d_loss + 2 * t, d_sums + 2 * t);
