@@ -8,9 +8,10 @@ iterations adapt the grid; the timed iterations continue the same run.
 
 Prints one JSON line (value = events/s of the whole job, inputs generated in
 the kernel).  The roofline entry prices the fused per-event kernel's
-algorithmic FP64 flops (the emitted amplitude recursion, counted statically)
-against the MI355X FP64 vector peak, using the kernel time the library
-measures with HIP events on the call's stream.  The CPU baseline times the
+algorithmic FP64 flops (the emitted amplitude recursion, counted statically,
+for each event that passes the cuts: the kernel evaluates the matrix element
+of those events only) against the MI355X FP64 vector peak, using the kernel
+time the library measures with HIP events on the call's stream.  The CPU baseline times the
 FP64 oracle on a bounded sample of the same event stream.
 """
 from __future__ import annotations
@@ -33,7 +34,7 @@ EVENTS = 10_000_000
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy
 # calibration (profiles/traffic_k_vegas_gg_ttg_fp64_1e7.md).  Set to None when
 # that kernel changes until the counters are taken again.
-MEASURED_TRAFFIC_BYTES = 20.12e6
+MEASURED_TRAFFIC_BYTES = None
 
 
 def flops_per_event(m: int) -> int:
@@ -69,18 +70,22 @@ def _eff(stats: dict) -> dict:
 
 
 def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_000, steps: int = 30,
-                    flow_iter_events: int = 4_000_000, vegas: bool = True) -> dict:
-    """g g -> t t~ g g (Delta R > 0.4): wall time from process creation to a
-    relative error of 1e-3, for plain VEGAS in FP64, plain VEGAS with FP32
-    amplitudes, and FP32 amplitudes with the learned proposal: VEGAS warm-up
+                    flow_iter_events: int = 4_000_000, vegas: bool = True, process: str = "gg>ttxgg",
+                    precisions=("fp64", "fp32"), long_steps: int = 300, batch: int = 65536,
+                    lr: float = 5e-3) -> dict:
+    """g g -> t t~ g g (or g g g; Delta R > 0.4): wall time from process
+    creation to a relative error of 1e-3, for plain VEGAS in FP64 (where
+    built), plain VEGAS with FP32 amplitudes, and FP32 amplitudes with the
+    learned proposal: VEGAS warm-up
     5 x 1e6, `steps` on-policy variance-training steps of the flow (65536
     points per step, sampled from the flow mixed with 20% uniform points on
     the frozen grid), whose batches are themselves estimates of the integral
     (pooled per 50 steps and combined by inverse variance, stopping at 1e-3),
     then iterations of flow_iter_events points of the trained proposal
     combined with that estimate until 1e-3 (30 steps is the fastest setting
-    measured to this target; longer training lowers the variance further,
-    which a second, untimed flow trained for 300 steps shows).
+    measured to this target on g g -> t t~ g g; longer training lowers the
+    variance further, which a second, untimed flow trained for long_steps
+    steps shows).
     Also the per-event relative variance and the unweighting efficiency of
     each proposal on a fresh sample of eval_events with the final grid."""
     import torch
@@ -88,11 +93,11 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
     import paper_2105_10529_amd as mf
 
     def cfg(prec):
-        return mf.Config(process="gg>ttxgg", precision=prec, dr_min=0.4)
+        return mf.Config(process=process, precision=prec, dr_min=0.4)
 
-    # load every kernel of the three pipelines once (untimed), so that no timing
+    # load every kernel of the pipelines once (untimed), so that no timing
     # below includes one-time code-object loading
-    for prec in ("fp64", "fp32"):
+    for prec in precisions:
         w = mf.Process(cfg(prec))
         w.integrate(2, 20_000, adapt=True)
         if prec == "fp32":
@@ -104,7 +109,7 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
         del w
     torch.cuda.synchronize()
     res = {}
-    for prec in (("fp64", "fp32") if vegas else ()):
+    for prec in (precisions if vegas else ()):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         p = mf.Process(cfg(prec))
@@ -125,9 +130,9 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
     p.integrate(5, 1_000_000, adapt=True)
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
-    f = mf.Flow(p.ndim, max_batch=65536)
+    f = mf.Flow(p.ndim, max_batch=batch)
     mix, group = 0.2, 50
-    rel, est = p.train_flow_online(f, steps, batch=65536, lr=5e-3, loss="variance", flow_mix=mix,
+    rel, est = p.train_flow_online(f, steps, batch=batch, lr=lr, loss="variance", flow_mix=mix,
                                    group_steps=group, target_rel_err=1e-3, with_estimate=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0 - t_warm
@@ -144,15 +149,17 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
     wv, _ = p.weights(1 << 30, eval_events)
     sv = mf.weight_stats(wv)
     del wv
-    # attainable variance: the same recipe trained for 300 steps (untimed)
-    f300 = mf.Flow(p.ndim, max_batch=65536)
-    p.train_flow_online(f300, 300, batch=65536, lr=5e-3, loss="variance", flow_mix=mix, iter_offset=1 << 26)
+    # attainable variance: the same recipe trained for long_steps steps (untimed)
+    f300 = mf.Flow(p.ndim, max_batch=batch)
+    p.train_flow_online(f300, long_steps, batch=batch, lr=lr, loss="variance", flow_mix=mix,
+                        iter_offset=1 << 26)
     w3, _ = p.weights(1 << 30, eval_events, flow=f300, flow_mix=mix)
     s3 = mf.weight_stats(w3)
     del w3, f300
     res["fp32_flow"] = {"time_to_1e-3_s": t, "time_excluding_training_s": t - t_train, "warmup_s": t_warm,
                         "training_s": t_train, "training_steps_done": int(np.count_nonzero(rel)),
-                        "training_batch": 65536, "training_estimate_pb": [est.integral, est.error],
+                        "training_batch": batch, "learning_rate": lr,
+                        "training_estimate_pb": [est.integral, est.error],
                         "training_events": est.n_events_total,
                         "iterations_after_training": r.n_iter_done if r is not est else 0,
                         "events_after_training": r.n_events_total if r is not est else 0,
@@ -161,8 +168,56 @@ def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_0
                         "relative_variance_per_event": sf["relvar"],
                         "relative_variance_per_event_vegas_same_grid": sv["relvar"],
                         "unweighting": _eff(sf), "unweighting_vegas_same_grid": _eff(sv),
-                        "trained_300_steps": {"relative_variance_per_event": s3["relvar"], "unweighting": _eff(s3)}}
+                        f"trained_{long_steps}_steps": {"relative_variance_per_event": s3["relvar"],
+                                                        "unweighting": _eff(s3)}}
     return res
+
+
+FP32_VECTOR_PEAK = 157.3e12  # MI355X FP32 vector FLOP/s (published; packed FP32 instructions)
+FP32_MATRIX_PEAK = 157.3e12  # MI355X FP32 matrix-core FLOP/s (dense)
+
+
+def ttggg_throughput(events: int = 4_000_000, iters: int = 3) -> dict:
+    """g g -> t t~ g g g with FP32 amplitudes: events/s of staged VEGAS
+    iterations (after a warm-up that adapts the grid), and the algorithmic
+    FLOP/s of the amplitude and colour kernels from their statically counted
+    flops per passing event and the kernel times of the iterations (HIP events
+    around each iteration's integrand)."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+
+    sys.path.insert(0, os.path.join(ROOT, "paper_2105_10529_amd", "gen"))
+    import gen_me
+
+    fc = gen_me.amp_flop_count(5)
+    p = mf.Process(mf.Config(process="gg>ttxggg", precision="fp32", dr_min=0.4))
+    p.integrate(3, 1_000_000, adapt=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = p.integrate(iters, events, adapt=True, iter_offset=3)
+    dt = time.perf_counter() - t0
+    passing = r.n_nonzero
+    amp_flops = passing * fc["states"] * fc["amplitudes_per_state"]
+    col_flops = passing * fc["states"] * fc["colour_per_state"]
+    return {"events_per_s": iters * events / dt, "events_per_iteration": events, "cut_efficiency": passing /
+            max(r.n_events_total, 1), "integral_pb": r.integral, "error_pb": r.error,
+            "iteration_kernels_ms_avg": 1e3 * r.kernel_seconds / iters,
+            "flops_per_passing_event": fc["total"],
+            "algorithmic_tflops_whole_integrand": (amp_flops + col_flops) / r.kernel_seconds / 1e12,
+            "amplitude_flops_per_passing_event": fc["states"] * fc["amplitudes_per_state"],
+            "colour_flops_per_passing_event": fc["states"] * fc["colour_per_state"]}
+
+
+def ttggg_flow_comparison() -> dict:
+    """The learned-proposal comparison on g g -> t t~ g g g (13 dims; FP32
+    amplitudes, so FP32 VEGAS is the baseline): iterations of 4e6 events, 60
+    training steps of 65536 points (the fastest of 30/60 steps x 65536 and
+    120 x 32768 measured; a learning rate of 1e-2 trained worse or diverged),
+    flow iterations of 2e6 points, and a 150-step flow for the attainable
+    variance."""
+    return flow_comparison(4_000_000, 4_000_000, 60, 2_000_000, process="gg>ttxggg", precisions=("fp32",),
+                           long_steps=150)
 
 
 def fp32_subsample_check(n: int = 100_000) -> dict:
@@ -286,6 +341,8 @@ def secondary(seed_events: int) -> dict:
         }
     out["ttgg_fp32_vs_oracle_subsample"] = fp32_subsample_check()
     out["ttgg_flow_vs_vegas"] = flow_comparison()
+    out["ttggg_fp32"] = ttggg_throughput()
+    out["ttggg_flow_vs_vegas"] = ttggg_flow_comparison()
     out["flow_roofline"] = flow_roofline()
     grads = {}
     for mt in (171.0, 173.0, 175.0):
@@ -311,11 +368,13 @@ def main() -> int:
     ap.add_argument("--events", type=int, default=EVENTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--workload", choices=("ttg", "ttgg"), default="ttg",
-                    help="ttg: g g -> t t~ g FP64 (the reported workload); ttgg: g g -> t t~ g g with FP32 "
-                         "amplitudes (profiling runs)")
+    ap.add_argument("--workload", choices=("ttg", "ttgg", "ttggg"), default="ttg",
+                    help="ttg: g g -> t t~ g FP64 (the reported workload); ttgg, ttggg: g g -> t t~ g g (g) with "
+                         "FP32 amplitudes (profiling runs)")
     ap.add_argument("--flow-only", action="store_true",
                     help="only run the g g -> t t~ g g learned-proposal comparison and the flow roofline (profiling)")
+    ap.add_argument("--ttggg-only", action="store_true",
+                    help="only run the g g -> t t~ g g g throughput and learned-proposal measurements (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (to calibrate HBM counters) and exit")
     args = ap.parse_args()
@@ -341,14 +400,20 @@ def main() -> int:
     if args.flow_only:
         print(json.dumps({"ttgg_flow_vs_vegas": flow_comparison(), "flow_roofline": flow_roofline()}), flush=True)
         return 0
-    if args.workload == "ttgg":
-        p = mf.Process(mf.Config(process="gg>ttxgg", precision="fp32", dr_min=0.4))
+    if args.ttggg_only:
+        print(json.dumps({"ttggg_fp32": ttggg_throughput(),
+                          "ttggg_flow_vs_vegas": ttggg_flow_comparison()}), flush=True)
+        return 0
+    if args.workload in ("ttgg", "ttggg"):
+        proc = "gg>ttx" + args.workload[2:]
+        p = mf.Process(mf.Config(process=proc, precision="fp32", dr_min=0.4))
         if args.warmup:
             p.integrate(args.warmup, args.events, adapt=True)
         r = p.integrate(args.steps, args.events, adapt=True, iter_offset=args.warmup)
-        print(json.dumps({"workload": "gg>ttxgg fp32", "events_per_s": args.steps * args.events / r.seconds,
+        print(json.dumps({"workload": f"{proc} fp32", "events_per_s": args.steps * args.events / r.seconds,
                           "kernel_ms_avg": 1e3 * r.kernel_seconds / args.steps,
-                          "flops_per_event": flops_per_event(4)}), flush=True)
+                          "cut_efficiency": r.n_nonzero / max(r.n_events_total, 1),
+                          "integral_pb": r.integral, "error_pb": r.error}), flush=True)
         return 0
     p = mf.Process(mf.Config(process="gg>ttxg", precision="fp64"))
     stream = torch.cuda.current_stream()
@@ -370,7 +435,8 @@ def main() -> int:
 
     fpe = flops_per_event(3)
     kernel_avg = r.kernel_seconds / args.steps
-    achieved = fpe * args.events / kernel_avg
+    passing = r.n_nonzero / args.steps  # events whose matrix element is evaluated, per launch
+    achieved = fpe * passing / kernel_avg
     out = {
         "metric": METRIC,
         "value": value,
@@ -397,10 +463,12 @@ def main() -> int:
             "peak": FP64_VECTOR_PEAK / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK,
-            "traffic": MEASURED_TRAFFIC_BYTES if args.events == EVENTS else None,
+            "traffic": MEASURED_TRAFFIC_BYTES if args.events == EVENTS and MEASURED_TRAFFIC_BYTES else None,
             "traffic_unit": "bytes per launch (HBM read + write, counter-calibrated)",
-            "kernel": "k_vegas<1,0,double> (fused per-event VEGAS iteration)",
+            "kernel": "k_select<1> + k_vegas<1,0,double> (cut selection, then the fused weight of the kept events)",
             "flops_per_event": fpe,
+            "flops_per": "event that passes the cuts (the matrix element is evaluated for those only)",
+            "evaluated_events_per_launch": passing,
             "kernel_ms_avg": 1e3 * kernel_avg,
         },
         "integral_pb": r.integral,

@@ -182,8 +182,11 @@ typedef struct mf_result_s {
  * (e, iter_offset + it, call, 0) and key (cfg.seed, 0); the uniforms go
  * through the grid, the weights w = f * Jacobian are reduced (compensated
  * FP64 sums of w and w^2) and binned (w^2 per dimension and bin); the grid
- * is refined on the device.  The handle keeps the final grid.  Blocks until
- * the result is on the host. */
+ * is refined on the device.  The handle keeps the final grid.  Events that
+ * fail the cuts contribute zero and their matrix element is not evaluated.
+ * Under a learned proposal (opts.flow) any non-finite weight is MF_ERANGE
+ * (the integrand itself never returns one, so it comes from a broken
+ * proposal).  Blocks until the result is on the host. */
 mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r);
 
 /* Per-event weights of one sample with the frozen grid of the handle:

@@ -181,6 +181,9 @@ typedef struct {
  *                  time_to_target; group estimates into iter_integral /
  *                  iter_error when those are given, with room for
  *                  ceil(steps / group_steps) values), or NULL.
+ * MF_ERANGE (checked at the end of every group) if the proposal produced a
+ * non-finite density or Jacobian for any point, which a diverged training
+ * step causes; the flow is then left as the last step made it.
  * Blocks until done. */
 mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_online_opts* o, double* loss_per_step,
                                mf_result* est);

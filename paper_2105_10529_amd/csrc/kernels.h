@@ -97,11 +97,67 @@ __global__ void __launch_bounds__(BLOCK) k_integrand_grad(DevCfg c, const double
   }
 }
 
+// ----------------------------------------------------- event selection
+// Stage 1 of a VEGAS iteration: every event of the block's chunks (the same
+// interleaved chunks as the fused kernel) is drawn, mapped and tested for
+// threshold and cuts (kinematics only); the indices of the events that pass
+// are written, in event order, to the block's own slice list[b * cap ...]
+// and their number to cnt[b].  The fused kernel then evaluates the weight of
+// those events only, on full wavefronts; events that fail contribute zero
+// to every sum and histogram.
+template <int NG>
+__global__ void __launch_bounds__(BLOCK) k_select(DevCfg c, const double* __restrict__ edges_g, uint64_t iter,
+                                                  int64_t N, uint64_t seed, int* __restrict__ list,
+                                                  int* __restrict__ cnt, int64_t cap) {
+  extern __shared__ double lds[];
+  __shared__ int wcount[WAVES];
+  const int d = c.ndim, nb = c.nb;
+  double* edges = lds;  // d*(nb+1)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < d * (nb + 1); i += BLOCK) edges[i] = edges_g[i];
+  __syncthreads();
+  int* out = list + (int64_t)blockIdx.x * cap;
+  int qn = 0;
+  const int64_t nchunk = chunks_of_block(N);
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t e0 = chunk_base(it) + tid;
+    const bool live = e0 < N;
+    double y[MAXD], x[MAXD];
+    event_uniforms((uint64_t)(live ? e0 : N - 1), iter, seed, 0, d, y);
+    double jac = 1.0;
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j)
+      if (j < d) {
+        int bin;
+        x[j] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], bin, jac);
+      }
+    const bool pass = event_passes<NG>(c, x) && live;
+    const unsigned long long b = __ballot(pass);
+    if (lane == 0) wcount[wave] = __popcll(b);
+    __syncthreads();
+    int off = qn, total = 0;
+#pragma unroll
+    for (int v = 0; v < WAVES; ++v) {
+      const int cv = wcount[v];
+      off += v < wave ? cv : 0;
+      total += cv;
+    }
+    if (pass) out[off + __popcll(b & ((1ull << lane) - 1ull))] = (int)e0;
+    __syncthreads();
+    qn += total;
+  }
+  if (tid == 0) cnt[blockIdx.x] = qn;
+}
+
 // ----------------------------------------------------- fused VEGAS iteration
+// Stage 2: the weights of the events k_select kept for this block (chunks of
+// BLOCK list entries; the last chunk's idle lanes recompute the block's first
+// event with the weight masked).
 template <int NG, int CH, class RA>
 __global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restrict__ edges_g, uint64_t iter,
                                                  int64_t N, uint64_t seed, double* __restrict__ partials,
-                                                 int pstride) {
+                                                 int pstride, const int* __restrict__ list,
+                                                 const int* __restrict__ cnt, int64_t cap) {
   extern __shared__ double lds[];
   const int d = c.ndim, nb = c.nb;
   double* edges = lds;                             // d*(nb+1)
@@ -126,14 +182,16 @@ __global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restr
   double* acc = wacc + wave * 4;  // S1 (hi, lo), S2 (hi, lo)
   unsigned long long nnz = 0, nbad = 0;
   double* my_hist = hist + wave * d * nb;
-  // The chunk loop is controlled by block-uniform scalars (block index, grid
-  // size, N), so its counter lives in scalar registers and is not exposed to
-  // vector-register spills inside the divergent per-event code.
-  const int64_t nchunk = chunks_of_block(N);
+  // The chunk loop is controlled by block-uniform scalars (the length of the
+  // block's list), so its counter lives in scalar registers and is not
+  // exposed to vector-register spills inside the divergent per-event code.
+  const int* mine_list = list + (int64_t)blockIdx.x * cap;
+  const int nsel = __builtin_amdgcn_readfirstlane(cnt[blockIdx.x]);
+  const int64_t nchunk = (nsel + BLOCK - 1) / BLOCK;
   for (int64_t it = 0; it < nchunk; ++it) {
-    const int64_t e0 = chunk_base(it) + tid;
-    const bool live = e0 < N;
-    const int64_t e = live ? e0 : N - 1;  // tail lanes recompute the last event, weight masked
+    const int64_t j0 = it * BLOCK + tid;
+    const bool live = j0 < nsel;
+    const int64_t e = mine_list[live ? j0 : 0];
     {
       // map the uniforms and stage the bin indices and the Jacobian in LDS
       // before the amplitude, so no per-lane value is live across it
@@ -292,8 +350,11 @@ Launchers make_launchers() {
     hipLaunchKernelGGL((k_integrand<NG, CH, RA>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w);
   };
   L.vegas = [](const DevCfg& c, const double* edges, uint64_t iter, int64_t N, uint64_t seed, double* part,
-               int pstride, int nblk, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_vegas<NG, CH, RA>), dim3(nblk), dim3(BLOCK), lds, s, c, edges, iter, N, seed, part, pstride);
+               int pstride, int nblk, size_t lds, int* list, int* cnt, int64_t cap, hipStream_t s) {
+    hipLaunchKernelGGL((k_select<NG>), dim3(nblk), dim3(BLOCK), sizeof(double) * c.ndim * (c.nb + 1), s, c, edges,
+                       iter, N, seed, list, cnt, cap);
+    hipLaunchKernelGGL((k_vegas<NG, CH, RA>), dim3(nblk), dim3(BLOCK), lds, s, c, edges, iter, N, seed, part, pstride,
+                       list, cnt, cap);
   };
   L.integrand_grad = nullptr;
   L.grad_vegas = nullptr;

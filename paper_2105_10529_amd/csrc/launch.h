@@ -71,7 +71,10 @@ struct Launchers {
   bool fused;
   void (*integrand)(const DevCfg&, const double*, int64_t, double*, int, hipStream_t);
   void (*integrand_grad)(const DevCfg&, const double*, int64_t, double*, double*, int, hipStream_t);
-  void (*vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, int, size_t, hipStream_t);
+  // selection (k_select) then the fused weight kernel (k_vegas) of one
+  // iteration; list/cnt/cap: per-block event lists, [nblk][cap] and [nblk]
+  void (*vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, int, size_t, int*, int*,
+                int64_t, hipStream_t);
   void (*grad_vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, size_t, hipStream_t);
   // Multi-kernel integrand with a workspace held by the process handle
   // (*ws, created on first use, released with ws_free); used instead of

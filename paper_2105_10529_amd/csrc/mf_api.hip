@@ -222,10 +222,15 @@ __global__ void k_weight(const double* __restrict__ f, const double* __restrict_
 // batch's relative-variance estimate.
 __global__ void k_online_weights(const double* __restrict__ f, const double* __restrict__ jac,
                                  const float* __restrict__ logq, double mix, int64_t N, int variance,
-                                 float* __restrict__ out, float* __restrict__ rw, float* __restrict__ r2) {
+                                 float* __restrict__ out, float* __restrict__ rw, float* __restrict__ r2,
+                                 int* __restrict__ bad) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
   double r = f[e] * jac[e];
+  // a non-finite density or Jacobian means the proposal itself is broken (a
+  // diverged training step): flagged, so the caller can stop instead of
+  // silently dropping those points from the estimate
+  if (!isfinite(r) || !isfinite(logq[e])) *bad = 1;
   r = isfinite(r) ? r : 0.0;
   const double q = exp((double)logq[e]);
   const double share = q / (mix + (1.0 - mix) * q);
@@ -501,6 +506,10 @@ struct mf_process {
   float* d_sz = nullptr;           // [ndim][cap] scratch for the flow's density pass
   float* d_sw32 = nullptr;         // [3][cap] on-policy training weights
   void* ws = nullptr;              // workspace of a multi-kernel integrand (Launchers::integrand_ws)
+  // per-block lists of the events that pass the cuts (fused iterations)
+  int64_t sel_cap = 0;             // list entries per block
+  int* d_sel = nullptr;            // [MAX_BLOCKS][sel_cap]
+  int* d_selcnt = nullptr;         // [MAX_BLOCKS]
 };
 
 namespace {
@@ -561,6 +570,24 @@ mf_status run_integrand(mf_process* p, const double* x, int64_t n, double* w, hi
   }
   p->L.integrand(p->dc, x, n, w, blocks_for(n), s);
   return check_stream_launch("k_integrand");
+}
+
+// Grow the per-block selection lists to the chunks of an n-event iteration.
+mf_status ensure_select(mf_process* p, int64_t n, hipStream_t s) {
+  if (n > (int64_t)INT32_MAX) return fail(MF_EINVAL, "n_events must be below 2^31 for fused iterations");
+  const int nblk = blocks_for(n);
+  const int64_t cap = (n + (int64_t)nblk * BLOCK - 1) / ((int64_t)nblk * BLOCK) * BLOCK;
+  if (p->d_selcnt && p->sel_cap >= cap) return MF_OK;
+  HIP_TRY(hipStreamSynchronize(s));
+  (void)hipFree(p->d_sel);
+  p->d_sel = nullptr;
+  p->sel_cap = 0;
+  if (!p->d_selcnt && hipMalloc(&p->d_selcnt, sizeof(int) * MAX_BLOCKS) != hipSuccess)
+    return fail(MF_ENOMEM, "selection counts");
+  if (hipMalloc(&p->d_sel, sizeof(int) * (size_t)MAX_BLOCKS * cap) != hipSuccess)
+    return fail(MF_ENOMEM, "selection lists (%lld events)", (long long)n);
+  p->sel_cap = cap;
+  return MF_OK;
 }
 
 // Grow the staging buffers of the handle to n events.
@@ -727,6 +754,8 @@ void mf_process_destroy(mf_process* p) {
   hipFree(p->d_sz);
   hipFree(p->d_sw32);
   if (p->ws && p->L.ws_free) p->L.ws_free(p->ws);
+  hipFree(p->d_sel);
+  hipFree(p->d_selcnt);
   delete p;
 }
 
@@ -793,6 +822,9 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   if (!p->L.fused || o->flow) {
     mf_status st = ensure_stage(p, o->n_events, s);
     if (st != MF_OK) return st;
+  } else {
+    mf_status st = ensure_select(p, o->n_events, s);
+    if (st != MF_OK) return st;
   }
   std::vector<double> rec((size_t)REC * o->n_iter, 0.0);
   double time_to_target = -1.0;
@@ -822,7 +854,8 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
       hipLaunchKernelGGL(k_stage_accumulate, dim3(nblk), dim3(256), 0, s, p->d_sw, p->d_sjac, p->d_sbins, d, nb, N,
                          p->d_part, p->pstride);
     } else if (p->L.fused) {
-      p->L.vegas(p->dc, p->d_edges, iter, o->n_events, p->cfg.seed, p->d_part, p->pstride, nblk, lds, s);
+      p->L.vegas(p->dc, p->d_edges, iter, o->n_events, p->cfg.seed, p->d_part, p->pstride, nblk, lds, p->d_sel,
+                 p->d_selcnt, p->sel_cap, s);
     } else {
       const int64_t N = o->n_events;
       hipLaunchKernelGGL(k_stage_points, dim3(nblk), dim3(256), sizeof(double) * d * (nb + 1), s, p->d_edges, d, nb,
@@ -910,6 +943,11 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   r->kernel_seconds = ksec;
   for (int it = 0; it < done; ++it)
     if (rec[(size_t)REC * it + 6] != 0.0) return fail(MF_ERANGE, "grid refinement failed at iteration %d", it);
+  // the integrand never returns a non-finite value, so under a learned
+  // proposal a non-finite weight comes from the proposal's density: the
+  // estimate would silently miss those points
+  if (o->flow && bad > 0.0)
+    return fail(MF_ERANGE, "the proposal gave %.0f non-finite weights (diverged training)", bad);
   return MF_OK;
 }
 
@@ -980,9 +1018,9 @@ mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_onlin
   mf_status st = ensure_stage(p, n, s);
   if (st != MF_OK) return st;
   float* d_loss = nullptr;
-  double* d_sums = nullptr;
+  double* d_sums = nullptr;  // [steps][2] batch sums, then one int flag
   HIP_TRY(hipMalloc(&d_loss, sizeof(float) * 2 * o->steps));
-  if (hipMalloc(&d_sums, sizeof(double) * 2 * o->steps) != hipSuccess) {
+  if (hipMalloc(&d_sums, sizeof(double) * (2 * o->steps + 1)) != hipSuccess) {
     (void)hipFree(d_loss);
     return fail(MF_ENOMEM, "training statistics");
   }
@@ -994,7 +1032,8 @@ mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_onlin
       (void)hipFree(r);
     }
   } guard{d_loss, d_sums};
-  const int nblk = blocks_for(n);
+  int* d_bad = reinterpret_cast<int*>(d_sums + 2 * o->steps);
+  HIP_TRY(hipMemsetAsync(d_bad, 0, sizeof(int), s));
   float* wt = p->d_sw32;
   float* rw = p->d_sw32 + n;
   float* r2 = p->d_sw32 + 2 * n;
@@ -1008,7 +1047,7 @@ mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_onlin
     st = run_integrand(p, p->d_sx, n, p->d_sw, s);
     if (st != MF_OK) return st;
     hipLaunchKernelGGL(k_online_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->d_sw, p->d_sjac,
-                       p->d_slq, o->flow_mix, n, o->loss == MF_FLOW_LOSS_VARIANCE ? 1 : 0, wt, rw, r2);
+                       p->d_slq, o->flow_mix, n, o->loss == MF_FLOW_LOSS_VARIANCE ? 1 : 0, wt, rw, r2, d_bad);
     hipLaunchKernelGGL(k_batch_relvar, dim3(1), dim3(1024), 0, s, rw, r2, n, d_loss + 2 * t, d_sums + 2 * t);
     const double lr =
         o->lr_final + 0.5 * (o->lr - o->lr_final) * (1.0 + std::cos(M_PI * (double)t / (double)o->steps));
@@ -1018,9 +1057,14 @@ mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_onlin
     if (done - g0 == group || done == o->steps) {
       // the group's estimate: all its batches pooled (each batch is an unbiased
       // sample of the integral from the flow as it was at that step)
+      int h_bad = 0;
       HIP_TRY(hipMemcpyAsync(hs.data() + 2 * (size_t)g0, d_sums + 2 * g0, sizeof(double) * 2 * (done - g0),
                              hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(&h_bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
+      if (h_bad)
+        return fail(MF_ERANGE, "the proposal gave non-finite densities by step %d (diverged training; "
+                               "lower the learning rate)", done);
       double S1 = 0.0, S2 = 0.0;
       for (int k = g0; k < done; ++k) {
         S1 += hs[2 * (size_t)k];

@@ -343,6 +343,23 @@ template <class R> struct EventOut {
   int pass;
 };
 
+// Whether the event at x has kinematics and passes the cuts: the same
+// decision, in the same FP64 arithmetic, as the selection of event_weight
+// with the kinematic type double.
+template <int NG>
+__device__ __forceinline__ bool event_passes(const DevCfg& c, const double* x) {
+  const double x1 = x[0], x2 = x[1];
+  const double shat = x1 * x2 * c.s;
+  const double thr = 4.0 * c.mt * c.mt;
+  bool ok = shat > thr;
+  const double shat_k = ok ? shat : thr * (1.0 + 1e-3);
+  V4<double> gl[NG > 0 ? NG : 1];
+  V4<double> top, atop;
+  const double wps = phase_space<double>(NG, x, shat_k, c.mt, gl, top, atop);
+  ok = ok && (wps > 0.0);
+  return ok && pass_cuts(c, NG, gl, 0.5 * log(x1 / x2));
+}
+
 // The integrand at x (unit hypercube, after the VEGAS map).  Branch-free:
 // an event below threshold or outside the cuts is evaluated on safe
 // kinematics and its weight is selected to zero, so the amplitude code never
