@@ -30,11 +30,12 @@ sys.path.insert(0, ROOT)
 METRIC = "events/s per MI355X and time to 1e-3 rel. error: FP32+flow vs FP64 VEGAS"
 FP64_VECTOR_PEAK = 78.6e12  # MI355X FP64 vector FLOP/s (256 CUs x 128 FLOP/clk x 2.4 GHz)
 EVENTS = 10_000_000
-# HBM bytes per launch of the fused kernel k_vegas<1,0,double> at 1e7 events,
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy
-# calibration (profiles/traffic_k_vegas_gg_ttg_fp64_1e7.md).  Set to None when
-# that kernel changes until the counters are taken again.
-MEASURED_TRAFFIC_BYTES = None
+# HBM bytes per iteration of the kernel pair k_select<1> + k_vegas<1,0,double>
+# at 1e7 events (29.9 + 49.9 MB), from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs scaled by a 1 GiB copy calibration
+# (profiles/traffic_k_vegas_gg_ttg_fp64_1e7.md).  Set to None when those
+# kernels change until the counters are taken again.
+MEASURED_TRAFFIC_BYTES = 79.8e6
 
 
 def flops_per_event(m: int) -> int:
@@ -464,7 +465,7 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK,
             "traffic": MEASURED_TRAFFIC_BYTES if args.events == EVENTS and MEASURED_TRAFFIC_BYTES else None,
-            "traffic_unit": "bytes per launch (HBM read + write, counter-calibrated)",
+            "traffic_unit": "bytes per iteration (HBM read + write of both kernels, counter-calibrated)",
             "kernel": "k_select<1> + k_vegas<1,0,double> (cut selection, then the fused weight of the kept events)",
             "flops_per_event": fpe,
             "flops_per": "event that passes the cuts (the matrix element is evaluated for those only)",

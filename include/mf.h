@@ -111,8 +111,11 @@ const char* mf_last_error(void);
  *   w: device, [n] FP64 output: d sigma in pb per unit hypercube volume.
  *      Zero below threshold or outside the cuts; a non-finite value is
  *      never written (such events give 0).
- * n = 0 is accepted and does nothing.  MF_EINVAL for n < 0 or NULL pointers
- * with n > 0. */
+ * Points that fail threshold or cuts are written as 0 without evaluating the
+ * matrix element.  The call may allocate (or grow) per-block point lists
+ * inside the handle (4 B per point), synchronising `stream` when it does.
+ * n = 0 is accepted and does nothing.  MF_EINVAL for n < 0, n >= 2^31 or NULL
+ * pointers with n > 0. */
 mf_status mf_integrand(mf_process* p, const double* u, int64_t n, double* w, void* stream);
 
 /* The same integrand and its derivatives (forward mode) at the same points:

@@ -22,14 +22,57 @@ __device__ __forceinline__ int64_t chunks_of_block(int64_t n) {
 }
 
 // -------------------------------------------------------------- integrand
-template <int NG, int CH, class RA>
-__global__ void __launch_bounds__(BLOCK) k_integrand(DevCfg c, const double* __restrict__ u, int64_t n,
-                                                     double* __restrict__ w) {
+// At caller-supplied points: k_select_points writes w = 0 for every point and
+// lists, per block and in point order, the points that pass threshold and
+// cuts; k_integrand evaluates the weights of the listed points only (full
+// wavefronts of points that count, as in the fused iteration).
+template <int NG>
+__global__ void __launch_bounds__(BLOCK) k_select_points(DevCfg c, const double* __restrict__ u, int64_t n,
+                                                         double* __restrict__ w, int* __restrict__ list,
+                                                         int* __restrict__ cnt, int64_t cap) {
+  __shared__ int wcount[WAVES];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int* out = list + (int64_t)blockIdx.x * cap;
+  int qn = 0;
   const int64_t nchunk = chunks_of_block(n);
   for (int64_t it = 0; it < nchunk; ++it) {
-    const int64_t e0 = chunk_base(it) + threadIdx.x;
+    const int64_t e0 = chunk_base(it) + tid;
     const bool live = e0 < n;
-    const int64_t e = live ? e0 : n - 1;  // tail lanes recompute the last event
+    const int64_t e = live ? e0 : n - 1;
+    double x[MAXD];
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j)
+      if (j < c.ndim) x[j] = u[(int64_t)j * n + e];
+    const bool pass = event_passes<NG>(c, x) && live;
+    if (live) w[e0] = 0.0;
+    const unsigned long long b = __ballot(pass);
+    if (lane == 0) wcount[wave] = __popcll(b);
+    __syncthreads();
+    int off = qn, total = 0;
+#pragma unroll
+    for (int v = 0; v < WAVES; ++v) {
+      const int cv = wcount[v];
+      off += v < wave ? cv : 0;
+      total += cv;
+    }
+    if (pass) out[off + __popcll(b & ((1ull << lane) - 1ull))] = (int)e0;
+    __syncthreads();
+    qn += total;
+  }
+  if (tid == 0) cnt[blockIdx.x] = qn;
+}
+
+template <int NG, int CH, class RA>
+__global__ void __launch_bounds__(BLOCK) k_integrand(DevCfg c, const double* __restrict__ u, int64_t n,
+                                                     double* __restrict__ w, const int* __restrict__ list,
+                                                     const int* __restrict__ cnt, int64_t cap) {
+  const int* mine_list = list + (int64_t)blockIdx.x * cap;
+  const int nsel = __builtin_amdgcn_readfirstlane(cnt[blockIdx.x]);
+  const int64_t nchunk = (nsel + BLOCK - 1) / BLOCK;
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t j0 = it * BLOCK + threadIdx.x;
+    const bool live = j0 < nsel;
+    const int64_t e = mine_list[live ? j0 : 0];  // idle lanes recompute the block's first point
     double x[MAXD];
 #pragma unroll
     for (int j = 0; j < MAXD; ++j)
@@ -346,8 +389,10 @@ template <int NG, int CH, class RA, class RD, int GRAD, int FUSED = 1>
 Launchers make_launchers() {
   Launchers L;
   L.fused = FUSED != 0;
-  L.integrand = [](const DevCfg& c, const double* u, int64_t n, double* w, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((k_integrand<NG, CH, RA>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w);
+  L.integrand = [](const DevCfg& c, const double* u, int64_t n, double* w, int nblk, int* list, int* cnt,
+                   int64_t cap, hipStream_t s) {
+    hipLaunchKernelGGL((k_select_points<NG>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w, list, cnt, cap);
+    hipLaunchKernelGGL((k_integrand<NG, CH, RA>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w, list, cnt, cap);
   };
   L.vegas = [](const DevCfg& c, const double* edges, uint64_t iter, int64_t N, uint64_t seed, double* part,
                int pstride, int nblk, size_t lds, int* list, int* cnt, int64_t cap, hipStream_t s) {

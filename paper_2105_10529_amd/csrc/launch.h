@@ -69,7 +69,9 @@ struct Launchers {
   // false: VEGAS iterations go through the staged path (points kernel ->
   // integrand kernel -> accumulation kernel) instead of the fused kernel
   bool fused;
-  void (*integrand)(const DevCfg&, const double*, int64_t, double*, int, hipStream_t);
+  // selection (k_select_points) then the weights of the kept points
+  // (k_integrand); list/cnt/cap as for vegas
+  void (*integrand)(const DevCfg&, const double*, int64_t, double*, int, int*, int*, int64_t, hipStream_t);
   void (*integrand_grad)(const DevCfg&, const double*, int64_t, double*, double*, int, hipStream_t);
   // selection (k_select) then the fused weight kernel (k_vegas) of one
   // iteration; list/cnt/cap: per-block event lists, [nblk][cap] and [nblk]

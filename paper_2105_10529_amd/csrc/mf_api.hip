@@ -559,19 +559,6 @@ mf_status check_stream_launch(const char* what) {
   return MF_OK;
 }
 
-// The integrand of the process on n mapped points (single-kernel or staged).
-mf_status run_integrand(mf_process* p, const double* x, int64_t n, double* w, hipStream_t s) {
-  if (p->L.integrand_ws) {
-    hipError_t e = p->L.integrand_ws(p->dc, x, n, w, &p->ws, s);
-    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
-      return fail(MF_ENOMEM, "integrand workspace allocation failed");
-    if (e != hipSuccess) return fail(MF_EDEVICE, "integrand: %s", hipGetErrorString(e));
-    return MF_OK;
-  }
-  p->L.integrand(p->dc, x, n, w, blocks_for(n), s);
-  return check_stream_launch("k_integrand");
-}
-
 // Grow the per-block selection lists to the chunks of an n-event iteration.
 mf_status ensure_select(mf_process* p, int64_t n, hipStream_t s) {
   if (n > (int64_t)INT32_MAX) return fail(MF_EINVAL, "n_events must be below 2^31 for fused iterations");
@@ -588,6 +575,21 @@ mf_status ensure_select(mf_process* p, int64_t n, hipStream_t s) {
     return fail(MF_ENOMEM, "selection lists (%lld events)", (long long)n);
   p->sel_cap = cap;
   return MF_OK;
+}
+
+// The integrand of the process on n mapped points (single-kernel or staged).
+mf_status run_integrand(mf_process* p, const double* x, int64_t n, double* w, hipStream_t s) {
+  if (p->L.integrand_ws) {
+    hipError_t e = p->L.integrand_ws(p->dc, x, n, w, &p->ws, s);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      return fail(MF_ENOMEM, "integrand workspace allocation failed");
+    if (e != hipSuccess) return fail(MF_EDEVICE, "integrand: %s", hipGetErrorString(e));
+    return MF_OK;
+  }
+  mf_status st = ensure_select(p, n, s);
+  if (st != MF_OK) return st;
+  p->L.integrand(p->dc, x, n, w, blocks_for(n), p->d_sel, p->d_selcnt, p->sel_cap, s);
+  return check_stream_launch("k_integrand");
 }
 
 // Grow the staging buffers of the handle to n events.
