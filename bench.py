@@ -221,6 +221,30 @@ def ttggg_flow_comparison() -> dict:
                            long_steps=150)
 
 
+def ttg_observables(events: int = EVENTS, iters: int = 10) -> dict:
+    """Observable histograms filled during the benchmark workload (g g -> t t~ g
+    FP64, 2 adapting warm-up iterations, then `iters` iterations of 1e7 events
+    on the frozen grid): per-bin cross sections and errors of the top pT, the
+    top-pair mass and the hardest-gluon pT, and the cost of the histograms
+    (kernel time of the same iterations with and without them)."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+
+    spec = {"nbins": 20, "lo": (0.0, 345.0, 20.0), "hi": (600.0, 1545.0, 420.0)}
+    p = mf.Process(mf.Config(process="gg>ttxg"))
+    p.integrate(2, events, adapt=True)
+    torch.cuda.synchronize()
+    r0 = p.integrate(iters, events, adapt=False, iter_offset=2)
+    r = p.integrate(iters, events, adapt=False, iter_offset=2, observables=spec)
+    o = r.observables
+    return {"names": list(o["names"]), "bin_edges": [list(map(float, e)) for e in o["edges"]],
+            "sigma_pb": o["sigma_pb"].tolist(), "error_pb": o["error_pb"].tolist(),
+            "integral_pb": r.integral, "error_total_pb": r.error, "events": o["events"],
+            "kernel_ms_per_iteration_without": 1e3 * r0.kernel_seconds / iters,
+            "kernel_ms_per_iteration_with": 1e3 * r.kernel_seconds / iters}
+
+
 def fp32_subsample_check(n: int = 100_000) -> dict:
     """g g -> t t~ g g with FP32 amplitudes against the FP64 oracle on a
     subsample of n events of one VEGAS iteration on an adapted grid: the same
@@ -342,6 +366,7 @@ def secondary(seed_events: int) -> dict:
         }
     out["ttgg_fp32_vs_oracle_subsample"] = fp32_subsample_check()
     out["ttgg_flow_vs_vegas"] = flow_comparison()
+    out["ttg_observables"] = ttg_observables()
     out["ttggg_fp32"] = ttggg_throughput()
     out["ttggg_flow_vs_vegas"] = ttggg_flow_comparison()
     out["flow_roofline"] = flow_roofline()
@@ -374,6 +399,8 @@ def main() -> int:
                          "FP32 amplitudes (profiling runs)")
     ap.add_argument("--flow-only", action="store_true",
                     help="only run the g g -> t t~ g g learned-proposal comparison and the flow roofline (profiling)")
+    ap.add_argument("--observables-only", action="store_true",
+                    help="only run the g g -> t t~ g observable histograms (profiling)")
     ap.add_argument("--ttggg-only", action="store_true",
                     help="only run the g g -> t t~ g g g throughput and learned-proposal measurements (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -400,6 +427,9 @@ def main() -> int:
         return 0
     if args.flow_only:
         print(json.dumps({"ttgg_flow_vs_vegas": flow_comparison(), "flow_roofline": flow_roofline()}), flush=True)
+        return 0
+    if args.observables_only:
+        print(json.dumps({"ttg_observables": ttg_observables()}), flush=True)
         return 0
     if args.ttggg_only:
         print(json.dumps({"ttggg_fp32": ttggg_throughput(),

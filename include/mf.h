@@ -142,6 +142,25 @@ mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins
 struct mf_flow;     /* learned proposal, mf_flow.h */
 struct mf_result_s; /* mf_result, below */
 
+/* Weighted histograms of observables of the events of a VEGAS integration
+ * (the distributions of Sec. 3, here on synthetic inputs).  Observables, in
+ * GeV: 0 = transverse momentum of the top quark, 1 = invariant mass of the
+ * top pair, 2 = transverse momentum of the hardest final-state gluon (no
+ * entries without final gluons).  Uniform bins [lo, hi) per observable;
+ * events outside are not binned. */
+#define MF_N_OBS 3
+typedef struct {
+  int32_t nbins;          /* bins per observable, 1..64 */
+  double lo[MF_N_OBS];    /* lower edge of each range */
+  double hi[MF_N_OBS];    /* upper edge, > lo */
+  double* sums;           /* host output [MF_N_OBS][nbins][2]: per bin the sum
+                             of w and of w^2 over the events of the counted
+                             iterations (those after warmup_iters_discarded);
+                             with N events per iteration and n counted
+                             iterations the bin's cross section is
+                             sum w / (n N) (pb) */
+} mf_observables;
+
 typedef struct {
   int32_t n_iter;                 /* iterations, >= 1 */
   int64_t n_events;               /* events per iteration, >= 2 */
@@ -161,6 +180,11 @@ typedef struct {
                                      error) that enters the inverse-variance
                                      combination and the target test as one
                                      more iteration */
+  const mf_observables* obs;      /* NULL, or histograms to fill (VEGAS
+                                     proposal of the single-kernel processes
+                                     only: MF_ENOTSUP with a flow, for
+                                     g g -> t t~ g g in FP64 and for
+                                     g g -> t t~ g g g) */
 } mf_integrate_opts;
 
 typedef struct mf_result_s {

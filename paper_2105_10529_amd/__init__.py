@@ -64,6 +64,20 @@ class _IntegrateOpts(ctypes.Structure):
         ("flow", ctypes.c_void_p),
         ("flow_mix", ctypes.c_double),
         ("prior", ctypes.c_void_p),
+        ("obs", ctypes.c_void_p),
+    ]
+
+
+N_OBS = 3
+OBSERVABLES = ("pt_top", "m_ttbar", "pt_gluon_max")
+
+
+class _Observables(ctypes.Structure):
+    _fields_ = [
+        ("nbins", ctypes.c_int32),
+        ("lo", ctypes.c_double * N_OBS),
+        ("hi", ctypes.c_double * N_OBS),
+        ("sums", ctypes.c_void_p),
     ]
 
 
@@ -256,6 +270,7 @@ class IntegrationResult:
     kernel_seconds: float
     iter_integral: np.ndarray = field(default_factory=lambda: np.zeros(0))
     iter_error: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    observables: dict | None = None  # see Process.integrate(observables=...)
 
 
 class Process:
@@ -311,10 +326,24 @@ class Process:
     def integrate(self, n_iter: int, n_events: int, target_rel_err: float = 0.0, warmup: int = 0, adapt: bool = True,
                   iter_offset: int = 0, edges_in=None, edges_out=None, stream=None,
                   flow: "Flow | None" = None, flow_mix: float = 0.0,
-                  prior: "IntegrationResult | None" = None) -> IntegrationResult:
+                  prior: "IntegrationResult | None" = None, observables: dict | None = None) -> IntegrationResult:
         """VEGAS integration entirely on the device -- mf_integrate (flow: learned proposal, frozen grid;
-        prior: an earlier estimate combined with the new iterations)."""
+        prior: an earlier estimate combined with the new iterations; observables: {"nbins": n, "lo": (3,),
+        "hi": (3,)} fills histograms of OBSERVABLES, returned as result.observables with the raw per-bin
+        sums of w and w^2 ([3][nbins][2]), the bin edges, and the per-bin cross sections (pb) and their
+        Monte Carlo errors over the counted iterations)."""
         o = _IntegrateOpts()
+        ob = sums = None
+        if observables is not None:
+            nb = int(observables["nbins"])
+            sums = np.zeros((N_OBS, nb, 2))
+            ob = _Observables()
+            ob.nbins = nb
+            for q in range(N_OBS):
+                ob.lo[q] = float(observables["lo"][q])
+                ob.hi[q] = float(observables["hi"][q])
+            ob.sums = sums.ctypes.data
+            o.obs = ctypes.addressof(ob)
         o.flow = flow._h.value if flow is not None else None
         o.flow_mix = flow_mix
         pr = None
@@ -334,8 +363,18 @@ class Process:
         r.iter_error = Ie.ctypes.data
         _check(lib().mf_integrate(self._h, ctypes.byref(o), ctypes.byref(r)))
         k = r.n_iter_done
-        return IntegrationResult(r.integral, r.error, r.chi2_dof, k, r.n_events_total, r.n_nonzero, r.n_nonfinite,
-                                 r.seconds, r.time_to_target, r.kernel_seconds, Ii[:k].copy(), Ie[:k].copy())
+        res = IntegrationResult(r.integral, r.error, r.chi2_dof, k, r.n_events_total, r.n_nonzero, r.n_nonfinite,
+                                r.seconds, r.time_to_target, r.kernel_seconds, Ii[:k].copy(), Ie[:k].copy())
+        if sums is not None:
+            n = float(n_events) * max(k - warmup, 0)
+            mean = sums[:, :, 0] / max(n, 1.0)
+            var = (sums[:, :, 1] / max(n, 1.0) - mean ** 2) / max(n - 1.0, 1.0)
+            res.observables = {
+                "names": OBSERVABLES, "sums": sums, "events": n,
+                "edges": [np.linspace(observables["lo"][q], observables["hi"][q], sums.shape[1] + 1)
+                          for q in range(N_OBS)],
+                "sigma_pb": mean, "error_pb": np.sqrt(np.maximum(var, 0.0))}
+        return res
 
     def weights(self, it: int, n: int, flow: "Flow | None" = None, want_y: bool = False, stream=None,
                 flow_mix: float = 0.0):

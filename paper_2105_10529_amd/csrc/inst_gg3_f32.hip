@@ -95,6 +95,7 @@ Launchers launchers_gg3_f32() {
   L.vegas = nullptr;
   L.integrand_grad = nullptr;
   L.grad_vegas = nullptr;
+  L.observables = nullptr;
   L.integrand_ws = g3::integrand;
   L.ws_free = g3::ws_free;
   return L;

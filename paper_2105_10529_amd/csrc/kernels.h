@@ -200,7 +200,8 @@ template <int NG, int CH, class RA>
 __global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restrict__ edges_g, uint64_t iter,
                                                  int64_t N, uint64_t seed, double* __restrict__ partials,
                                                  int pstride, const int* __restrict__ list,
-                                                 const int* __restrict__ cnt, int64_t cap) {
+                                                 const int* __restrict__ cnt, int64_t cap,
+                                                 double* __restrict__ wk) {
   extern __shared__ double lds[];
   const int d = c.ndim, nb = c.nb;
   double* edges = lds;                             // d*(nb+1)
@@ -262,6 +263,7 @@ __global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restr
     nbad += __popcll(__ballot(live && !finite));
     w = (live && finite) ? w : 0.0;
     nnz += __popcll(__ballot(w != 0.0));
+    if (wk != nullptr && live) wk[(int64_t)blockIdx.x * cap + j0] = w;  // for the observable histograms
     {
       double h1, l1, h2, l2;
       wave_sum_dd(w, h1, l1);
@@ -321,6 +323,93 @@ __global__ void __launch_bounds__(BLOCK) k_vegas(DevCfg c, const double* __restr
     p[3] = acc_lo[1];
     p[4] = (double)tn;
     p[5] = (double)tb;
+  }
+}
+
+// ------------------------------------------------- observable histograms
+// Weighted histograms of three observables of the kept events of one fused
+// iteration (after k_vegas wrote their weights wk, in list order): 0 = top
+// transverse momentum, 1 = invariant mass of the top pair, 2 = transverse
+// momentum of the hardest gluon (absent without final gluons).  All three
+// are invariant under the longitudinal boost, so they are taken from the
+// partonic centre-of-mass momenta of the phase-space map.  Per bin the sum
+// of w and of w^2; bin k = floor((v - lo) scale), kept for 0 <= k < nbins.
+// One wave's 64 events are staged in LDS and binned by lanes 0..2 (one
+// observable each) in event order, so the block partials are reproducible.
+template <int NG>
+__global__ void __launch_bounds__(BLOCK) k_observables(DevCfg c, const double* __restrict__ edges_g, uint64_t iter,
+                                                       uint64_t seed, const int* __restrict__ list,
+                                                       const int* __restrict__ cnt, int64_t cap,
+                                                       const double* __restrict__ wk, ObsSpec o,
+                                                       double* __restrict__ opart) {
+  extern __shared__ double lds[];
+  const int d = c.ndim, nb = c.nb, onb = o.nbins;
+  const int W = N_OBS * onb * 2;
+  double* edges = lds;                       // d*(nb+1)
+  double* hw = edges + d * (nb + 1);         // [WAVES][N_OBS][onb][2]
+  double* ws = hw + WAVES * W;               // [BLOCK] staged weights
+  int* ks = (int*)(ws + BLOCK);              // [N_OBS][BLOCK] staged bins
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < d * (nb + 1); i += BLOCK) edges[i] = edges_g[i];
+  for (int i = tid; i < WAVES * W; i += BLOCK) hw[i] = 0.0;
+  __syncthreads();
+  const int* mine_list = list + (int64_t)blockIdx.x * cap;
+  const double* mine_w = wk + (int64_t)blockIdx.x * cap;
+  const int nsel = __builtin_amdgcn_readfirstlane(cnt[blockIdx.x]);
+  const int64_t nchunk = (nsel + BLOCK - 1) / BLOCK;
+  for (int64_t it = 0; it < nchunk; ++it) {
+    const int64_t j0 = it * BLOCK + tid;
+    const bool live = j0 < nsel;
+    const int64_t e = mine_list[live ? j0 : 0];
+    double y[MAXD], x[MAXD];
+    event_uniforms((uint64_t)e, iter, seed, 0, d, y);
+    double jac = 1.0;
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j)
+      if (j < d) {
+        int bin;
+        x[j] = vegas_map_dim(edges + j * (nb + 1), nb, y[j], bin, jac);
+      }
+    const double thr = 4.0 * c.mt * c.mt, shat = x[0] * x[1] * c.s;
+    V4<double> gl[NG > 0 ? NG : 1], top, atop;
+    (void)phase_space<double>(NG, x, shat > thr ? shat : thr * (1.0 + 1e-3), c.mt, gl, top, atop);
+    double v[N_OBS];
+    v[0] = sqrt(top.x * top.x + top.y * top.y);
+    const V4<double> P = top + atop;
+    v[1] = sqrt(fmax(mdot(P, P), 0.0));
+    v[2] = -1.0;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) v[2] = fmax(v[2], sqrt(gl[i].x * gl[i].x + gl[i].y * gl[i].y));
+    ws[tid] = live ? mine_w[j0] : 0.0;
+#pragma unroll
+    for (int q = 0; q < N_OBS; ++q) {
+      const double t = (v[q] - o.lo[q]) * o.scale[q];
+      ks[q * BLOCK + tid] = (live && t >= 0.0 && t < (double)onb) ? (int)t : -1;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < N_OBS) {
+      double* h = hw + wave * W + lane * onb * 2;
+      const int* kq = ks + lane * BLOCK + wave * 64;
+      const double* wq = ws + wave * 64;
+      for (int k = 0; k < 64; ++k) {
+        const int b = kq[k];
+        if (b >= 0) {
+          h[2 * b] += wq[k];
+          h[2 * b + 1] += wq[k] * wq[k];
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();
+  for (int i = tid; i < W; i += BLOCK) {
+    double h = 0.0;
+    for (int v2 = 0; v2 < WAVES; ++v2) h += hw[v2 * W + i];
+    opart[(int64_t)blockIdx.x * W + i] = h;
   }
 }
 
@@ -395,11 +484,19 @@ Launchers make_launchers() {
     hipLaunchKernelGGL((k_integrand<NG, CH, RA>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w, list, cnt, cap);
   };
   L.vegas = [](const DevCfg& c, const double* edges, uint64_t iter, int64_t N, uint64_t seed, double* part,
-               int pstride, int nblk, size_t lds, int* list, int* cnt, int64_t cap, hipStream_t s) {
+               int pstride, int nblk, size_t lds, int* list, int* cnt, int64_t cap, double* wk, hipStream_t s) {
     hipLaunchKernelGGL((k_select<NG>), dim3(nblk), dim3(BLOCK), sizeof(double) * c.ndim * (c.nb + 1), s, c, edges,
                        iter, N, seed, list, cnt, cap);
     hipLaunchKernelGGL((k_vegas<NG, CH, RA>), dim3(nblk), dim3(BLOCK), lds, s, c, edges, iter, N, seed, part, pstride,
-                       list, cnt, cap);
+                       list, cnt, cap, wk);
+  };
+  L.observables = [](const DevCfg& c, const double* edges, uint64_t iter, uint64_t seed, const int* list,
+                     const int* cnt, int64_t cap, const double* wk, const ObsSpec& o, double* opart, int nblk,
+                     hipStream_t s) {
+    const size_t lds = sizeof(double) * ((size_t)c.ndim * (c.nb + 1) + (size_t)WAVES * N_OBS * o.nbins * 2 + BLOCK) +
+                       sizeof(int) * N_OBS * BLOCK;
+    hipLaunchKernelGGL((k_observables<NG>), dim3(nblk), dim3(BLOCK), lds, s, c, edges, iter, seed, list, cnt, cap, wk,
+                       o, opart);
   };
   L.integrand_grad = nullptr;
   L.grad_vegas = nullptr;

@@ -65,6 +65,15 @@ __device__ __forceinline__ void lds_dd_accumulate(double* acc, double hi, double
   acc[1] = l;
 }
 
+// Observable histograms (k_observables): bins per observable and, per
+// observable, the lower edge and nbins / (upper - lower edge).
+constexpr int N_OBS = 3;
+constexpr int MAX_OBS_BINS = 64;
+struct ObsSpec {
+  int nbins;
+  double lo[N_OBS], scale[N_OBS];
+};
+
 struct Launchers {
   // false: VEGAS iterations go through the staged path (points kernel ->
   // integrand kernel -> accumulation kernel) instead of the fused kernel
@@ -76,7 +85,11 @@ struct Launchers {
   // selection (k_select) then the fused weight kernel (k_vegas) of one
   // iteration; list/cnt/cap: per-block event lists, [nblk][cap] and [nblk]
   void (*vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, int, size_t, int*, int*,
-                int64_t, hipStream_t);
+                int64_t, double*, hipStream_t);
+  // observable histograms of the kept events of the last fused iteration
+  // (their weights from vegas' wk output); per-block partial rows
+  void (*observables)(const DevCfg&, const double*, uint64_t, uint64_t, const int*, const int*, int64_t,
+                      const double*, const ObsSpec&, double*, int, hipStream_t);
   void (*grad_vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, size_t, hipStream_t);
   // Multi-kernel integrand with a workspace held by the process handle
   // (*ws, created on first use, released with ws_free); used instead of

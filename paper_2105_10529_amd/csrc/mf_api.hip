@@ -418,6 +418,25 @@ __global__ void k_reduce_partials(const double* partials, int nblk, int pstride,
   }
 }
 
+// Column sums of the observables' block partial rows [nblk][W] in a fixed
+// order: stage 1 sums row groups (grid (ceil(W/256), R)), stage 2 adds the R
+// group sums, in order, to the running histogram.
+__global__ void k_obs_reduce(const double* part, int nblk, int W, int R, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (i >= W) return;
+  const int b0 = (int)((int64_t)r * nblk / R), b1 = (int)((int64_t)(r + 1) * nblk / R);
+  double acc = 0.0;
+  for (int b = b0; b < b1; ++b) acc += part[(int64_t)b * W + i];
+  out[(int64_t)r * W + i] = acc;
+}
+__global__ void k_obs_accumulate(const double* rows, int R, int W, double* sums) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W) return;
+  double acc = 0.0;
+  for (int r = 0; r < R; ++r) acc += rows[(int64_t)r * W + i];
+  sums[i] += acc;
+}
+
 // Ordered reduction of the block partials of one iteration; writes the
 // iteration record and (if adapt) refines the grid in place.
 __global__ void k_finalize(const double* partials, int nblk, int pstride, int d, int nb, int64_t N, double alpha,
@@ -510,6 +529,9 @@ struct mf_process {
   int64_t sel_cap = 0;             // list entries per block
   int* d_sel = nullptr;            // [MAX_BLOCKS][sel_cap]
   int* d_selcnt = nullptr;         // [MAX_BLOCKS]
+  double* d_selw = nullptr;        // [MAX_BLOCKS][sel_cap] weights of the kept events (observables)
+  int64_t selw_cap = 0;
+  double* d_obs = nullptr;         // observables: block partials, reduced rows, running sums
 };
 
 namespace {
@@ -758,6 +780,8 @@ void mf_process_destroy(mf_process* p) {
   if (p->ws && p->L.ws_free) p->L.ws_free(p->ws);
   hipFree(p->d_sel);
   hipFree(p->d_selcnt);
+  hipFree(p->d_selw);
+  hipFree(p->d_obs);
   delete p;
 }
 
@@ -828,6 +852,36 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
     mf_status st = ensure_select(p, o->n_events, s);
     if (st != MF_OK) return st;
   }
+  // observable histograms: validation and buffers
+  ObsSpec ospec{};
+  const int OW = o->obs ? N_OBS * o->obs->nbins * 2 : 0;  // histogram row width
+  if (o->obs) {
+    const mf_observables* ob = o->obs;
+    if (o->flow || !p->L.fused || !p->L.observables)
+      return fail(MF_ENOTSUP, "observable histograms are built for VEGAS iterations of the single-kernel processes");
+    if (ob->nbins < 1 || ob->nbins > MAX_OBS_BINS) return fail(MF_EINVAL, "nbins must be in 1..%d", MAX_OBS_BINS);
+    if (!ob->sums) return fail(MF_EINVAL, "NULL histogram output");
+    ospec.nbins = ob->nbins;
+    for (int q = 0; q < N_OBS; ++q) {
+      if (!(std::isfinite(ob->lo[q]) && std::isfinite(ob->hi[q]) && ob->hi[q] > ob->lo[q]))
+        return fail(MF_EINVAL, "observable %d: need finite lo < hi", q);
+      ospec.lo[q] = ob->lo[q];
+      ospec.scale[q] = ob->nbins / (ob->hi[q] - ob->lo[q]);
+    }
+    if (p->selw_cap < p->sel_cap) {
+      HIP_TRY(hipStreamSynchronize(s));
+      (void)hipFree(p->d_selw);
+      p->d_selw = nullptr;
+      p->selw_cap = 0;
+      if (hipMalloc(&p->d_selw, sizeof(double) * (size_t)MAX_BLOCKS * p->sel_cap) != hipSuccess)
+        return fail(MF_ENOMEM, "weights of the kept events");
+      p->selw_cap = p->sel_cap;
+    }
+    if (!p->d_obs && hipMalloc(&p->d_obs, sizeof(double) * (size_t)(MAX_BLOCKS + RED_ROWS + 1) * N_OBS *
+                                              MAX_OBS_BINS * 2) != hipSuccess)
+      return fail(MF_ENOMEM, "observable partials");
+    HIP_TRY(hipMemsetAsync(p->d_obs + (size_t)(MAX_BLOCKS + RED_ROWS) * OW, 0, sizeof(double) * OW, s));
+  }
   std::vector<double> rec((size_t)REC * o->n_iter, 0.0);
   double time_to_target = -1.0;
   int done = 0;
@@ -857,7 +911,17 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
                          p->d_part, p->pstride);
     } else if (p->L.fused) {
       p->L.vegas(p->dc, p->d_edges, iter, o->n_events, p->cfg.seed, p->d_part, p->pstride, nblk, lds, p->d_sel,
-                 p->d_selcnt, p->sel_cap, s);
+                 p->d_selcnt, p->sel_cap, o->obs ? p->d_selw : nullptr, s);
+      if (o->obs && it >= o->warmup_iters_discarded) {
+        double* opart = p->d_obs;
+        double* orows = p->d_obs + (size_t)MAX_BLOCKS * OW;
+        double* osums = p->d_obs + (size_t)(MAX_BLOCKS + RED_ROWS) * OW;
+        p->L.observables(p->dc, p->d_edges, iter, p->cfg.seed, p->d_sel, p->d_selcnt, p->sel_cap, p->d_selw, ospec,
+                         opart, nblk, s);
+        const int R = nblk < RED_ROWS ? nblk : RED_ROWS;
+        hipLaunchKernelGGL(k_obs_reduce, dim3((OW + 255) / 256, R), dim3(256), 0, s, opart, nblk, OW, R, orows);
+        hipLaunchKernelGGL(k_obs_accumulate, dim3((OW + 255) / 256), dim3(256), 0, s, orows, R, OW, osums);
+      }
     } else {
       const int64_t N = o->n_events;
       hipLaunchKernelGGL(k_stage_points, dim3(nblk), dim3(256), sizeof(double) * d * (nb + 1), s, p->d_edges, d, nb,
@@ -945,6 +1009,11 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   r->kernel_seconds = ksec;
   for (int it = 0; it < done; ++it)
     if (rec[(size_t)REC * it + 6] != 0.0) return fail(MF_ERANGE, "grid refinement failed at iteration %d", it);
+  if (o->obs) {
+    HIP_TRY(hipMemcpyAsync(o->obs->sums, p->d_obs + (size_t)(MAX_BLOCKS + RED_ROWS) * OW, sizeof(double) * OW,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   // the integrand never returns a non-finite value, so under a learned
   // proposal a non-finite weight comes from the proposal's density: the
   // estimate would silently miss those points

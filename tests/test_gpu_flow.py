@@ -384,6 +384,28 @@ def test_training_batches_estimate_the_integral():
     assert e2.time_to_target > 0 and e2.error / e2.integral <= 3e-3 and e2.n_events_total < 400 * 16384
 
 
+def test_broken_proposal_is_an_error_not_a_biased_estimate():
+    """A proposal whose densities are not finite (here: every parameter NaN,
+    as after a diverged training step) must not yield an estimate that
+    silently drops its points: on-policy training and a flow-driven
+    integration both report MF_ERANGE.  Every kernel on this path runs fixed
+    loops and clamped indices, so NaN inputs only propagate as values."""
+    p = mf.Process(mf.Config(process="gg>ttxg"))
+    p.integrate(2, 200_000, adapt=True)
+    f = mf.Flow(7, max_batch=4096)
+    f.set_params(np.full(f.param_count, np.nan, dtype=np.float32))
+    with pytest.raises(mf.MFError) as e:
+        p.train_flow_online(f, 2, batch=4096, lr=1e-3, loss="variance", flow_mix=0.2)
+    assert e.value.status == mf.MF_ERANGE
+    with pytest.raises(mf.MFError) as e:
+        p.integrate(1, 100_000, adapt=False, flow=f, flow_mix=0.2)
+    assert e.value.status == mf.MF_ERANGE
+    # a healthy proposal on the same process still integrates
+    g = mf.Flow(7, max_batch=4096)
+    r = p.integrate(1, 100_000, adapt=False, flow=g, flow_mix=0.2)
+    assert r.n_nonfinite == 0 and r.integral > 0.0
+
+
 def test_training_is_bitwise_reproducible():
     """Fixed-order reductions everywhere (no atomics): two identical on-policy
     trainings from the identity flow give bit-identical parameters and
