@@ -178,6 +178,41 @@ FP32_VECTOR_PEAK = 157.3e12  # MI355X FP32 vector FLOP/s (published; packed FP32
 FP32_MATRIX_PEAK = 157.3e12  # MI355X FP32 matrix-core FLOP/s (dense)
 
 
+def ttggg_helicity_sampling(events: int = 4_000_000) -> dict:
+    """g g -> t t~ g g g with one polarisation state per point (drawn by
+    Philox, weight x 64) against the sum over the 64 states: events/s, the
+    per-event relative variance of the weights on the same adapted grid, and
+    the wall time of plain FP32 VEGAS to 1e-3 from process creation."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+
+    out = {}
+    for mode in (0, 1):
+        cfg = mf.Config(process="gg>ttxggg", precision="fp32", dr_min=0.4, helicity=mode)
+        w = mf.Process(cfg)
+        w.integrate(1, 200_000, adapt=True)  # load the kernels (untimed)
+        del w
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = mf.Process(cfg)
+        r = p.integrate(200, events, target_rel_err=1e-3, adapt=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        wv, _ = p.weights(1 << 30, events)
+        st = mf.weight_stats(wv)
+        del wv
+        t1 = time.perf_counter()
+        r2 = p.integrate(3, events, adapt=False, iter_offset=1 << 20)
+        dt = time.perf_counter() - t1
+        out["summed_states" if mode == 0 else "sampled_state"] = {
+            "time_to_1e-3_s": t, "iterations": r.n_iter_done, "events": r.n_events_total, "integral_pb": r.integral,
+            "error_pb": r.error, "events_per_s": 3 * events / dt, "relative_variance_per_event": st["relvar"],
+            "check_integral_pb": [r2.integral, r2.error]}
+        del p
+    return out
+
+
 def ttggg_throughput(events: int = 4_000_000, iters: int = 3) -> dict:
     """g g -> t t~ g g g with FP32 amplitudes: events/s of staged VEGAS
     iterations (after a warm-up that adapts the grid), and the algorithmic
@@ -368,6 +403,7 @@ def secondary(seed_events: int) -> dict:
     out["ttgg_flow_vs_vegas"] = flow_comparison()
     out["ttg_observables"] = ttg_observables()
     out["ttggg_fp32"] = ttggg_throughput()
+    out["ttggg_helicity_sampling"] = ttggg_helicity_sampling()
     out["ttggg_flow_vs_vegas"] = ttggg_flow_comparison()
     out["flow_roofline"] = flow_roofline()
     grads = {}
@@ -432,7 +468,7 @@ def main() -> int:
         print(json.dumps({"ttg_observables": ttg_observables()}), flush=True)
         return 0
     if args.ttggg_only:
-        print(json.dumps({"ttggg_fp32": ttggg_throughput(),
+        print(json.dumps({"ttggg_fp32": ttggg_throughput(), "ttggg_helicity_sampling": ttggg_helicity_sampling(),
                           "ttggg_flow_vs_vegas": ttggg_flow_comparison()}), flush=True)
         return 0
     if args.workload in ("ttgg", "ttggg"):

@@ -79,6 +79,20 @@ typedef struct {
   int32_t n_bins;          /* VEGAS bins per dimension, 1..64 */
   double alpha;            /* VEGAS refinement damping exponent, > 0 */
   uint64_t seed;           /* Philox key word 0 for in-library sampling */
+  int32_t helicity;        /* polarisation states of g g -> t t~ g g g (other
+                              processes: 0 only, else MF_ENOTSUP):
+                              0 = sum over all 64 states (antitop helicity x
+                                  gluon polarisations; both top helicities
+                                  always summed);
+                              1 = one state per point, drawn by Philox4x64-10
+                                  from the point itself (counter = the bit
+                                  patterns of its first two coordinates, key
+                                  (seed, 5)), weighted by 64: an unbiased
+                                  estimate of the sum at 1/64 of the amplitude
+                                  work;
+                              2 + k = only state k (0..63), weight not scaled
+                                  (the 64 single-state integrands add up to
+                                  the sum; for checks) */
 } mf_config;
 
 typedef struct mf_process mf_process;

@@ -47,6 +47,7 @@ class _Config(ctypes.Structure):
         ("n_bins", ctypes.c_int32),
         ("alpha", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("helicity", ctypes.c_int32),
     ]
 
 
@@ -243,6 +244,7 @@ class Config:
     n_bins: int = 50
     alpha: float = 1.5
     seed: int = 2105105290
+    helicity: int = 0  # g g -> t t~ g g g: 0 sum, 1 one sampled state (x64), 2 + k only state k
 
     def _c(self) -> _Config:
         c = _Config()
@@ -253,6 +255,7 @@ class Config:
         for k in range(20):
             c.pdf_params[k] = float(self.pdf_params[k])
         c.n_bins, c.alpha, c.seed = self.n_bins, self.alpha, self.seed
+        c.helicity = self.helicity
         return c
 
 

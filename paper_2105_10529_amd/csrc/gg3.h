@@ -166,7 +166,7 @@ __device__ __forceinline__ void ordering_amp(const V4<R> (&Jp)[5], const V4<R> (
   A1 = ubar_dot(UB[1], F);
 }
 
-// Partial amplitudes of states s0 .. s0 + SP - 1 for the passing events
+// Partial amplitudes of states s0 .. s0 + ns - 1 for the passing events
 // idx[0 .. nc-1] of this chunk, written to
 //   amp[((slice * NQ + ordering / 4) * ld + j) * 4 + ordering % 4]
 // with slice = ((state - s0) * 2 + top helicity) * 2 + (0: re, 1: im) and
@@ -174,9 +174,12 @@ __device__ __forceinline__ void ordering_amp(const V4<R> (&Jp)[5], const V4<R> (
 // past nc recompute the last event into columns below ld, never read as
 // results.  The propagator factors of every gluon subset are formed in FP64
 // from the FP64 momenta and kept per lane in LDS, indexed by subset.
+// With c.helicity != 0 each lane evaluates one state of its own (ns = 1):
+// drawn by Philox from the point's first two coordinates (mode 1) or the
+// fixed state helicity - 2; the ordering loop stays wave-uniform.
 template <class R>
 __global__ void __launch_bounds__(AWAVE) k_g3_amp(DevCfg c, const double* __restrict__ u, int64_t n,
-                                                  const int* __restrict__ idx, int64_t nc, int s0,
+                                                  const int* __restrict__ idx, int64_t nc, int s0, int ns,
                                                   R* __restrict__ amp, int64_t ld) {
   // Per-lane tables (each lane reads only its own column, so no barriers):
   __shared__ R gtab[32][AWAVE];        // -1 / P_S^2 for gluon subsets S (>= 2 gluons)
@@ -237,9 +240,18 @@ __global__ void __launch_bounds__(AWAVE) k_g3_amp(DevCfg c, const double* __rest
   }
   const int64_t sstride = (int64_t)NQ * ld * 4;
   R* out = amp + j * 4;
+  int own = -1;  // this lane's state when states are sampled or fixed
+  if (c.helicity == 1) {
+    const U4 r = philox4x64_10((uint64_t)__double_as_longlong(x[0]), (uint64_t)__double_as_longlong(x[1]), 0, 0,
+                               c.seed, 5);
+    own = (int)(r.x0 >> 58);
+  } else if (c.helicity >= 2) {
+    own = c.helicity - 2;
+  }
 #pragma unroll 1
-  for (int st = s0; st < s0 + SP; ++st) {
-    const int ht = st >> 5, hg = st & 31;
+  for (int st = s0; st < s0 + ns; ++st) {
+    const int sx = own >= 0 ? own : st;
+    const int ht = sx >> 5, hg = sx & 31;
     const Sp<R> V = vtab[ht][lane];
     R* o4 = out + (int64_t)((st - s0) * 4) * sstride;
 #pragma unroll 1
@@ -280,7 +292,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f4 load_f4(const float* p) { return *reinterpret_cast<const f4*>(p); }
 
-// Colour sum of one pass over the SLICES slices of the buffer for the nc
+// Colour sum of one pass over the nsl slices (a multiple of 4) of the buffer for the nc
 // events of the chunk.  C in LDS in A-operand order: entry
 // ((rb * 8 + s) * 64 + l) * 4 + r holds C[16 rb + l % 16][16 s + 4 (l / 16) + r]
 // (zero beyond the 120 orderings).  For the MFMA step (s, r) lane l supplies
@@ -290,7 +302,7 @@ __device__ __forceinline__ f4 load_f4(const float* p) { return *reinterpret_cast
 // amplitudes are the B values the lane loaded for s = rb.
 // first: the pass overwrites me[]; last: it also writes the event weights.
 __global__ void __launch_bounds__(CBLOCK) k_g3_colour(const float* __restrict__ amp, int64_t ld, int64_t nc,
-                                                      int first, int last, double* __restrict__ me,
+                                                      int nsl, int first, int last, double* __restrict__ me,
                                                       const int* __restrict__ idx, const double* __restrict__ wpre,
                                                       double* __restrict__ w, double inv_den) {
   __shared__ float cs[8 * 8 * 64 * 4];
@@ -307,7 +319,7 @@ __global__ void __launch_bounds__(CBLOCK) k_g3_colour(const float* __restrict__ 
     const int64_t c0 = tile * CT;
     double sum[2] = {0.0, 0.0};
 #pragma unroll 1
-    for (int sl = wave * (SLICES / 4); sl < (wave + 1) * (SLICES / 4); ++sl) {
+    for (int sl = wave * (nsl / 4); sl < (wave + 1) * (nsl / 4); ++sl) {
       const float* base = amp + (int64_t)sl * NQ * ld * 4;
       f4 bv[8][2];
 #pragma unroll

@@ -67,8 +67,10 @@ hipError_t integrand(const DevCfg& c, const double* u, int64_t n, double* w, voi
   }
   const int64_t ld = ws->ld;
   float* amp = static_cast<float*>(ws->d_amp);
-  const double inv_den = 1.0 / AMP_M5_COLOUR_DEN;
-  constexpr int NPASS = STATES / SP;
+  // all states in passes of SP, or one state per point in a single pass
+  const bool own = c.helicity != 0;
+  const int NPASS = own ? 1 : STATES / SP, ns = own ? 1 : SP, nsl = 4 * ns;
+  const double inv_den = (c.helicity == 1 ? (double)STATES : 1.0) / AMP_M5_COLOUR_DEN;
   for (int64_t c0 = 0; c0 < count; c0 += ld) {
     const int64_t nc = (count - c0) < ld ? (count - c0) : ld;
     const int* idx = ws->d_idx + c0;
@@ -76,8 +78,8 @@ hipError_t integrand(const DevCfg& c, const double* u, int64_t n, double* w, voi
     const int64_t ntile = (nc + CT - 1) / CT;
     const unsigned cblk = (unsigned)(ntile < CMAX_BLOCKS ? ntile : CMAX_BLOCKS);
     for (int pass = 0; pass < NPASS; ++pass) {
-      hipLaunchKernelGGL((k_g3_amp<float>), dim3(ablk), dim3(AWAVE), 0, s, c, u, n, idx, nc, pass * SP, amp, ld);
-      hipLaunchKernelGGL(k_g3_colour, dim3(cblk), dim3(CBLOCK), 0, s, amp, ld, nc, pass == 0 ? 1 : 0,
+      hipLaunchKernelGGL((k_g3_amp<float>), dim3(ablk), dim3(AWAVE), 0, s, c, u, n, idx, nc, pass * SP, ns, amp, ld);
+      hipLaunchKernelGGL(k_g3_colour, dim3(cblk), dim3(CBLOCK), 0, s, amp, ld, nc, nsl, pass == 0 ? 1 : 0,
                          pass == NPASS - 1 ? 1 : 0, ws->d_me, idx, ws->d_wpre, w, inv_den);
     }
     G3_TRY(hipGetLastError());

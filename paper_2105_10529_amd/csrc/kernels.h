@@ -416,7 +416,9 @@ __global__ void __launch_bounds__(BLOCK) k_observables(DevCfg c, const double* _
 // ------------------------------------------------- gradient estimator
 template <int NG, int CH, class RA>
 __global__ void __launch_bounds__(BLOCK) k_grad_vegas(DevCfg c, const double* __restrict__ edges_g, uint64_t iter,
-                                                      int64_t N, uint64_t seed, double* __restrict__ partials) {
+                                                      int64_t N, uint64_t seed, double* __restrict__ partials,
+                                                      const int* __restrict__ list, const int* __restrict__ cnt,
+                                                      int64_t cap) {
   extern __shared__ double lds[];
   const int d = c.ndim, nb = c.nb;
   const int tid = threadIdx.x, wave = tid >> 6;
@@ -427,11 +429,16 @@ __global__ void __launch_bounds__(BLOCK) k_grad_vegas(DevCfg c, const double* __
   __syncthreads();
   double* acc = wacc + wave * GV * 4;
   // As in k_vegas, nothing per lane is carried across event chunks.
-  const int64_t nchunk = chunks_of_block(N);
+  // Only the events k_select kept: the others have zero weight and zero
+  // pathwise derivatives (the cut boundaries do not move with the grid and
+  // uniforms frozen).
+  const int* mine_list = list + (int64_t)blockIdx.x * cap;
+  const int nsel = __builtin_amdgcn_readfirstlane(cnt[blockIdx.x]);
+  const int64_t nchunk = (nsel + BLOCK - 1) / BLOCK;
   for (int64_t it = 0; it < nchunk; ++it) {
-    const int64_t e0 = chunk_base(it) + tid;
-    const bool live = e0 < N;
-    const int64_t e = live ? e0 : N - 1;
+    const int64_t j0 = it * BLOCK + tid;
+    const bool live = j0 < nsel;
+    const int64_t e = mine_list[live ? j0 : 0];
     double y[MAXD], x[MAXD];
     int bins[MAXD];
     event_uniforms((uint64_t)e, iter, seed, 0, d, y);
@@ -508,8 +515,11 @@ Launchers make_launchers() {
       hipLaunchKernelGGL((k_integrand_grad<NG, CH, RD>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w, dw);
     };
     L.grad_vegas = [](const DevCfg& c, const double* edges, uint64_t iter, int64_t N, uint64_t seed, double* part,
-                      int nblk, size_t lds, hipStream_t s) {
-      hipLaunchKernelGGL((k_grad_vegas<NG, CH, RD>), dim3(nblk), dim3(BLOCK), lds, s, c, edges, iter, N, seed, part);
+                      int nblk, size_t lds, int* list, int* cnt, int64_t cap, hipStream_t s) {
+      hipLaunchKernelGGL((k_select<NG>), dim3(nblk), dim3(BLOCK), sizeof(double) * c.ndim * (c.nb + 1), s, c, edges,
+                         iter, N, seed, list, cnt, cap);
+      hipLaunchKernelGGL((k_grad_vegas<NG, CH, RD>), dim3(nblk), dim3(BLOCK), lds, s, c, edges, iter, N, seed, part,
+                         list, cnt, cap);
     };
   }
   return L;

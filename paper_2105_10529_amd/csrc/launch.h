@@ -90,7 +90,9 @@ struct Launchers {
   // (their weights from vegas' wk output); per-block partial rows
   void (*observables)(const DevCfg&, const double*, uint64_t, uint64_t, const int*, const int*, int64_t,
                       const double*, const ObsSpec&, double*, int, hipStream_t);
-  void (*grad_vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, size_t, hipStream_t);
+  // selection (k_select) then the derivative estimator over the kept events
+  void (*grad_vegas)(const DevCfg&, const double*, uint64_t, int64_t, uint64_t, double*, int, size_t, int*, int*,
+                     int64_t, hipStream_t);
   // Multi-kernel integrand with a workspace held by the process handle
   // (*ws, created on first use, released with ws_free); used instead of
   // `integrand` when set.  Synchronises the stream (it reads the number of

@@ -700,6 +700,9 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
   const int ng = n_final_gluons(cfg->process);
   if (ng == 3 && cfg->precision != MF_PREC_FP32_AMP)
     return fail(MF_ENOTSUP, "g g -> t t~ g g g is built with FP32 amplitudes only");
+  if (cfg->helicity < 0 || cfg->helicity > 2 + 63) return fail(MF_EINVAL, "helicity mode %d", cfg->helicity);
+  if (cfg->helicity != 0 && ng != 3)
+    return fail(MF_ENOTSUP, "polarisation-state sampling is built for g g -> t t~ g g g only");
   if (channel_of(cfg->process) != 0 && cfg->precision != MF_PREC_FP64)
     return fail(MF_ENOTSUP, "quark channels are built in FP64 only");
   for (int i = 0; i < 20; i += 5)
@@ -719,6 +722,8 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
   c.mt = cfg->m_t;
   c.mu = mu;
   c.mu_is_mt = cfg->mu > 0.0 ? 0 : 1;
+  c.helicity = cfg->helicity;
+  c.seed = cfg->seed;
   c.pt_min = cfg->pt_min;
   c.eta_max = cfg->eta_max;
   c.dr_min = cfg->dr_min;
@@ -1187,7 +1192,10 @@ mf_status mf_grad(mf_process* p, const mf_integrate_opts* o, double* out, double
   const int nblk = blocks_for(o->n_events);
   const size_t lds = sizeof(double) * (d * (nb + 1) + WAVES * GV * 4);
   if (!p->L.grad_vegas) return fail(MF_ENOTSUP, "derivatives are not built for this process");
-  p->L.grad_vegas(p->dc, p->d_edges, o->iter_offset, o->n_events, p->cfg.seed, p->d_part, nblk, lds, s);
+  mf_status sst = ensure_select(p, o->n_events, s);
+  if (sst != MF_OK) return sst;
+  p->L.grad_vegas(p->dc, p->d_edges, o->iter_offset, o->n_events, p->cfg.seed, p->d_part, nblk, lds, p->d_sel,
+                  p->d_selcnt, p->sel_cap, s);
   mf_status st = check_stream_launch("k_grad_vegas");
   if (st != MF_OK) return st;
   hipLaunchKernelGGL(k_grad_finalize, dim3(1), dim3(64), 0, s, p->d_part, nblk, o->n_events, p->d_out);

@@ -39,6 +39,8 @@ struct DevCfg {
   const double* pdfc;  // [4][196] x f(x_i, mu), flavours g, u, d, u~
   const double* pdfd;  // [4][196] d(x f)/d mu at x_i
   const double* pdft;  // [8][196] d(x f)/d theta_k at x_i (flavour of theta_k)
+  int helicity;        // polarisation-state mode of the staged 5-gluon process (mf_config.helicity)
+  uint64_t seed;       // Philox key word 0 (the process seed)
 };
 
 // ------------------------------------------------------------------ Philox

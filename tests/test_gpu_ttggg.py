@@ -103,3 +103,47 @@ def test_fp64_and_derivatives_are_not_built():
     with pytest.raises(mf.MFError) as e:
         p.integrand_grad(x)
     assert e.value.status == mf.MF_ENOTSUP
+
+
+def test_single_states_add_up_to_the_sum_and_sampling_is_unbiased():
+    """Polarisation states of the 5-gluon process: the 64 single-state
+    integrands (helicity = 2 + k) add up to the summed integrand point by
+    point; the sampled mode (helicity = 1) is 64 times one of them, the same
+    state on every call for a given point, and its VEGAS estimate agrees with
+    the summed one within the errors."""
+    x = si.points_above_threshold(150, D, SQRT_S, MT, seed=35)
+    xd = to_dev_soa(x)
+    full = _proc().integrand(xd).cpu().numpy()
+    parts = []
+    for k in range(64):
+        pk = mf.Process(mf.Config(process="gg>ttxggg", precision="fp32", dr_min=0.4, helicity=2 + k))
+        parts.append(pk.integrand(xd).cpu().numpy())
+        pk.close()
+    parts = np.array(parts)
+    # each state's colour-summed |M|^2 is a positive-definite form, so every
+    # state carries the sign of the event's weight (which the PDF product can
+    # make negative near x -> 1, where the interpolant crosses zero); states
+    # whose amplitudes nearly vanish come out as FP32 rounding around zero
+    nz = full != 0.0
+    assert np.all(parts[:, nz] / full[nz] >= -1e-5)
+    assert np.all(parts[:, ~nz] == 0.0)
+    assert_close(parts.sum(axis=0), full, 1e-5)
+    ps = mf.Process(mf.Config(process="gg>ttxggg", precision="fp32", dr_min=0.4, helicity=1))
+    samp = ps.integrand(xd).cpu().numpy()
+    assert np.array_equal(samp, ps.integrand(xd).cpu().numpy())
+    match = np.isclose(samp[nz][None, :], 64.0 * parts[:, nz], rtol=1e-6, atol=0.0)
+    assert np.all(match.sum(axis=0) >= 1)  # each sampled value is 64 x one of the states
+    # the estimator is unbiased: VEGAS with sampled states agrees with the sum
+    grid = torch.from_numpy(si.random_grid(D, 50, seed=8)).to("cuda")
+    rs = ps.integrate(3, 400_000, adapt=False, iter_offset=50, edges_in=grid)
+    rf = _proc().integrate(2, 200_000, adapt=False, iter_offset=60, edges_in=grid)
+    assert abs(rs.integral - rf.integral) < 4.0 * np.hypot(rs.error, rf.error), (rs, rf)
+
+
+def test_helicity_modes_are_validated():
+    with pytest.raises(mf.MFError) as e:
+        mf.Process(mf.Config(process="gg>ttxg", helicity=1))
+    assert e.value.status == mf.MF_ENOTSUP
+    with pytest.raises(mf.MFError) as e:
+        mf.Process(mf.Config(process="gg>ttxggg", precision="fp32", dr_min=0.4, helicity=66))
+    assert e.value.status == mf.MF_EINVAL
