@@ -124,6 +124,7 @@ class _Cfg(ctypes.Structure):
         ("eta_max", ctypes.c_double),
         ("dr_min", ctypes.c_double),
         ("pdf", ctypes.c_double * 20),
+        ("dyn_scale", ctypes.c_int),
     ]
 
 
@@ -143,6 +144,7 @@ class Config:
     eta_max: float = 2.5
     dr_min: float = 0.0
     pdf: np.ndarray = field(default_factory=default_pdf)
+    dyn_scale: bool = False   # True: mu = H_T / 2 per event (half the final-state transverse masses)
 
     @property
     def ndim(self) -> int:
@@ -162,6 +164,7 @@ class Oracle:
         c.pt_min, c.eta_max, c.dr_min = cfg.pt_min, cfg.eta_max, cfg.dr_min
         for k in range(20):
             c.pdf[k] = float(cfg.pdf[k])
+        c.dyn_scale = int(cfg.dyn_scale)
         if cfg.channel == "gg":
             lib()
             _install_colour((cfg.n_g + 2,))

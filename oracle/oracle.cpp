@@ -629,6 +629,7 @@ typedef struct {
   int channel;   // 0: g g, 1: u u~ (+ u~ u), 2: d d~ (+ d~ d)
   double sqrt_s, m_t, mu, alpha_s, pt_min, eta_max, dr_min;
   double pdf[20];  // (A,a,b,c,d) for g, u, d, u~
+  int dyn_scale;   // 1: factorisation scale mu = H_T / 2 per event (else mu / m_t)
 } or_cfg;
 }
 
@@ -809,6 +810,15 @@ static R integrand_T(const State& S, const double* x, R mt, int dir, double* mom
   if (!pass_cuts(c, ng, gl.data(), x1, x2)) return R(0.0);
   if (pass_out) *pass_out = 1;
   R mu = (c.mu > 0.0) ? R(c.mu) : mt;
+  if (c.dyn_scale) {
+    // mu = H_T / 2: half the sum of the transverse masses of the final state
+    // (the tops with mass m_t, the massless gluons)
+    const P4<R>& t = fs[ng];
+    const P4<R>& tb = fs[ng + 1];
+    R ht = sqrt(mt * mt + t.x * t.x + t.y * t.y) + sqrt(mt * mt + tb.x * tb.x + tb.y * tb.y);
+    for (int i = 0; i < ng; ++i) ht = ht + sqrt(fs[i].x * fs[i].x + fs[i].y * fs[i].y);
+    mu = ht * R(0.5);
+  }
   double E = 0.5 * std::sqrt(shat);
   P4<R> p1{R(E), R(0.0), R(0.0), R(E)}, p2{R(E), R(0.0), R(0.0), R(-E)};
   double gs2 = 4.0 * M_PI * c.alpha_s;  // g^2
