@@ -262,6 +262,28 @@ def ttggg_flow_comparison() -> dict:
                                              precisions=("fp32",), long_steps=150, helicity=1)}
 
 
+def ttg_dynamic_scale(events: int = EVENTS, iters: int = 10) -> dict:
+    """The benchmark workload with the dynamic scale mu = H_T / 2 (full (x, Q)
+    PDF interpolation per event): events/s and the cross section, beside the
+    fixed scale mu = m_t."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+
+    out = {}
+    for dyn in (False, True):
+        p = mf.Process(mf.Config(process="gg>ttxg", dynamic_scale=dyn))
+        p.integrate(2, events, adapt=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = p.integrate(iters, events, adapt=True, iter_offset=2)
+        dt = time.perf_counter() - t0
+        out["dynamic_mu_ht_half" if dyn else "fixed_mu_mt"] = {
+            "events_per_s": iters * events / dt, "kernel_ms_per_iteration": 1e3 * r.kernel_seconds / iters,
+            "integral_pb": r.integral, "error_pb": r.error}
+    return out
+
+
 def ttg_observables(events: int = EVENTS, iters: int = 10) -> dict:
     """Observable histograms filled during the benchmark workload (g g -> t t~ g
     FP64, 2 adapting warm-up iterations, then `iters` iterations of 1e7 events
@@ -318,6 +340,7 @@ def fp32_subsample_check(n: int = 100_000) -> dict:
     nz = ref != 0.0
     r32 = np.abs(w32[nz] - ref[nz]) / np.abs(ref[nz])
     r64 = np.abs(w64[nz] - ref[nz]) / np.abs(ref[nz])
+
     return {"events": n, "nonzero": int(nz.sum()), "same_zero_pattern": bool(np.array_equal(w32 != 0, nz)),
             "fp32_per_event_rel_err_max": float(r32.max()), "fp32_per_event_rel_err_median": float(np.median(r32)),
             "fp32_per_event_rel_err_q999": float(np.quantile(r32, 0.999)),
@@ -408,6 +431,7 @@ def secondary(seed_events: int) -> dict:
     out["ttgg_fp32_vs_oracle_subsample"] = fp32_subsample_check()
     out["ttgg_flow_vs_vegas"] = flow_comparison()
     out["ttg_observables"] = ttg_observables()
+    out["ttg_dynamic_scale"] = ttg_dynamic_scale()
     out["ttggg_fp32"] = ttggg_throughput()
     out["ttggg_helicity_sampling"] = ttggg_helicity_sampling()
     out["ttggg_flow_vs_vegas"] = ttggg_flow_comparison()
@@ -471,7 +495,8 @@ def main() -> int:
         print(json.dumps({"ttgg_flow_vs_vegas": flow_comparison(), "flow_roofline": flow_roofline()}), flush=True)
         return 0
     if args.observables_only:
-        print(json.dumps({"ttg_observables": ttg_observables()}), flush=True)
+        print(json.dumps({"ttg_observables": ttg_observables(), "ttg_dynamic_scale": ttg_dynamic_scale()}),
+              flush=True)
         return 0
     if args.ttggg_only:
         print(json.dumps({"ttggg_fp32": ttggg_throughput(), "ttggg_helicity_sampling": ttggg_helicity_sampling(),

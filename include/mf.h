@@ -93,6 +93,12 @@ typedef struct {
                               2 + k = only state k (0..63), weight not scaled
                                   (the 64 single-state integrands add up to
                                   the sum; for checks) */
+  int32_t dynamic_scale;   /* 0: the fixed scale mu above; 1: per event
+                              mu = H_T / 2, half the sum of the final-state
+                              transverse masses (tops of mass m_t, massless
+                              gluons), with the PDFs interpolated in x and Q
+                              on the full knot grid (the derivative entry
+                              points are then MF_ENOTSUP) */
 } mf_config;
 
 typedef struct mf_process mf_process;

@@ -48,6 +48,7 @@ class _Config(ctypes.Structure):
         ("alpha", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("helicity", ctypes.c_int32),
+        ("dynamic_scale", ctypes.c_int32),
     ]
 
 
@@ -245,6 +246,7 @@ class Config:
     alpha: float = 1.5
     seed: int = 2105105290
     helicity: int = 0  # g g -> t t~ g g g: 0 sum, 1 one sampled state (x64), 2 + k only state k
+    dynamic_scale: bool = False  # True: mu = H_T / 2 per event
 
     def _c(self) -> _Config:
         c = _Config()
@@ -256,6 +258,7 @@ class Config:
             c.pdf_params[k] = float(self.pdf_params[k])
         c.n_bins, c.alpha, c.seed = self.n_bins, self.alpha, self.seed
         c.helicity = self.helicity
+        c.dynamic_scale = int(self.dynamic_scale)
         return c
 
 

@@ -87,8 +87,9 @@ __global__ void __launch_bounds__(BLOCK) k_g3_select(DevCfg c, const double* __r
   double shat_k, wps;
   V4<double> gl[NG], top, atop;
   bool ok = kinematics(c, x, shat_k, gl, top, atop, wps);
+  const double tq = c.dyn_scale ? q_position(half_ht<NG>(c.mt, top, atop, gl)) : 0.0;
   const double pre = c.norm / (2.0 * shat_k * x[0] * x[1]) * wps *
-                     (hermite_x(c.pdfc, x_position(c, x[0])) * hermite_x(c.pdfc, x_position(c, x[1])));
+                     (pdf_at(c, c.pdfc, 0, x_position(c, x[0]), tq) * pdf_at(c, c.pdfc, 0, x_position(c, x[1]), tq));
   ok = ok && live && isfinite(pre) && pre != 0.0;
   if (live) {
     w[e] = 0.0;

@@ -123,6 +123,17 @@ __global__ void k_pdf_setup(PdfParams P, double mu, double* pdfc, double* pdfd, 
   }
 }
 
+// The full knot table x f(x_i, Q_j) of the four flavours, [4][50][196], for
+// the dynamic scale (the same knots and formula as the fixed-scale set-up).
+__global__ void k_pdf_table(PdfParams P, double* tab) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * NQK * NXK) return;
+  const int f = t / (NQK * NXK), j = (t / NXK) % NQK, i = t % NXK;
+  const double x = pow(10.0, -9.0 + 9.0 * i / 195.0);
+  const double Q = PDF_Q0 * pow(PDF_QMAX / PDF_Q0, j / 49.0);
+  tab[t] = pdf_formula(P.p + 5 * f, x, log(Q / PDF_Q0), -1);
+}
+
 __global__ void k_fill_uniform(double* edges, int d, int nb) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d * (nb + 1)) return;
@@ -532,6 +543,7 @@ struct mf_process {
   double* d_selw = nullptr;        // [MAX_BLOCKS][sel_cap] weights of the kept events (observables)
   int64_t selw_cap = 0;
   double* d_obs = nullptr;         // observables: block partials, reduced rows, running sums
+  double* d_pdfq = nullptr;        // [4][50][196] full PDF knot table (dynamic scale)
 };
 
 namespace {
@@ -703,6 +715,8 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
   if (cfg->helicity < 0 || cfg->helicity > 2 + 63) return fail(MF_EINVAL, "helicity mode %d", cfg->helicity);
   if (cfg->helicity != 0 && ng != 3)
     return fail(MF_ENOTSUP, "polarisation-state sampling is built for g g -> t t~ g g g only");
+  if (cfg->dynamic_scale != 0 && cfg->dynamic_scale != 1)
+    return fail(MF_EINVAL, "dynamic_scale must be 0 or 1");
   if (channel_of(cfg->process) != 0 && cfg->precision != MF_PREC_FP64)
     return fail(MF_ENOTSUP, "quark channels are built in FP64 only");
   for (int i = 0; i < 20; i += 5)
@@ -724,6 +738,8 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
   c.mu_is_mt = cfg->mu > 0.0 ? 0 : 1;
   c.helicity = cfg->helicity;
   c.seed = cfg->seed;
+  c.dyn_scale = cfg->dynamic_scale;
+  c.pdfq = nullptr;
   c.pt_min = cfg->pt_min;
   c.eta_max = cfg->eta_max;
   c.dr_min = cfg->dr_min;
@@ -759,6 +775,14 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
                      p->d_pdf + 8 * NXK);
   hipLaunchKernelGGL(k_fill_uniform, dim3((p->ndim * (p->nb + 1) + 255) / 256), dim3(256), 0, 0, p->d_edges,
                      p->ndim, p->nb);
+  if (c.dyn_scale) {
+    if (hipMalloc(&p->d_pdfq, sizeof(double) * 4 * NQK * NXK) != hipSuccess) {
+      hipGetLastError();
+      return cleanup(fail(MF_ENOMEM, "device allocation failed"));
+    }
+    c.pdfq = p->d_pdfq;
+    hipLaunchKernelGGL(k_pdf_table, dim3((4 * NQK * NXK + 255) / 256), dim3(256), 0, 0, P, p->d_pdfq);
+  }
   if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(MF_EDEVICE, "table set-up failed"));
   *out = p;
   return MF_OK;
@@ -787,6 +811,7 @@ void mf_process_destroy(mf_process* p) {
   hipFree(p->d_selcnt);
   hipFree(p->d_selw);
   hipFree(p->d_obs);
+  hipFree(p->d_pdfq);
   delete p;
 }
 
@@ -808,6 +833,7 @@ mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w
   hipStream_t s = (hipStream_t)stream;
   const int nblk = blocks_for(n);
   if (!p->L.integrand_grad) return fail(MF_ENOTSUP, "derivatives are not built for this process");
+  if (p->dc.dyn_scale) return fail(MF_ENOTSUP, "derivatives are not built with the dynamic scale");
   p->L.integrand_grad(p->dc, u, n, w, dw, nblk, s);
   return check_stream_launch("k_integrand_grad");
 }
@@ -1192,6 +1218,7 @@ mf_status mf_grad(mf_process* p, const mf_integrate_opts* o, double* out, double
   const int nblk = blocks_for(o->n_events);
   const size_t lds = sizeof(double) * (d * (nb + 1) + WAVES * GV * 4);
   if (!p->L.grad_vegas) return fail(MF_ENOTSUP, "derivatives are not built for this process");
+  if (p->dc.dyn_scale) return fail(MF_ENOTSUP, "derivatives are not built with the dynamic scale");
   mf_status sst = ensure_select(p, o->n_events, s);
   if (sst != MF_OK) return sst;
   p->L.grad_vegas(p->dc, p->d_edges, o->iter_offset, o->n_events, p->cfg.seed, p->d_part, nblk, lds, p->d_sel,

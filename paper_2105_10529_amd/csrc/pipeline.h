@@ -41,6 +41,8 @@ struct DevCfg {
   const double* pdft;  // [8][196] d(x f)/d theta_k at x_i (flavour of theta_k)
   int helicity;        // polarisation-state mode of the staged 5-gluon process (mf_config.helicity)
   uint64_t seed;       // Philox key word 0 (the process seed)
+  int dyn_scale;       // 1: factorisation scale mu = H_T / 2 per event
+  const double* pdfq;  // [4][50][196] x f(x_i, Q_j) (dynamic scale), else unused
 };
 
 // ------------------------------------------------------------------ Philox
@@ -110,6 +112,44 @@ __device__ __forceinline__ double hermite_x(const double* f, double t) {
   return h00 * f0 + h10 * s0 + h01 * f1 + h11 * s1;
 }
 __device__ __forceinline__ double x_position(const DevCfg& c, double x) { return (log(x) - c.lx0) * c.ihx; }
+
+// Dynamic scale: mu = H_T / 2, half the sum of the final-state transverse
+// masses (tops of mass m_t, massless gluons), and x f(x, mu) from the full
+// knot table by the same tensor-product Hermite scheme as the fixed-scale
+// tables (along x on the four Q rows around mu, then along Q).
+template <int NG, class RK>
+__device__ __forceinline__ double half_ht(double mt, const V4<RK>& top, const V4<RK>& atop, const V4<double>* gl) {
+  const double tx = val(top.x), ty = val(top.y), ax = val(atop.x), ay = val(atop.y);
+  double ht = sqrt(mt * mt + tx * tx + ty * ty) + sqrt(mt * mt + ax * ax + ay * ay);
+#pragma unroll
+  for (int i = 0; i < NG; ++i) ht += sqrt(gl[i].x * gl[i].x + gl[i].y * gl[i].y);
+  return 0.5 * ht;
+}
+__device__ __forceinline__ double q_position(double mu) {
+  return (log(mu) - log(PDF_Q0)) / ((log(PDF_QMAX) - log(PDF_Q0)) / (NQK - 1));
+}
+__device__ __forceinline__ double hermite_xq(const double* tab, double tx, double tq) {
+  int j = (int)floor(tq);
+  j = j < 0 ? 0 : (j > NQK - 2 ? NQK - 2 : j);
+  const double u = tq - j;
+  double F[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int jj = j - 1 + r;
+    jj = jj < 0 ? 0 : (jj > NQK - 1 ? NQK - 1 : jj);
+    F[r] = hermite_x(tab + (int64_t)jj * NXK, tx);
+  }
+  const double s0 = (j == 0) ? F[2] - F[1] : 0.5 * (F[2] - F[0]);
+  const double s1 = (j + 1 == NQK - 1) ? F[2] - F[1] : 0.5 * (F[3] - F[1]);
+  const double u2 = u * u, u3 = u2 * u;
+  return (2.0 * u3 - 3.0 * u2 + 1.0) * F[1] + (u3 - 2.0 * u2 + u) * s0 + (-2.0 * u3 + 3.0 * u2) * F[2] +
+         (u3 - u2) * s1;
+}
+// x f of flavour fl at x-table position t: from the fixed-scale tables pdf1
+// ([4][196]) or, with the dynamic scale, from the full table at Q position tq
+__device__ __forceinline__ double pdf_at(const DevCfg& c, const double* pdf1, int fl, double t, double tq) {
+  return c.dyn_scale ? hermite_xq(c.pdfq + (int64_t)fl * NQK * NXK, t, tq) : hermite_x(pdf1 + fl * NXK, t);
+}
 
 // ------------------------------------------------------------ phase space
 template <class R>
@@ -385,10 +425,11 @@ __device__ __forceinline__ EventOut<RK> event_weight(const DevCfg& c, const doub
   out.t2 = x_position(c, x2);
   RK pre = RK(c.norm / (2.0 * shat_k * x1 * x2)) * wps;
   const RK zero = RK(0.0);
+  const double tq = c.dyn_scale ? q_position(half_ht<NG>(val(mt), top, atop, gl)) : 0.0;
   if constexpr (CH == 0) {
     RK me = to_k(me_gg<NG, RA, RK>(E, gl, top, atop, mt), (RK*)nullptr);
     RK r1 = pre * me;
-    RK w = r1 * RK(hermite_x(pdf, out.t1) * hermite_x(pdf, out.t2));
+    RK w = r1 * RK(pdf_at(c, pdf, 0, out.t1, tq) * pdf_at(c, pdf, 0, out.t2, tq));
     out.r1 = ok ? r1 : zero;
     out.r2 = zero;
     out.w = ok ? w : zero;
@@ -396,10 +437,9 @@ __device__ __forceinline__ EventOut<RK> event_weight(const DevCfg& c, const doub
     V4<double> p1{E, 0.0, 0.0, E}, p2{E, 0.0, 0.0, -E};
     RK r1 = pre * to_k(me_qqbar<RA, RK>(p1, p2, top, atop, mt), (RK*)nullptr);
     RK r2 = pre * to_k(me_qqbar<RA, RK>(p2, p1, top, atop, mt), (RK*)nullptr);
-    const double* fq = pdf + (CH == 1 ? 1 : 2) * NXK;
-    const double* fa = pdf + 3 * NXK;
-    double q1 = hermite_x(fq, out.t1), a2 = hermite_x(fa, out.t2), a1 = hermite_x(fa, out.t1),
-           q2 = hermite_x(fq, out.t2);
+    const int fq = CH == 1 ? 1 : 2, fa = 3;
+    double q1 = pdf_at(c, pdf, fq, out.t1, tq), a2 = pdf_at(c, pdf, fa, out.t2, tq),
+           a1 = pdf_at(c, pdf, fa, out.t1, tq), q2 = pdf_at(c, pdf, fq, out.t2, tq);
     RK w = r1 * RK(q1 * a2) + r2 * RK(a1 * q2);
     out.r1 = ok ? r1 : zero;
     out.r2 = ok ? r2 : zero;
