@@ -473,7 +473,7 @@ def main() -> int:
                     help="only run a plain device-to-device copy of MIB MiB (to calibrate HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
         return 2
 

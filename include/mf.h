@@ -45,7 +45,7 @@ typedef enum {
   MF_ERANGE = 2,   /* value outside a supported range (grid order, PDF range) */
   MF_ENOMEM = 3,   /* device allocation failed */
   MF_EDEVICE = 4,  /* HIP runtime error (launch, copy, synchronisation) */
-  MF_ENOTSUP = 5   /* combination not supported by this build */
+  MF_ENOTSUP = 5   /* combination not provided by the library */
 } mf_status;
 
 typedef enum {
