@@ -110,26 +110,25 @@ __global__ void __launch_bounds__(BLOCK) k_g3_select(DevCfg c, const double* __r
 // three- and four-gluon vertices), the top-line spinor currents of every
 // suffix closed by the top propagator, and the final contraction with
 // ubar(top) (the same steps, in the same order of terms, as the per-ordering
-// amplitudes of the smaller processes).  Jp/kp: external current and
-// momentum at each position; g[r]: propagator factor of range r in
+// amplitudes of the smaller processes).  J[a][a], P[a][a]: external current
+// and momentum at position a; g[r]: propagator factor of range r in
 // AMP_M5_RANGE order; iq[j]: factor of the suffix starting at position j + 1.
-template <class R>
-__device__ __forceinline__ void ordering_amp(const V4<R> (&Jp)[5], const V4<R> (&kp)[5], const R (&g)[10],
-                                             const R (&iq)[4], const Sp<R>& V, const V4<R>& pb, R MT,
-                                             const Sp<R>* UB, C2<R>& A0, C2<R>& A1) {
-  V4<R> J[5][5], P[5][5];
-#pragma unroll
-  for (int a = 0; a < 5; ++a) {
-    J[a][a] = Jp[a];
-    P[a][a] = kp[a];
-  }
+// In two stages: SUFFIX = true computes what depends on positions 2..4 only
+// (the currents of the ranges inside them and the spinor currents S[2..4]),
+// which two orderings that differ by the swap of their first two gluons
+// share; SUFFIX = false completes the ordering from them.
+template <class R, bool SUFFIX>
+__device__ __forceinline__ void ordering_stage(V4<R> (&J)[5][5], V4<R> (&P)[5][5], Sp<R> (&S)[6], const R (&g)[10],
+                                               const R (&iq)[4], const V4<R>& pb, R MT, const Sp<R>* UB, C2<R>& A0,
+                                               C2<R>& A1) {
   int r = 0;  // range index in AMP_M5_RANGE order: by length, then start
 #pragma unroll
   for (int len = 2; len <= 5; ++len)
 #pragma unroll
   for (int a = 0; a + len <= 5; ++a, ++r) {
+    if (SUFFIX != (a >= 2)) continue;
     const int b = a + len - 1;
-    P[a][b] = P[a][b - 1] + kp[b];
+    P[a][b] = P[a][b - 1] + P[b][b];
     V4<R> t3 = v3(J[a][a], J[a + 1][b], P[a][a], P[a + 1][b]);
 #pragma unroll
     for (int j = a + 1; j < b; ++j) t3 = t3 + v3(J[a][j], J[j + 1][b], P[a][j], P[j + 1][b]);
@@ -151,20 +150,21 @@ __device__ __forceinline__ void ordering_amp(const V4<R> (&Jp)[5], const V4<R> (
       J[a][b] = g[r] * t3;
     }
   }
-  Sp<R> S[6];
-  S[5] = V;
 #pragma unroll
   for (int a = 4; a >= 1; --a) {
+    if (SUFFIX != (a >= 2)) continue;
     Sp<R> acc = slash(J[a][a], S[a + 1]);
 #pragma unroll
     for (int j = a + 1; j < 5; ++j) acc = acc + slash(J[a][j], S[j + 1]);
     S[a] = prop(R(-1.0) * (pb + P[a][4]), MT, iq[a - 1], acc);
   }
-  Sp<R> F = slash(J[0][0], S[1]);
+  if (!SUFFIX) {
+    Sp<R> F = slash(J[0][0], S[1]);
 #pragma unroll
-  for (int j = 1; j < 5; ++j) F = F + slash(J[0][j], S[j + 1]);
-  A0 = ubar_dot(UB[0], F);
-  A1 = ubar_dot(UB[1], F);
+    for (int j = 1; j < 5; ++j) F = F + slash(J[0][j], S[j + 1]);
+    A0 = ubar_dot(UB[0], F);
+    A1 = ubar_dot(UB[1], F);
+  }
 }
 
 // Partial amplitudes of states s0 .. s0 + ns - 1 for the passing events
@@ -256,26 +256,51 @@ __global__ void __launch_bounds__(AWAVE) k_g3_amp(DevCfg c, const double* __rest
     const Sp<R> V = vtab[ht][lane];
     R* o4 = out + (int64_t)((st - s0) * 4) * sstride;
 #pragma unroll 1
-    for (int k = 0; k < NF; ++k) {
-      V4<R> Jp[5], kp[5];
+    for (int pr = 0; pr < AMP_M5_NPAIR; ++pr) {
+      V4<R> J[5][5], P[5][5];
+      Sp<R> S[6];
       R gr[10], iq[4];
+      C2<R> a0, a1;
+      S[5] = V;
+      {
+        // positions 2..4 hold the same gluons in both orderings of the pair
+        const int k = AMP_M5_PAIR[pr][0];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) {
-        const int sg = AMP_M5_SIGMA[k][i];
-        Jp[i] = etab[2 * sg + ((hg >> (4 - sg)) & 1)][lane];
-        kp[i] = ktab[sg][lane];
+        for (int i = 2; i < 5; ++i) {
+          const int sg = AMP_M5_SIGMA[k][i];
+          J[i][i] = etab[2 * sg + ((hg >> (4 - sg)) & 1)][lane];
+          P[i][i] = ktab[sg][lane];
+        }
+        gr[2] = gtab[AMP_M5_GMASK[k][2]][lane];
+        gr[3] = gtab[AMP_M5_GMASK[k][3]][lane];
+        gr[6] = gtab[AMP_M5_GMASK[k][6]][lane];
+#pragma unroll
+        for (int j = 1; j < 4; ++j) iq[j] = qtab[AMP_M5_QMASK[k][j]][lane];
+        ordering_stage<R, true>(J, P, S, gr, iq, PB, MT, UB, a0, a1);
       }
 #pragma unroll
-      for (int r = 0; r < 10; ++r) gr[r] = gtab[AMP_M5_GMASK[k][r]][lane];
+      for (int h = 0; h < 2; ++h) {
+        const int k = AMP_M5_PAIR[pr][h];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) iq[r] = qtab[AMP_M5_QMASK[k][r]][lane];
-      C2<R> a0, a1;
-      ordering_amp<R>(Jp, kp, gr, iq, V, PB, MT, UB, a0, a1);
-      R* p = o4 + (int64_t)(k >> 2) * ld * 4 + (k & 3);
-      p[0] = a0.re;
-      p[sstride] = a0.im;
-      p[2 * sstride] = a1.re;
-      p[3 * sstride] = a1.im;
+        for (int i = 0; i < 2; ++i) {
+          const int sg = AMP_M5_SIGMA[k][i];
+          J[i][i] = etab[2 * sg + ((hg >> (4 - sg)) & 1)][lane];
+          P[i][i] = ktab[sg][lane];
+        }
+        gr[0] = gtab[AMP_M5_GMASK[k][0]][lane];
+        gr[1] = gtab[AMP_M5_GMASK[k][1]][lane];
+        gr[4] = gtab[AMP_M5_GMASK[k][4]][lane];
+        gr[5] = gtab[AMP_M5_GMASK[k][5]][lane];
+#pragma unroll
+        for (int r = 7; r < 10; ++r) gr[r] = gtab[AMP_M5_GMASK[k][r]][lane];
+        iq[0] = qtab[AMP_M5_QMASK[k][0]][lane];
+        ordering_stage<R, false>(J, P, S, gr, iq, PB, MT, UB, a0, a1);
+        R* p = o4 + (int64_t)(k >> 2) * ld * 4 + (k & 3);
+        p[0] = a0.re;
+        p[sstride] = a0.im;
+        p[2 * sstride] = a1.re;
+        p[3 * sstride] = a1.im;
+      }
     }
     // zero padding of the orderings NF .. 4 NQ - 1
 #pragma unroll 1

@@ -34,6 +34,16 @@ def _array(text, name):
     return [int(float(v)) for v in re.findall(r"-?\d+(?:\.\d+)?", body)]
 
 
+def test_ttggg_pairs_differ_by_the_first_two_gluons():
+    text = gen_me.emit_amp_tables(5)
+    perms = list(itertools.permutations(range(5)))
+    pairs = np.array(_array(text, "AMP_M5_PAIR")).reshape(-1, 2)
+    assert len(pairs) == 60 and sorted(pairs.ravel().tolist()) == list(range(120))
+    for a, b in pairs:
+        pa, pb = perms[a], perms[b]
+        assert pa[0] == pb[1] and pa[1] == pb[0] and pa[2:] == pb[2:]
+
+
 def test_ttggg_tables_follow_their_definition():
     text = gen_me.emit_amp_tables(5)
     perms = list(itertools.permutations(range(5)))
@@ -68,5 +78,10 @@ def test_flop_counts_are_consistent():
                     + (4 * c["v3"] + 6 * c["w4"] + 9 * c["vadd"] + c["vscale"])
                     + sum(L * c["slash"] + (L - 1) * c["sadd"] + c["prop"] for L in range(1, 5))
                     + 5 * c["slash"] + 4 * c["sadd"] + 2 * c["ubar"])
-    assert fc["amplitudes_per_state"] == 120 * per_ordering
+    # a pair of orderings (first two gluons swapped) shares the currents of
+    # positions 2..4: J(2,3), J(3,4), J(2,4) and the spinor currents from 4, 3, 2
+    shared = (2 * (c["v3"] + c["vscale"]) + (2 * c["v3"] + c["w4"] + 2 * c["vadd"] + c["vscale"])
+              + sum(L * c["slash"] + (L - 1) * c["sadd"] + c["prop"] for L in range(1, 4)))
+    assert shared == 788
+    assert fc["amplitudes_per_state"] == 120 * per_ordering - 60 * shared
     assert fc["total"] == 64 * (fc["amplitudes_per_state"] + fc["colour_per_state"])
