@@ -35,7 +35,7 @@ EVENTS = 10_000_000
 # runs scaled by a 1 GiB copy calibration
 # (profiles/traffic_k_vegas_gg_ttg_fp64_1e7.md).  Set to None when those
 # kernels change until the counters are taken again.
-MEASURED_TRAFFIC_BYTES = 79.9e6
+MEASURED_TRAFFIC_BYTES = None
 
 
 def flops_per_event(m: int) -> int:

@@ -113,14 +113,17 @@ COST = {"v3": 63, "w4": 42, "vscale": 4, "vadd": 4, "slash": 42, "prop": 66, "sa
 
 
 def flop_count(m: int) -> dict:
-    """Static flop count per event of the generated |M|^2 (the algorithm as
-    emitted: per-event constants, then for every antitop helicity and gluon
-    polarisation state the currents, partial amplitudes and colour form)."""
+    """Static flop count per event of the generated |M|^2 with the currents
+    shared across colour orderings (per-event constants, then for every
+    antitop helicity and gluon polarisation state the currents, partial
+    amplitudes and colour form; where the schedule shares the gluon currents
+    between the two antitop helicities they are counted once per gluon
+    polarisation state)."""
     return emit_me(m, with_cost=True)[1]
 
 
 def emit_me(m: int, with_cost: bool = False):
-    cost = {"const": 0, "body": 0}
+    cost = {"const": 0, "body": 0, "gluon": 0}
     perms, Z, den = colour_matrix(m)
     nf = len(perms)
     L = []
@@ -192,8 +195,10 @@ def emit_me(m: int, with_cost: bool = False):
         if terms4:
             expr = f"({expr}) - (" + " + ".join(terms4) + ")"
         w(f"{ind}const V4<R> {nm} = G{_mask(seq)} * ({expr});")
-        cost["body"] += (len(terms3) * COST["v3"] + len(terms4) * COST["w4"]
-                         + (len(terms3) + len(terms4) - 1) * COST["vadd"] + COST["vscale"])
+        c_ = (len(terms3) * COST["v3"] + len(terms4) * COST["w4"]
+              + (len(terms3) + len(terms4) - 1) * COST["vadd"] + COST["vscale"])
+        cost["body"] += c_
+        cost["gluon"] += c_
         emitted.add(nm)
         return nm
 
@@ -246,12 +251,18 @@ def emit_me(m: int, with_cost: bool = False):
     text = "\n".join(L) + "\n"
     if with_cost:
         n_states = 2 * (1 << m)
-        return text, {"per_event_constants": cost["const"], "per_state": cost["body"], "states": n_states,
-                      "total": cost["const"] + n_states * cost["body"]}
+        out = {"per_event_constants": cost["const"], "per_state": cost["body"], "states": n_states,
+               "total": cost["const"] + n_states * cost["body"]}
+        if SCHEDULE.get(m) == "per_ordering_shared_antitop":
+            # the gluon currents do not depend on the antitop helicity and are
+            # built once per gluon polarisation state
+            out["gluon_currents_per_polarisation"] = cost["gluon"]
+            out["total"] -= (n_states // 2) * cost["gluon"]
+        return text, out
     return text
 
 
-def emit_me_per_ordering(m: int) -> str:
+def emit_me_per_ordering(m: int, share_antitop: bool = False) -> str:
     """Lower-register schedule: each colour ordering builds its own currents.
 
     Only per-event scalars (propagator factors, formed in the kinematic type),
@@ -262,6 +273,10 @@ def emit_me_per_ordering(m: int) -> str:
     The amplitudes A[ordering][top helicity] stay in registers for the colour
     form.  Extra work versus sharing currents across orderings: the
     sub-sequence currents and antitop currents are rebuilt per ordering.
+    share_antitop: the gluon currents of an ordering are built once per gluon
+    polarisation state and used for both antitop helicities (the antitop
+    spinor enters only the top-line currents), at the cost of holding the
+    amplitudes of both antitop helicities until the colour form.
     """
     perms, Z, den = colour_matrix(m)
     nf = len(perms)
@@ -300,24 +315,31 @@ def emit_me_per_ordering(m: int) -> str:
         w(f"  const V4<R> K{i} = cvt4<R>(K[{i}]);")
     w("  const V4<R> PB = cvt4<R>(PTB);")
     w("  R total = R(0.0);")
-    w("#pragma unroll 1")
-    w("  for (int ht = 0; ht < 2; ++ht) {")
-    w("    const Sp<R> V = VS[ht];")
+    hts = (0, 1) if share_antitop else (None,)
+    if not share_antitop:
+        w("#pragma unroll 1")
+        w("  for (int ht = 0; ht < 2; ++ht) {")
+        w("    const Sp<R> V = VS[ht];")
+    else:
+        w("  {")
     w("#pragma unroll 1")
     w(f"    for (int hg = 0; hg < {1 << m}; ++hg) {{")
     ind = "      "
     for i in range(m):
         w(f"{ind}const V4<R> E{i} = ((hg >> {m - 1 - i}) & 1) ? E[{i}][1] : E[{i}][0];")
     for k, seq in enumerate(perms):
-        w(f"{ind}C2<R> A0_{k}, A1_{k};")
+        for h in hts:
+            hs = "" if h is None else f"h{h}"
+            w(f"{ind}C2<R> A0{hs}_{k}, A1{hs}_{k};")
         w(f"{ind}{{  // ordering {seq}")
         ii = ind + "  "
         for i in range(m):
             w(f"{ii}V4<R> J{i} = E{i}; opaque4(J{i});")
             w(f"{ii}V4<R> k{i} = K{i}; opaque4(k{i});")
-        w(f"{ii}Sp<R> S_ = V; opaque_sp(S_);")
+        if not share_antitop:
+            w(f"{ii}Sp<R> S_ = V; opaque_sp(S_);")
         w(f"{ii}V4<R> pb = PB; opaque4(pb);")
-        done = set(f"J{i}" for i in range(m)) | {"S_"}
+        done = set(f"J{i}" for i in range(m)) | ({"S_"} if not share_antitop else set())
         psum = set()
 
         def P(sq):
@@ -344,32 +366,44 @@ def emit_me_per_ordering(m: int) -> str:
             done.add(nm)
             return nm
 
-        def S(sq):
-            nm = f"S_{_name(sq)}"
+        def S(sq, hs):
+            nm = f"S{hs}_{_name(sq)}"
             if nm in done:
                 return nm
-            terms = [f"slash({J(sq[:j])}, {S(sq[j:])})" for j in range(1, len(sq) + 1)]
+            terms = [f"slash({J(sq[:j])}, {S(sq[j:], hs)})" for j in range(1, len(sq) + 1)]
             s_ = _mask(sq)
             w(f"{ii}const Sp<R> {nm} = prop(R(-1.0) * (pb + {P(sq)}), MT, IQ{s_}, " + " + ".join(terms) + ");")
             done.add(nm)
             return nm
 
-        terms = [f"slash({J(seq[:j])}, {S(seq[j:])})" for j in range(1, m + 1)]
-        w(f"{ii}const Sp<R> F = " + " + ".join(terms) + ";")
-        w(f"{ii}A0_{k} = ubar_dot(UB[0], F);")
-        w(f"{ii}A1_{k} = ubar_dot(UB[1], F);")
+        # with share_antitop: the gluon currents first (shared by both antitop
+        # helicities), then the top line for each antitop helicity
+        if share_antitop:
+            for j in range(1, m + 1):
+                J(seq[:j])
+        for h in hts:
+            hs = "" if h is None else f"h{h}"
+            if share_antitop:
+                w(f"{ii}Sp<R> S{hs}_ = VS[{h}]; opaque_sp(S{hs}_);")
+                done.add(f"S{hs}_")
+            terms = [f"slash({J(seq[:j])}, {S(seq[j:], hs)})" for j in range(1, m + 1)]
+            w(f"{ii}const Sp<R> F{hs} = " + " + ".join(terms) + ";")
+            w(f"{ii}A0{hs}_{k} = ubar_dot(UB[0], F{hs});")
+            w(f"{ii}A1{hs}_{k} = ubar_dot(UB[1], F{hs});")
         w(f"{ind}}}")
     groups = {}
     for i in range(nf):
         for j in range(i, nf):
             c = Z[i][j] * (1 if i == j else 2)
             groups.setdefault(c, []).append((i, j))
-    for t in range(2):
-        parts = []
-        for c, lst in sorted(groups.items()):
-            terms = [f"cabs2(A{t}_{i})" if i == j else f"cre_dot(A{t}_{i}, A{t}_{j})" for (i, j) in lst]
-            parts.append(f"R({c}.0) * (" + " + ".join(terms) + ")")
-        w(f"{ind}total = total + (" + f"\n{ind}    + ".join(parts) + ");")
+    for h in hts:
+        hs = "" if h is None else f"h{h}"
+        for t in range(2):
+            parts = []
+            for c, lst in sorted(groups.items()):
+                terms = [f"cabs2(A{t}{hs}_{i})" if i == j else f"cre_dot(A{t}{hs}_{i}, A{t}{hs}_{j})" for (i, j) in lst]
+                parts.append(f"R({c}.0) * (" + " + ".join(terms) + ")")
+            w(f"{ind}total = total + (" + f"\n{ind}    + ".join(parts) + ");")
     w("    }")
     w("  }")
     w(f"  return total * R(1.0 / {den}.0);")
@@ -488,7 +522,7 @@ def amp_flop_count(m: int) -> dict:
             "total": states * (body + colour)}
 
 
-SCHEDULE = {2: "memo", 3: "per_ordering", 4: "per_ordering", 5: "amplitudes"}
+SCHEDULE = {2: "memo", 3: "per_ordering_shared_antitop", 4: "per_ordering", 5: "amplitudes"}
 
 
 def main(outdir: str, ms=(2, 3, 4, 5)) -> None:
@@ -499,7 +533,8 @@ def main(outdir: str, ms=(2, 3, 4, 5)) -> None:
             text = emit_amp_tables(m)
         else:
             path = os.path.join(outdir, f"me_gg_m{m}.h")
-            text = emit_me(m) if SCHEDULE[m] == "memo" else emit_me_per_ordering(m)
+            text = emit_me(m) if SCHEDULE[m] == "memo" else emit_me_per_ordering(
+                m, share_antitop=SCHEDULE[m] == "per_ordering_shared_antitop")
         old = open(path).read() if os.path.exists(path) else None
         if old != text:
             with open(path, "w") as f:
