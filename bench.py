@@ -31,11 +31,11 @@ METRIC = "events/s per MI355X and time to 1e-3 rel. error: FP32+flow vs FP64 VEG
 FP64_VECTOR_PEAK = 78.6e12  # MI355X FP64 vector FLOP/s (256 CUs x 128 FLOP/clk x 2.4 GHz)
 EVENTS = 10_000_000
 # HBM bytes per iteration of the kernel pair k_select<1> + k_vegas<1,0,double>
-# at 1e7 events (29.9 + 50.0 MB), from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# at 1e7 events (29.9 + 37.0 MB), from rocprofv3 FETCH_SIZE and WRITE_SIZE
 # runs scaled by a 1 GiB copy calibration
 # (profiles/traffic_k_vegas_gg_ttg_fp64_1e7.md).  Set to None when those
 # kernels change until the counters are taken again.
-MEASURED_TRAFFIC_BYTES = None
+MEASURED_TRAFFIC_BYTES = 66.9e6
 
 
 def flops_per_event(m: int) -> int:
