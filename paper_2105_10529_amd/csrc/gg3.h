@@ -26,6 +26,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "amp.h"
 #include "gen/amp_gg_m5.h"
 #include "launch.h"
@@ -107,20 +109,20 @@ __global__ void __launch_bounds__(BLOCK) k_g3_select(DevCfg c, const double* __r
 
 // One colour-ordered partial amplitude for both top helicities: the gluon
 // currents J(a..b) of every contiguous range of positions (Berends-Giele,
-// three- and four-gluon vertices), the top-line spinor currents of every
-// suffix closed by the top propagator, and the final contraction with
-// ubar(top) (the same steps, in the same order of terms, as the per-ordering
-// amplitudes of the smaller processes).  J[a][a], P[a][a]: external current
-// and momentum at position a; g[r]: propagator factor of range r in
-// AMP_M5_RANGE order; iq[j]: factor of the suffix starting at position j + 1.
-// In two stages: SUFFIX = true computes what depends on positions 2..4 only
-// (the currents of the ranges inside them and the spinor currents S[2..4]),
-// which two orderings that differ by the swap of their first two gluons
-// share; SUFFIX = false completes the ordering from them.
+// three- and four-gluon vertices; gluon_stage), then the top-line spinor
+// currents of every suffix closed by the top propagator and the final
+// contraction with ubar(top) (spinor_stage; the same steps, in the same order
+// of terms, as the per-ordering amplitudes of the smaller processes).  The
+// gluon currents do not depend on the antitop helicity, so one gluon stage
+// serves the spinor stages of both.  J[a][a], P[a][a]: external current and
+// momentum at position a; g[r]: propagator factor of range r in AMP_M5_RANGE
+// order; iq[j]: factor of the suffix starting at position j + 1; S[5]: the
+// antitop spinor.  In two stages each: SUFFIX = true computes what depends on
+// positions 2..4 only (the currents of the ranges inside them and the spinor
+// currents S[2..4]), which two orderings that differ by the swap of their
+// first two gluons share; SUFFIX = false completes the ordering from them.
 template <class R, bool SUFFIX>
-__device__ __forceinline__ void ordering_stage(V4<R> (&J)[5][5], V4<R> (&P)[5][5], Sp<R> (&S)[6], const R (&g)[10],
-                                               const R (&iq)[4], const V4<R>& pb, R MT, const Sp<R>* UB, C2<R>& A0,
-                                               C2<R>& A1) {
+__device__ __forceinline__ void gluon_stage(V4<R> (&J)[5][5], V4<R> (&P)[5][5], const R (&g)[10]) {
   int r = 0;  // range index in AMP_M5_RANGE order: by length, then start
 #pragma unroll
   for (int len = 2; len <= 5; ++len)
@@ -150,6 +152,12 @@ __device__ __forceinline__ void ordering_stage(V4<R> (&J)[5][5], V4<R> (&P)[5][5
       J[a][b] = g[r] * t3;
     }
   }
+}
+
+template <class R, bool SUFFIX>
+__device__ __forceinline__ void spinor_stage(const V4<R> (&J)[5][5], const V4<R> (&P)[5][5], Sp<R> (&S)[6],
+                                             const R (&iq)[4], const V4<R>& pb, R MT, const Sp<R>* UB, C2<R>& A0,
+                                             C2<R>& A1) {
 #pragma unroll
   for (int a = 4; a >= 1; --a) {
     if (SUFFIX != (a >= 2)) continue;
@@ -175,9 +183,14 @@ __device__ __forceinline__ void ordering_stage(V4<R> (&J)[5][5], V4<R> (&P)[5][5
 // past nc recompute the last event into columns below ld, never read as
 // results.  The propagator factors of every gluon subset are formed in FP64
 // from the FP64 momenta and kept per lane in LDS, indexed by subset.
-// With c.helicity != 0 each lane evaluates one state of its own (ns = 1):
-// drawn by Philox from the point's first two coordinates (mode 1) or the
-// fixed state helicity - 2; the ordering loop stays wave-uniform.
+// With c.helicity != 0 each lane evaluates one state k of its own (ns = 1;
+// antitop helicity k / 32, gluon polarisation state k % 32): drawn by Philox
+// from the point's first two coordinates (mode 1) or the fixed state
+// helicity - 2; the ordering loop stays wave-uniform.  In the summed mode
+// (ns even) pass state s stands for gluon polarisation state s / 2 and
+// antitop helicity s % 2, so that both antitop helicities of a gluon state
+// are evaluated together from one set of gluon currents.
+static_assert(SP % 2 == 0, "summed passes hold both antitop helicities of each gluon state");
 template <class R>
 __global__ void __launch_bounds__(AWAVE) k_g3_amp(DevCfg c, const double* __restrict__ u, int64_t n,
                                                   const int* __restrict__ idx, int64_t nc, int s0, int ns,
@@ -249,19 +262,16 @@ __global__ void __launch_bounds__(AWAVE) k_g3_amp(DevCfg c, const double* __rest
   } else if (c.helicity >= 2) {
     own = c.helicity - 2;
   }
-#pragma unroll 1
-  for (int st = s0; st < s0 + ns; ++st) {
-    const int sx = own >= 0 ? own : st;
-    const int ht = sx >> 5, hg = sx & 31;
-    const Sp<R> V = vtab[ht][lane];
-    R* o4 = out + (int64_t)((st - s0) * 4) * sstride;
+  // The 120 orderings of gluon polarisation state hg for NH antitop
+  // helicities (ht0 .. ht0 + NH - 1), written at slots 0 .. NH - 1 of o4.
+  auto orderings = [&](auto nh, int hg, int ht0, R* o4) {
+    constexpr int NH = decltype(nh)::value;
 #pragma unroll 1
     for (int pr = 0; pr < AMP_M5_NPAIR; ++pr) {
       V4<R> J[5][5], P[5][5];
-      Sp<R> S[6];
+      Sp<R> S[NH][6];
       R gr[10], iq[4];
       C2<R> a0, a1;
-      S[5] = V;
       {
         // positions 2..4 hold the same gluons in both orderings of the pair
         const int k = AMP_M5_PAIR[pr][0];
@@ -276,11 +286,16 @@ __global__ void __launch_bounds__(AWAVE) k_g3_amp(DevCfg c, const double* __rest
         gr[6] = gtab[AMP_M5_GMASK[k][6]][lane];
 #pragma unroll
         for (int j = 1; j < 4; ++j) iq[j] = qtab[AMP_M5_QMASK[k][j]][lane];
-        ordering_stage<R, true>(J, P, S, gr, iq, PB, MT, UB, a0, a1);
+        gluon_stage<R, true>(J, P, gr);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          S[h][5] = vtab[ht0 + h][lane];
+          spinor_stage<R, true>(J, P, S[h], iq, PB, MT, UB, a0, a1);
+        }
       }
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int k = AMP_M5_PAIR[pr][h];
+      for (int o = 0; o < 2; ++o) {
+        const int k = AMP_M5_PAIR[pr][o];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           const int sg = AMP_M5_SIGMA[k][i];
@@ -294,23 +309,37 @@ __global__ void __launch_bounds__(AWAVE) k_g3_amp(DevCfg c, const double* __rest
 #pragma unroll
         for (int r = 7; r < 10; ++r) gr[r] = gtab[AMP_M5_GMASK[k][r]][lane];
         iq[0] = qtab[AMP_M5_QMASK[k][0]][lane];
-        ordering_stage<R, false>(J, P, S, gr, iq, PB, MT, UB, a0, a1);
-        R* p = o4 + (int64_t)(k >> 2) * ld * 4 + (k & 3);
-        p[0] = a0.re;
-        p[sstride] = a0.im;
-        p[2 * sstride] = a1.re;
-        p[3 * sstride] = a1.im;
+        gluon_stage<R, false>(J, P, gr);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          spinor_stage<R, false>(J, P, S[h], iq, PB, MT, UB, a0, a1);
+          R* p = o4 + (int64_t)(h * 4) * sstride + (int64_t)(k >> 2) * ld * 4 + (k & 3);
+          p[0] = a0.re;
+          p[sstride] = a0.im;
+          p[2 * sstride] = a1.re;
+          p[3 * sstride] = a1.im;
+        }
       }
     }
     // zero padding of the orderings NF .. 4 NQ - 1
 #pragma unroll 1
     for (int k = NF; k < 4 * NQ; ++k) {
-      R* p = o4 + (int64_t)(k >> 2) * ld * 4 + (k & 3);
-      p[0] = R(0.0);
-      p[sstride] = R(0.0);
-      p[2 * sstride] = R(0.0);
-      p[3 * sstride] = R(0.0);
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        R* p = o4 + (int64_t)(h * 4) * sstride + (int64_t)(k >> 2) * ld * 4 + (k & 3);
+        p[0] = R(0.0);
+        p[sstride] = R(0.0);
+        p[2 * sstride] = R(0.0);
+        p[3 * sstride] = R(0.0);
+      }
     }
+  };
+  if (own >= 0) {
+    orderings(std::integral_constant<int, 1>{}, own & 31, own >> 5, out);
+  } else {
+    // pass states s0 .. s0 + ns - 1: gluon state (s0 + q) / 2, antitop helicity q % 2
+#pragma unroll 1
+    for (int q = 0; q < ns; q += 2) orderings(std::integral_constant<int, 2>{}, (s0 + q) >> 1, 0, out + (int64_t)(q * 4) * sstride);
   }
 }
 

@@ -476,14 +476,18 @@ def emit_amp_tables(m: int) -> str:
 def amp_flop_count(m: int) -> dict:
     """Static flop count per event of the streamed partial amplitudes plus the
     colour sum over the unpadded orderings (the algorithm as emitted: per
-    ordering, less what each pair of orderings shares)."""
+    ordering, less what each pair of orderings shares).  A single state
+    costs amplitudes_single_state; the sum over all states builds the gluon
+    currents of each gluon polarisation state once for both antitop
+    helicities, so its average per state is amplitudes_per_state."""
     perms, _, _ = colour_matrix(m)
     body = 0
+    gluon = 0
     for seq in perms:
         done = set()
 
         def J(sq):
-            nonlocal body
+            nonlocal body, gluon
             if len(sq) == 1 or sq in done:
                 return
             n3 = len(sq) - 1
@@ -491,7 +495,9 @@ def amp_flop_count(m: int) -> dict:
             for j in range(1, len(sq)):
                 J(sq[:j])
                 J(sq[j:])
-            body += n3 * COST["v3"] + n4 * COST["w4"] + (n3 + n4 - 1) * COST["vadd"] + COST["vscale"]
+            c_ = n3 * COST["v3"] + n4 * COST["w4"] + (n3 + n4 - 1) * COST["vadd"] + COST["vscale"]
+            body += c_
+            gluon += c_
             done.add(sq)
 
         def S(sq):
@@ -516,14 +522,18 @@ def amp_flop_count(m: int) -> dict:
         n3, n4 = ln - 1, (ln - 1) * (ln - 2) // 2
         shared += (m - 2 - ln + 1) * (n3 * COST["v3"] + n4 * COST["w4"] + (n3 + n4 - 1) * COST["vadd"]
                                       + COST["vscale"])
+    gluon_shared = shared
     for ln in range(1, m - 1):
         shared += ln * COST["slash"] + (ln - 1) * COST["sadd"] + COST["prop"]
     body -= (len(perms) // 2) * shared
+    gluon -= (len(perms) // 2) * gluon_shared
     nf = len(perms)
     colour = 2 * 2 * (2 * nf * nf)  # two top helicities, real and imaginary parts, C times A and the dot
     states = 2 << m
-    return {"amplitudes_per_state": body, "colour_per_state": colour, "states": states,
-            "total": states * (body + colour)}
+    per_state = body - gluon // 2
+    return {"amplitudes_per_state": per_state, "amplitudes_single_state": body,
+            "gluon_currents_per_state": gluon, "colour_per_state": colour, "states": states,
+            "total": states * (per_state + colour)}
 
 
 SCHEDULE = {2: "memo", 3: "per_ordering_shared_antitop", 4: "per_ordering_shared_antitop_fp32", 5: "amplitudes"}

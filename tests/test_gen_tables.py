@@ -83,7 +83,14 @@ def test_flop_counts_are_consistent():
     shared = (2 * (c["v3"] + c["vscale"]) + (2 * c["v3"] + c["w4"] + 2 * c["vadd"] + c["vscale"])
               + sum(L * c["slash"] + (L - 1) * c["sadd"] + c["prop"] for L in range(1, 4)))
     assert shared == 788
-    assert fc["amplitudes_per_state"] == 120 * per_ordering - 60 * shared
+    assert fc["amplitudes_single_state"] == 120 * per_ordering - 60 * shared
+    # the summed mode builds the gluon currents once for both antitop helicities
+    gluon = (4 * (c["v3"] + c["vscale"]) + 3 * (2 * c["v3"] + c["w4"] + 2 * c["vadd"] + c["vscale"])
+             + 2 * (3 * c["v3"] + 3 * c["w4"] + 5 * c["vadd"] + c["vscale"])
+             + (4 * c["v3"] + 6 * c["w4"] + 9 * c["vadd"] + c["vscale"]))
+    gluon_shared = 2 * (c["v3"] + c["vscale"]) + (2 * c["v3"] + c["w4"] + 2 * c["vadd"] + c["vscale"])
+    assert fc["gluon_currents_per_state"] == 120 * gluon - 60 * gluon_shared
+    assert fc["amplitudes_per_state"] == fc["amplitudes_single_state"] - fc["gluon_currents_per_state"] // 2
     assert fc["total"] == 64 * (fc["amplitudes_per_state"] + fc["colour_per_state"])
 
 
