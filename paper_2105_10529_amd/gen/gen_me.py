@@ -258,10 +258,6 @@ def emit_me(m: int, with_cost: bool = False):
             # built once per gluon polarisation state
             out["gluon_currents_per_polarisation"] = cost["gluon"]
             out["total"] -= (n_states // 2) * cost["gluon"]
-        elif SCHEDULE.get(m) == "per_ordering_shared_antitop_fp32":
-            # only the FP32 instantiation shares them
-            out["gluon_currents_per_polarisation"] = cost["gluon"]
-            out["total_fp32"] = out["total"] - (n_states // 2) * cost["gluon"]
         return text, out
     return text
 
@@ -536,29 +532,7 @@ def amp_flop_count(m: int) -> dict:
             "total": states * (per_state + colour)}
 
 
-SCHEDULE = {2: "memo", 3: "per_ordering_shared_antitop", 4: "per_ordering_shared_antitop_fp32", 5: "amplitudes"}
-
-
-def emit_me_per_precision(m: int) -> str:
-    """FP32 amplitudes with the shared-antitop schedule, FP64 amplitudes with
-    one pass per antitop helicity: an FP64 value takes two registers, and
-    holding both helicities' amplitudes would double the FP64 kernel's spill,
-    while in FP32 the shared schedule stays spill-free."""
-    po = emit_me_per_ordering(m, share_antitop=False)
-    sa = emit_me_per_ordering(m, share_antitop=True)
-    tmpl = "template <class R, class RK>\n"
-    end = "}  // namespace mf\n"
-    head, body_po = po.split(tmpl, 1)
-    body_sa = sa.split(tmpl, 1)[1]
-    name = f"me_gg_m{m}("
-    fn_po = tmpl + body_po[: body_po.rindex(end)].replace(name, f"me_gg_m{m}_po(", 1)
-    fn_sa = tmpl + body_sa[: body_sa.rindex(end)].replace(name, f"me_gg_m{m}_sa(", 1)
-    disp = (tmpl + f"__device__ __forceinline__ R me_gg_m{m}(const V4<RK>* K, const V4<R> (*E)[2], const Sp<R>* UB,\n"
-            "                                         const Sp<R>* VS, const V4<RK>& PTB, RK MTK) {\n"
-            f"  if constexpr (sizeof(R) == 4) return me_gg_m{m}_sa<R, RK>(K, E, UB, VS, PTB, MTK);\n"
-            f"  else return me_gg_m{m}_po<R, RK>(K, E, UB, VS, PTB, MTK);\n"
-            "}\n")
-    return head + fn_po + fn_sa + disp + end
+SCHEDULE = {2: "memo", 3: "per_ordering_shared_antitop", 4: "per_ordering_shared_antitop", 5: "amplitudes"}
 
 
 def main(outdir: str, ms=(2, 3, 4, 5)) -> None:
@@ -569,12 +543,8 @@ def main(outdir: str, ms=(2, 3, 4, 5)) -> None:
             text = emit_amp_tables(m)
         else:
             path = os.path.join(outdir, f"me_gg_m{m}.h")
-            if SCHEDULE[m] == "memo":
-                text = emit_me(m)
-            elif SCHEDULE[m] == "per_ordering_shared_antitop_fp32":
-                text = emit_me_per_precision(m)
-            else:
-                text = emit_me_per_ordering(m, share_antitop=SCHEDULE[m] == "per_ordering_shared_antitop")
+            text = emit_me(m) if SCHEDULE[m] == "memo" else emit_me_per_ordering(
+                m, share_antitop=SCHEDULE[m] == "per_ordering_shared_antitop")
         old = open(path).read() if os.path.exists(path) else None
         if old != text:
             with open(path, "w") as f:

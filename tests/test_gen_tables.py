@@ -94,19 +94,11 @@ def test_flop_counts_are_consistent():
     assert fc["total"] == 64 * (fc["amplitudes_per_state"] + fc["colour_per_state"])
 
 
-def test_four_gluon_header_shares_antitop_currents_in_fp32_only():
-    """The 4-gluon header holds both schedules: FP32 amplitudes build each
-    ordering's gluon currents once for both antitop helicities, FP64 ones
-    once per antitop helicity; the FP32 count drops by one set of gluon
-    currents per gluon polarisation state."""
-    text = gen_me.emit_me_per_precision(4)
-    assert text.count("__device__ __forceinline__ R me_gg_m4_po(") == 1
-    assert text.count("__device__ __forceinline__ R me_gg_m4_sa(") == 1
-    assert "if constexpr (sizeof(R) == 4) return me_gg_m4_sa<R, RK>" in text
-    assert text.count("#pragma once") == 1 and text.count("ME_M4_NF =") == 1
-    # the per-ordering body is the stand-alone per-ordering function, renamed
-    po = gen_me.emit_me_per_ordering(4)
-    body = po.split("template <class R, class RK>\n", 1)[1].rsplit("}  // namespace mf\n", 1)[0]
-    assert body.replace("me_gg_m4(", "me_gg_m4_po(", 1) in text
-    fc = gen_me.flop_count(4)
-    assert fc["total_fp32"] == fc["total"] - (fc["states"] // 2) * fc["gluon_currents_per_polarisation"]
+
+def test_shared_antitop_counts():
+    """g g -> t t~ g and g g -> t t~ g g build each ordering's gluon currents
+    once per gluon polarisation state for both antitop helicities: the count
+    drops by one set of gluon currents per gluon polarisation state."""
+    for m, before in ((3, 66474), (4, 929978)):
+        fc = gen_me.flop_count(m)
+        assert fc["total"] == before - (fc["states"] // 2) * fc["gluon_currents_per_polarisation"]
