@@ -55,6 +55,8 @@ def lib():
         L.or_state_create.argtypes = [P]
         L.or_state_create.restype = i
         L.or_state_destroy.argtypes = [i]
+        L.or_pass_cuts.argtypes = [i, i, P, d, d]
+        L.or_pass_cuts.restype = i
         L.or_pdf_table.argtypes = [i, i, P]
         L.or_pdf.argtypes = [i, i, i, P, P, i, P]
         L.or_hermite2d.argtypes = [P, i, P, P, P]
@@ -207,6 +209,11 @@ class Oracle:
         mom = np.zeros((n, ng + 4, 4))
         lib().or_integrand_mom(self._h, n, _ptr(x), _ptr(w), _ptr(mom))
         return w, mom
+
+    def pass_cuts(self, gluons: np.ndarray, x1: float, x2: float) -> bool:
+        """The cut decision for partonic-frame gluon momenta gluons[ng][4] at momentum fractions x1, x2."""
+        g = _c(np.atleast_2d(gluons))
+        return bool(lib().or_pass_cuts(self._h, g.shape[0], _ptr(g), float(x1), float(x2)))
 
     def pdf(self, flavour: str, x, Q, analytic: bool = False):
         x = _c(np.atleast_1d(x))

@@ -915,6 +915,14 @@ void or_state_destroy(int h) {
   if (h >= 0 && h < (int)g_states.size()) { delete g_states[h]; g_states[h] = nullptr; }
 }
 
+// The fiducial cut decision of a configured state for explicit partonic-frame
+// gluon momenta g[ng][4] and momentum fractions x1, x2 (1 = every cut passed).
+int or_pass_cuts(int h, int ng, const double* g, double x1, double x2) {
+  std::vector<P4<double>> gl(ng);
+  for (int i = 0; i < ng; ++i) gl[i] = P4<double>{g[4 * i], g[4 * i + 1], g[4 * i + 2], g[4 * i + 3]};
+  return pass_cuts(g_states[h]->cfg, ng, gl.data(), x1, x2) ? 1 : 0;
+}
+
 void or_pdf_table(int h, int f, double* out) {
   const State& S = *g_states[h];
   std::copy(S.tab[f].begin(), S.tab[f].end(), out);

@@ -1,6 +1,7 @@
 """Pins of the oracle's coupling flow (CPU only): bijectivity, normalisation,
-identity at zero output layer, mask coverage, and the analytic gradient
-against central differences."""
+identity at zero output layer, mask coverage, the analytic gradient
+against central differences, and the Adam update against properties of
+Kingma & Ba's Algorithm 1 (first step, constant gradient, sign flip)."""
 import itertools
 
 import numpy as np
@@ -133,3 +134,67 @@ def test_relative_variance_and_mixture_special_cases():
     lq = np.log(w / w.mean())
     assert abs(flow.relative_variance(lq, w)) < 1e-12
     assert np.allclose(flow.mixture_density(np.log(np.full(3, 4.0)), 0.25), 0.25 + 0.75 * 4.0)
+
+
+def _adam_setup(g_list):
+    params = [{"W": np.zeros_like(g_list[0])}]
+    state = [{"mW": np.zeros_like(g_list[0]), "vW": np.zeros_like(g_list[0])}]
+    return params, state
+
+
+def test_adam_first_step_is_sign_step():
+    # Kingma & Ba, Algorithm 1: with zero initial moments the bias-corrected
+    # moments of step 1 are g and g^2, so each parameter moves by -lr g/(|g| + eps)
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=(7, 5)) * np.logspace(-3, 3, 5)
+    g[0, 0] = 0.0  # a zero gradient leaves its parameter where it is
+    params, state = _adam_setup([g])
+    lr = 1e-3
+    flow.adam_step(params, [{"W": g}], state, lr, 1)
+    expect = -lr * g / (np.abs(g) + 1e-8)
+    assert np.allclose(params[0]["W"], expect, rtol=1e-12, atol=0)
+    nz = g != 0
+    # |step| = lr |g|/(|g| + eps): lr to within lr eps/|g|
+    assert np.all(np.abs(np.abs(params[0]["W"][nz]) - lr) <= 1.001 * lr * 1e-8 / np.abs(g[nz]))
+    assert params[0]["W"][0, 0] == 0.0
+
+
+def test_adam_constant_gradient_keeps_its_step():
+    # a constant gradient keeps both bias-corrected moments at g and g^2 at
+    # every step t, so every step has the size of the first one
+    g = np.array([[0.3, -2.0, 1e-2, 40.0]])
+    params, state = _adam_setup([g])
+    lr = 2e-3
+    prev = params[0]["W"].copy()
+    for t in range(1, 26):
+        flow.adam_step(params, [{"W": g}], state, lr, t)
+        step = params[0]["W"] - prev
+        prev = params[0]["W"].copy()
+        assert np.allclose(step, -lr * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=0), t
+
+
+def test_adam_gradient_sign_flip_closed_form():
+    # g at step 1, -g at step 2: m_2 = -(1 - b1)^2 g, v_2 = (1 - b2^2) g^2, so the
+    # bias-corrected moments are -g (1 - b1)/(1 + b1) and g^2, and step 2 moves
+    # by +lr (1 - b1)/(1 + b1) sign(g) (to eps); swapped b1 and b2 would move by
+    # lr (1 - b2)/(1 + b2)
+    g = np.array([[1.5, -0.25, 7.0]])
+    params, state = _adam_setup([g])
+    lr, b1 = 1e-2, 0.9
+    flow.adam_step(params, [{"W": g}], state, lr, 1)
+    p1 = params[0]["W"].copy()
+    flow.adam_step(params, [{"W": -g}], state, lr, 2)
+    step2 = params[0]["W"] - p1
+    assert np.allclose(step2, lr * (1 - b1) / (1 + b1) * np.sign(g), rtol=1e-6, atol=0)
+
+
+def test_adam_is_invariant_to_gradient_scale():
+    rng = np.random.default_rng(4)
+    gs = [rng.normal(size=(3, 4)) for _ in range(6)]
+    out = []
+    for scale in (1e3, 1e6):  # eps / sqrt(v) below ~1e-8: the update depends on the gradient's direction only
+        params, state = _adam_setup(gs)
+        for t, g in enumerate(gs, 1):
+            flow.adam_step(params, [{"W": scale * g}], state, 1e-3, t)
+        out.append(params[0]["W"])
+    assert np.allclose(out[0], out[1], rtol=1e-7, atol=0)
