@@ -138,6 +138,23 @@ const char* mf_last_error(void);
  * pointers with n > 0. */
 mf_status mf_integrand(mf_process* p, const double* u, int64_t n, double* w, void* stream);
 
+/* mf_integrand for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same results, bit for bit, as mf_integrand, with
+ * the per-block point lists in a fixed device array of the library
+ * (16 MiB per device, held until the process ends) instead of the handle.
+ * No device memory is allocated or freed.  At most MF_NOALLOC_MAX_POINTS
+ * points per call (MF_EINVAL above); MF_ENOTSUP for g g -> t t~ g g g, whose
+ * integrand runs as several kernels with a workspace; MF_EINVAL if the
+ * current device is not the handle's.
+ * Every call on a device shares that device's array, so calls that overlap
+ * on one device (different streams or host threads) race; calls ordered on
+ * one stream do not.  Nothing in the array needs clearing between calls:
+ * each call writes every count and list entry it reads.  Arguments as for
+ * mf_integrand. */
+#define MF_NOALLOC_MAX_POINTS (1 << 22)
+mf_status mf_integrand_noalloc(mf_process* p, const double* u, int64_t n, double* w, void* stream);
+
 /* The same integrand and its derivatives (forward mode) at the same points:
  *   dw: device, [9][n] FP64: d w / d m_t, then d w / d theta_k for
  *       theta = (A_g, a_g, b_g, c_g, d_g, A_u, A_d, A_u~), i.e. pdf_params

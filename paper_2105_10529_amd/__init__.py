@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmf.so")
 MF_OK, MF_EINVAL, MF_ERANGE, MF_ENOMEM, MF_EDEVICE, MF_ENOTSUP = range(6)
 PROCESSES = {"gg>ttx": 0, "uux>ttx": 1, "ddx>ttx": 2, "gg>ttxg": 3, "gg>ttxgg": 4, "gg>ttxggg": 5}
 PRECISIONS = {"fp64": 0, "fp32": 1}
+NOALLOC_MAX_POINTS = 1 << 22  # MF_NOALLOC_MAX_POINTS of include/mf.h
 DEFAULT_PDF = (1.6, -0.2, -0.05, 5.0, 0.3,   # g
                2.2, 0.5, -0.02, 3.0, 0.2,    # u
                1.1, 0.5, -0.02, 4.0, 0.2,    # d
@@ -141,7 +142,7 @@ EXPORTS = ("mf_process_create", "mf_process_destroy", "mf_process_ndim", "mf_las
            "mf_integrand_grad", "mf_vegas_refine", "mf_integrate", "mf_grad", "mf_weights", "mf_weight_stats",
            "mf_flow_create", "mf_flow_destroy", "mf_flow_ndim", "mf_flow_param_count", "mf_flow_masks",
            "mf_flow_set_params", "mf_flow_get_params", "mf_flow_forward", "mf_flow_inverse", "mf_flow_loss_grad",
-           "mf_flow_adam_step", "mf_flow_train", "mf_flow_train_online", "mf_vjp")
+           "mf_flow_adam_step", "mf_flow_train", "mf_flow_train_online", "mf_vjp", "mf_integrand_noalloc")
 
 _lib = None
 
@@ -164,6 +165,8 @@ def lib():
         L.mf_last_error.restype = ctypes.c_char_p
         L.mf_integrand.argtypes = [P, P, i64, P, P]
         L.mf_integrand.restype = i32
+        L.mf_integrand_noalloc.argtypes = [P, P, i64, P, P]
+        L.mf_integrand_noalloc.restype = i32
         L.mf_integrand_grad.argtypes = [P, P, i64, P, P, P]
         L.mf_integrand_grad.restype = i32
         L.mf_vegas_refine.argtypes = [P, P, ctypes.c_int, ctypes.c_int, d, P]
@@ -317,6 +320,12 @@ class Process:
         if w is None:
             w = torch.empty(n, dtype=torch.float64, device=u.device)
         _check(lib().mf_integrand(self._h, _dev_ptr(u), n, _dev_ptr(w), _stream_ptr(stream)))
+        return w
+
+    def integrand_noalloc(self, u, w, stream=None):
+        """w[n] = integrand at u into a caller-allocated w, with no device allocation -- mf_integrand_noalloc."""
+        assert u.dim() == 2 and u.shape[0] == self.ndim and w.dim() == 1 and w.shape[0] == u.shape[1]
+        _check(lib().mf_integrand_noalloc(self._h, _dev_ptr(u), u.shape[1], _dev_ptr(w), _stream_ptr(stream)))
         return w
 
     def integrand_grad(self, u, stream=None):

@@ -22,6 +22,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,19 @@
 #include "status.h"
 
 using namespace mf;
+
+// Selection lists of mf_integrand_noalloc, in a device array of fixed size
+// (never allocated at run time): [MAX_BLOCKS] per-block counts, then the
+// per-block lists.  An n-point call with n <= NOALLOC_MAX_POINTS needs at most
+// NOALLOC_MAX_POINTS list entries: below MAX_BLOCKS * BLOCK points the blocks
+// hold one BLOCK-sized chunk each (ceil(n / BLOCK) * BLOCK entries), above it
+// the MAX_BLOCKS blocks hold ceil(n / (MAX_BLOCKS * BLOCK)) chunks each, and
+// NOALLOC_MAX_POINTS is a multiple of MAX_BLOCKS * BLOCK.  Each device keeps
+// its own copy until the process ends; host code must use the address from
+// hipGetSymbolAddress (g_noalloc_ptr), never the symbol itself.
+constexpr int64_t NOALLOC_MAX_POINTS = MF_NOALLOC_MAX_POINTS;
+static_assert(NOALLOC_MAX_POINTS % ((int64_t)MAX_BLOCKS * BLOCK) == 0, "list bound");
+static __device__ __align__(256) int scratch[MAX_BLOCKS + NOALLOC_MAX_POINTS];
 
 namespace mf {
 namespace {
@@ -593,6 +607,23 @@ mf_status check_stream_launch(const char* what) {
   return MF_OK;
 }
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_noalloc_mtx;
+int* g_noalloc_ptr[MAX_DEVICES] = {};
+hipError_t g_noalloc_err[MAX_DEVICES] = {};
+
+// Look up this device's copy of the scratch array once, with the device current.
+void noalloc_scratch_init(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lock(g_noalloc_mtx);
+  if (g_noalloc_ptr[dev]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_noalloc_err[dev] = e;
+  if (e == hipSuccess) g_noalloc_ptr[dev] = static_cast<int*>(ptr);
+  else (void)hipGetLastError();
+}
+
 // Grow the per-block selection lists to the chunks of an n-event iteration.
 mf_status ensure_select(mf_process* p, int64_t n, hipStream_t s) {
   if (n > (int64_t)INT32_MAX) return fail(MF_EINVAL, "n_events must be below 2^31 for fused iterations");
@@ -725,6 +756,7 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
   mf_process* p = new mf_process();
   p->cfg = *cfg;
   hipGetDevice(&p->device);
+  noalloc_scratch_init(p->device);
   p->ndim = 3 * (ng + 2) - 2;
   p->nb = cfg->n_bins;
   DevCfg& c = p->dc;
@@ -822,6 +854,31 @@ mf_status mf_integrand(mf_process* p, const double* u, int64_t n, double* w, voi
   if (n == 0) return MF_OK;
   if (!u || !w) return fail(MF_EINVAL, "NULL buffer");
   return run_integrand(p, u, n, w, (hipStream_t)stream);
+}
+
+mf_status mf_integrand_noalloc(mf_process* p, const double* u, int64_t n, double* w, void* stream) {
+  mf::clear_error();
+  if (!p) return fail(MF_EINVAL, "NULL process");
+  if (n < 0) return fail(MF_EINVAL, "negative event count");
+  if (n == 0) return MF_OK;
+  if (!u || !w) return fail(MF_EINVAL, "NULL buffer");
+  if (n > NOALLOC_MAX_POINTS)
+    return fail(MF_EINVAL, "mf_integrand_noalloc takes at most %lld points per call (got %lld)",
+                (long long)NOALLOC_MAX_POINTS, (long long)n);
+  if (p->L.integrand_ws || !p->L.integrand)
+    return fail(MF_ENOTSUP, "this process evaluates its integrand with a multi-kernel workspace; use mf_integrand");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) return fail(MF_EINVAL, "the process was created on device %d, current is %d", p->device, dev);
+  if (dev < 0 || dev >= MAX_DEVICES || !g_noalloc_ptr[dev])
+    return fail(MF_EDEVICE, "scratch array address unavailable on device %d: %s", dev,
+                hipGetErrorString(dev >= 0 && dev < MAX_DEVICES ? g_noalloc_err[dev] : hipErrorInvalidDevice));
+  const int nblk = blocks_for(n);
+  const int64_t cap = (n + (int64_t)nblk * BLOCK - 1) / ((int64_t)nblk * BLOCK) * BLOCK;
+  int* cnt = g_noalloc_ptr[dev];
+  int* list = cnt + MAX_BLOCKS;  // nblk * cap <= NOALLOC_MAX_POINTS entries (see the array's bound)
+  p->L.integrand(p->dc, u, n, w, nblk, list, cnt, cap, (hipStream_t)stream);
+  return check_stream_launch("k_integrand");
 }
 
 mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w, double* dw, void* stream) {
