@@ -1,18 +1,24 @@
 """Benchmark of the on-device VEGAS integration of the LO integrand.
 
-Workload (one "step" = one VEGAS iteration = one pass of the whole per-event
-pipeline over one batch): g g -> t t~ g at sqrt(s) = 13 TeV, m_t = 173 GeV,
-mu = m_t, gluon pT > 20 GeV and |eta| < 2.5, 7-dimensional integrand, 50 bins
-per dimension, 1e7 Philox events per iteration, FP64 throughout.  Warmup
+Headline workload (one "step" = one VEGAS iteration = one pass of the whole
+per-event pipeline over one batch): g g -> t t~ g g at sqrt(s) = 13 TeV,
+m_t = 173 GeV, mu = m_t, each gluon pT > 20 GeV, |eta| < 2.5, Delta R > 0.4,
+10-dimensional integrand, 50 bins per dimension, 1e8 Philox events per
+iteration, amplitudes in FP32 with FP64 (double-double) sums.  Warmup
 iterations adapt the grid; the timed iterations continue the same run.
 
-Prints one JSON line (value = events/s of the whole job, inputs generated in
-the kernel).  The roofline entry prices the fused per-event kernel's
-algorithmic FP64 flops (the emitted amplitude recursion, counted statically,
-for each event that passes the cuts: the kernel evaluates the matrix element
-of those events only) against the MI355X FP64 vector peak, using the kernel
-time the library measures with HIP events on the call's stream.  The CPU baseline times the
-FP64 oracle on a bounded sample of the same event stream.
+Prints one JSON line: value = events/s of the whole job (inputs generated in
+the kernel), and the metric's second half, the wall time from process
+creation to a relative error of 1e-3 of FP32 amplitudes with the learned
+(BF16 coupling-flow) proposal against plain FP64 VEGAS (and FP32 VEGAS), for
+three seeds, with the time inside the iteration that crosses the target
+interpolated.  The roofline entry prices the selection + fused per-event
+kernels' algorithmic FP32 flops (the emitted amplitude recursion and colour
+form, counted statically, for each event that passes the cuts: only those
+reach the matrix element) against the MI355X FP32 vector peak, using the
+kernel time the library measures with HIP events on the call's stream.  The
+CPU baseline times the FP64 oracle on a bounded sample of the same
+adapted-grid events.
 """
 from __future__ import annotations
 
@@ -28,14 +34,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "events/s per MI355X and time to 1e-3 rel. error: FP32+flow vs FP64 VEGAS"
-FP64_VECTOR_PEAK = 78.6e12  # MI355X FP64 vector FLOP/s (256 CUs x 128 FLOP/clk x 2.4 GHz)
+FP64_VECTOR_PEAK = 78.6e12  # MI355X FP64 vector FLOP/s (256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz)
+FP32_VECTOR_PEAK = 157.3e12  # MI355X FP32 vector FLOP/s (published; needs packed FP32 instructions)
+FP32_UNPACKED_PEAK = 78.6e12  # the same chip without packed FP32 (this build's device code uses none)
+HEADLINE_EVENTS = 100_000_000
 EVENTS = 10_000_000
-# HBM bytes per iteration of the kernel pair k_select<1> + k_vegas<1,0,double>
-# at 1e7 events (29.9 + 37.0 MB), from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# runs scaled by a 1 GiB copy calibration
-# (profiles/traffic_k_vegas_gg_ttg_fp64_1e7.md).  Set to None when those
-# kernels change until the counters are taken again.
-MEASURED_TRAFFIC_BYTES = 66.9e6
+SEEDS = (2105105290, 2105105291, 2105105292)
+TARGET = 1e-3
+# HBM bytes per iteration of the kernel pair k_select<2> + k_vegas<2,0,float>
+# at 1e8 events, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a
+# 1 GiB copy calibration (profiles/traffic_k_vegas_gg_ttgg_fp32_1e8.md).  None
+# until those counters are taken on the current kernels.
+TTGG_TRAFFIC_BYTES = None
+# the same for k_select<1> + k_vegas<1,0,double> at 1e7 events
+# (profiles/traffic_k_vegas_gg_ttg_fp64_1e7.md)
+TTG_TRAFFIC_BYTES = 66.9e6
 
 
 def flops_per_event(m: int) -> int:
@@ -45,137 +58,193 @@ def flops_per_event(m: int) -> int:
     return gen_me.flop_count(m)["total"]
 
 
-def cpu_baseline(seed: int, target_seconds: float = 15.0) -> dict:
-    """The FP64 oracle on the host cores, on the first events of the same stream
-    (sized from a short calibration run to take about target_seconds)."""
-    import oracle
+def ttgg_config(prec: str, seed: int = SEEDS[0], **kw):
+    import paper_2105_10529_amd as mf
 
-    orc = oracle.Oracle(oracle.Config(n_g=1))
-    edges = oracle.uniform_edges(7)
-    orc.vegas_iteration(edges, 0, 2000, seed, purpose=0)  # thread start-up
-    n = 50_000
-    t0 = time.perf_counter()
-    orc.vegas_iteration(edges, 0, n, seed, purpose=0)
-    dt = time.perf_counter() - t0
-    n = int(max(n, min(10_000_000, n * target_seconds / max(dt, 1e-3))))
-    t0 = time.perf_counter()
-    orc.vegas_iteration(edges, 0, n, seed, purpose=0)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "events/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"first {n} events of the same Philox stream (iteration 0) through a uniform grid, "
-                      f"gg->ttg FP64, OpenMP over events, {dt:.1f} s"}
+    return mf.Config(process="gg>ttxgg", precision=prec, dr_min=0.4, seed=seed, **kw)
+
+
+def interpolated_time(r, t_call: float, target: float = TARGET, prior=None):
+    """Time (from process creation) and events at which the combined relative
+    error of a run first reaches `target`, with the crossing iteration
+    interpolated: inside it both the inverse variance and the wall time are
+    taken to grow linearly with its events.  r: an IntegrationResult with
+    per-iteration estimates and end times (seconds from the start of the
+    call, which started t_call after process creation); prior: an earlier
+    estimate combined first.  Returns (seconds, iterations as a fraction) or
+    (None, None) if the run never reached the target."""
+    I = np.asarray(r.iter_integral, float)
+    E = np.asarray(r.iter_error, float)
+    T = np.asarray(r.iter_seconds, float)
+    w = np.where(E > 0, 1.0 / np.maximum(E, 1e-300) ** 2, 0.0)
+    W0 = WI0 = 0.0
+    if prior is not None and prior.error > 0:
+        W0 = 1.0 / prior.error**2
+        WI0 = prior.integral * W0
+    W = W0 + np.cumsum(w)
+    mean = (WI0 + np.sum(I * w)) / W[-1]
+    need = 1.0 / (target * abs(mean)) ** 2
+    if W0 >= need:
+        return t_call, 0.0
+    k = int(np.argmax(W >= need)) if np.any(W >= need) else -1
+    if k < 0:
+        return None, None
+    Wp = W0 if k == 0 else W[k - 1]
+    f = (need - Wp) / (W[k] - Wp)
+    tp = 0.0 if k == 0 else T[k - 1]
+    return t_call + tp + f * (T[k] - tp), k + f
+
+
+def _spread(xs):
+    xs = [float(x) for x in xs]
+    return {"median": float(np.median(xs)), "min": min(xs), "max": max(xs), "per_seed": xs}
 
 
 def _eff(stats: dict) -> dict:
     return {"mean_over_max": stats["mean"] / stats["max"], "mean_over_q999": stats["mean"] / stats["quantile"]}
 
 
-def flow_comparison(n_iter_events: int = 10_000_000, eval_events: int = 10_000_000, steps: int = 30,
-                    flow_iter_events: int = 4_000_000, vegas: bool = True, process: str = "gg>ttxgg",
-                    precisions=("fp64", "fp32"), long_steps: int = 300, batch: int = 65536,
-                    lr: float = 5e-3, helicity: int = 0) -> dict:
-    """g g -> t t~ g g (or g g g; Delta R > 0.4): wall time from process
-    creation to a relative error of 1e-3, for plain VEGAS in FP64 (where
-    built), plain VEGAS with FP32 amplitudes, and FP32 amplitudes with the
-    learned proposal: VEGAS warm-up
-    5 x 1e6, `steps` on-policy variance-training steps of the flow (65536
-    points per step, sampled from the flow mixed with 20% uniform points on
-    the frozen grid), whose batches are themselves estimates of the integral
-    (pooled per 50 steps and combined by inverse variance, stopping at 1e-3),
-    then iterations of flow_iter_events points of the trained proposal
-    combined with that estimate until 1e-3 (30 steps is the fastest setting
-    measured to this target on g g -> t t~ g g; longer training lowers the
-    variance further, which a second, untimed flow trained for long_steps
-    steps shows).
-    Also the per-event relative variance and the unweighting efficiency of
-    each proposal on a fresh sample of eval_events with the final grid."""
+def _load_kernels(process: str, precisions, helicity: int = 0) -> None:
+    """Run every kernel of the VEGAS and flow pipelines once (untimed), so that
+    no timing includes one-time code-object loading."""
     import torch
 
     import paper_2105_10529_amd as mf
 
-    def cfg(prec):
-        return mf.Config(process=process, precision=prec, dr_min=0.4, helicity=helicity)
-
-    # load every kernel of the pipelines once (untimed), so that no timing
-    # below includes one-time code-object loading
     for prec in precisions:
-        w = mf.Process(cfg(prec))
+        w = mf.Process(mf.Config(process=process, precision=prec, dr_min=0.4, helicity=helicity))
         w.integrate(2, 20_000, adapt=True)
         if prec == "fp32":
             wf = mf.Flow(w.ndim, max_batch=1024)
             w.train_flow_online(wf, 2, batch=1024, loss="variance", flow_mix=0.2)
             w.integrate(1, 20_000, adapt=False, flow=wf, flow_mix=0.2)
+            w.integrate(2, 20_000, adapt=False, flow=wf, flow_mix=0.2, fallback_rel_var=1e-30)
             mf.weight_stats(w.weights(0, 20_000, flow=wf, flow_mix=0.2)[0])
             del wf
         del w
     torch.cuda.synchronize()
-    res = {}
-    for prec in (precisions if vegas else ()):
+
+
+def learned_vs_vegas(process: str = "gg>ttxgg", precisions=("fp64", "fp32"), seeds=SEEDS,
+                     vegas_events: int = 10_000_000, flow_iter_events: int = 4_000_000, steps: int = 30,
+                     batch: int = 65536, lr: float = 5e-3, helicity: int = 0, eval_events: int = 10_000_000,
+                     long_steps: int = 0) -> dict:
+    """Wall time from process creation to a combined relative error of 1e-3,
+    per seed, for plain VEGAS in each precision (iterations of vegas_events,
+    the grid adapting after each) and for FP32 amplitudes with the learned
+    proposal: VEGAS warm-up 5 x 1e6, `steps` on-policy variance-training
+    steps of the flow (batch points per step from the flow mixed with 20%
+    uniform points on the frozen grid; the batches are themselves unbiased
+    estimates, pooled per 50 steps), then iterations of flow_iter_events
+    points combined with that estimate, with plain VEGAS on the same frozen
+    grid as the fallback when the flow's first iteration has a larger
+    per-event relative variance than the last warm-up iteration of VEGAS.
+    Times are given as measured to the iteration boundary and interpolated
+    inside the crossing iteration.  For the first seed also the per-event
+    relative variance and unweighting efficiency of both proposals on a fresh
+    sample of eval_events on the final grid (and, with long_steps, of a flow
+    trained that long, untimed)."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+
+    def cfg(prec, seed):
+        return mf.Config(process=process, precision=prec, dr_min=0.4, helicity=helicity, seed=seed)
+
+    _load_kernels(process, precisions, helicity)
+    runs = {f"vegas_{p}": [] for p in precisions}
+    runs["fp32_flow"] = []
+    for si_, seed in enumerate(seeds):
+        for prec in precisions:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = mf.Process(cfg(prec, seed))
+            t_call = time.perf_counter() - t0
+            r = p.integrate(200, vegas_events, target_rel_err=TARGET, adapt=True)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            ti, k = interpolated_time(r, t_call)
+            rec = {"seed": seed, "time_to_1e-3_s": t, "time_to_1e-3_interpolated_s": ti,
+                   "iterations": r.n_iter_done, "iterations_interpolated": k,
+                   "events_interpolated": None if k is None else k * vegas_events,
+                   "integral_pb": r.integral, "error_pb": r.error,
+                   "events_per_s": r.n_events_total / r.seconds}
+            if si_ == 0 and eval_events:
+                w, _ = p.weights(1 << 30, eval_events)
+                st = mf.weight_stats(w)
+                del w
+                rec["relative_variance_per_event"] = st["relvar"]
+                rec["unweighting"] = _eff(st)
+            runs[f"vegas_{prec}"].append(rec)
+            del p
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        p = mf.Process(cfg(prec))
-        r = p.integrate(100, n_iter_events, target_rel_err=1e-3, adapt=True)
+        p = mf.Process(cfg("fp32", seed))
+        warm = p.integrate(5, 1_000_000, adapt=True)
         torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        w, _ = p.weights(1 << 30, eval_events)
-        st = mf.weight_stats(w)
-        del w
-        res[f"vegas_{prec}"] = {"time_to_1e-3_s": t, "iterations": r.n_iter_done, "events": r.n_events_total,
-                                "integral_pb": r.integral, "error_pb": r.error,
-                                "relative_variance_per_event": st["relvar"],
-                                "unweighting": _eff(st)}
-        del p
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    p = mf.Process(cfg("fp32"))
-    p.integrate(5, 1_000_000, adapt=True)
-    torch.cuda.synchronize()
-    t_warm = time.perf_counter() - t0
-    f = mf.Flow(p.ndim, max_batch=batch)
-    mix, group = 0.2, 50
-    rel, est = p.train_flow_online(f, steps, batch=batch, lr=lr, loss="variance", flow_mix=mix,
-                                   group_steps=group, target_rel_err=1e-3, with_estimate=True)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0 - t_warm
-    if est.time_to_target >= 0.0:
-        r = est
-    else:
-        r = p.integrate(100, flow_iter_events, target_rel_err=1e-3, adapt=False, flow=f, flow_mix=mix,
-                        iter_offset=1 << 24, prior=est)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    wf, _ = p.weights(1 << 30, eval_events, flow=f, flow_mix=mix)
-    sf = mf.weight_stats(wf)
-    del wf
-    wv, _ = p.weights(1 << 30, eval_events)
-    sv = mf.weight_stats(wv)
-    del wv
-    # attainable variance: the same recipe trained for long_steps steps (untimed)
-    f300 = mf.Flow(p.ndim, max_batch=batch)
-    p.train_flow_online(f300, long_steps, batch=batch, lr=lr, loss="variance", flow_mix=mix,
-                        iter_offset=1 << 26)
-    w3, _ = p.weights(1 << 30, eval_events, flow=f300, flow_mix=mix)
-    s3 = mf.weight_stats(w3)
-    del w3, f300
-    res["fp32_flow"] = {"time_to_1e-3_s": t, "time_excluding_training_s": t - t_train, "warmup_s": t_warm,
-                        "training_s": t_train, "training_steps_done": int(np.count_nonzero(rel)),
-                        "training_batch": batch, "learning_rate": lr,
-                        "training_estimate_pb": [est.integral, est.error],
-                        "training_events": est.n_events_total,
-                        "iterations_after_training": r.n_iter_done if r is not est else 0,
-                        "events_after_training": r.n_events_total if r is not est else 0,
-                        "integral_pb": r.integral, "error_pb": r.error,
-                        "batch_relative_variance_first_last": [float(np.mean(rel[:5])), float(np.mean(rel[-10:]))],
-                        "relative_variance_per_event": sf["relvar"],
+        t_warm = time.perf_counter() - t0
+        # the VEGAS proposal's per-event relative variance on the frozen grid,
+        # from the last warm-up iteration: (N - 1) sigma^2 / I^2
+        rv_vegas = (1_000_000 - 1) * warm.iter_error[-1] ** 2 / warm.iter_integral[-1] ** 2
+        f = mf.Flow(p.ndim, max_batch=batch, seed=seed)
+        mix, group = 0.2, 50
+        rel, est = p.train_flow_online(f, steps, batch=batch, lr=lr, loss="variance", flow_mix=mix,
+                                       group_steps=group, target_rel_err=TARGET, with_estimate=True)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0 - t_warm
+        r = None
+        if est.time_to_target >= 0.0:
+            t = ti = time.perf_counter() - t0
+            k = 0.0
+            final = est
+        else:
+            t_call = time.perf_counter() - t0
+            r = p.integrate(200, flow_iter_events, target_rel_err=TARGET, adapt=False, flow=f, flow_mix=mix,
+                            iter_offset=1 << 24, prior=est, fallback_rel_var=rv_vegas)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            ti, k = interpolated_time(r, t_call, prior=est)
+            final = r
+        rec = {"seed": seed, "time_to_1e-3_s": t, "time_to_1e-3_interpolated_s": ti,
+               "warmup_s": t_warm, "training_s": t_train, "time_excluding_training_s": t - t_train,
+               "training_steps": int(np.count_nonzero(rel)), "training_batch": batch, "learning_rate": lr,
+               "training_estimate_pb": [est.integral, est.error],
+               "iterations_after_training": 0 if r is None else r.n_iter_done,
+               "iterations_after_training_interpolated": k,
+               "integral_pb": final.integral, "error_pb": final.error,
+               "vegas_warmup_relative_variance": rv_vegas,
+               "flow_first_iteration_relative_variance": None if r is None else r.flow_rel_var,
+               "fallback_to_vegas": None if r is None else bool(r.fallback_iter >= 0),
+               "batch_relative_variance_first_last": [float(np.mean(rel[:5])), float(np.mean(rel[-10:]))]}
+        if si_ == 0 and eval_events:
+            wf, _ = p.weights(1 << 30, eval_events, flow=f, flow_mix=mix)
+            sf = mf.weight_stats(wf)
+            del wf
+            wv, _ = p.weights(1 << 30, eval_events)
+            sv = mf.weight_stats(wv)
+            del wv
+            rec.update({"relative_variance_per_event": sf["relvar"],
                         "relative_variance_per_event_vegas_same_grid": sv["relvar"],
-                        "unweighting": _eff(sf), "unweighting_vegas_same_grid": _eff(sv),
-                        f"trained_{long_steps}_steps": {"relative_variance_per_event": s3["relvar"],
-                                                        "unweighting": _eff(s3)}}
-    return res
-
-
-FP32_VECTOR_PEAK = 157.3e12  # MI355X FP32 vector FLOP/s (published; packed FP32 instructions)
-FP32_MATRIX_PEAK = 157.3e12  # MI355X FP32 matrix-core FLOP/s (dense)
+                        "unweighting": _eff(sf), "unweighting_vegas_same_grid": _eff(sv)})
+            if long_steps:
+                fl = mf.Flow(p.ndim, max_batch=batch, seed=seed)
+                p.train_flow_online(fl, long_steps, batch=batch, lr=lr, loss="variance", flow_mix=mix,
+                                    iter_offset=1 << 26)
+                w3, _ = p.weights(1 << 30, eval_events, flow=fl, flow_mix=mix)
+                s3 = mf.weight_stats(w3)
+                del w3, fl
+                rec[f"trained_{long_steps}_steps"] = {"relative_variance_per_event": s3["relvar"],
+                                                      "unweighting": _eff(s3)}
+        runs["fp32_flow"].append(rec)
+        del p, f
+    out = {"process": process, "seeds": list(seeds), "vegas_events_per_iteration": vegas_events,
+           "flow_events_per_iteration": flow_iter_events, "runs": runs, "time_to_1e-3_s": {},
+           "time_to_1e-3_interpolated_s": {}}
+    for key, lst in runs.items():
+        out["time_to_1e-3_s"][key] = _spread([x["time_to_1e-3_s"] for x in lst])
+        tis = [x["time_to_1e-3_interpolated_s"] for x in lst]
+        out["time_to_1e-3_interpolated_s"][key] = _spread(tis) if all(v is not None for v in tis) else None
+    return out
 
 
 def ttggg_helicity_sampling(events: int = 4_000_000) -> dict:
@@ -245,21 +314,19 @@ def ttggg_throughput(events: int = 4_000_000, iters: int = 3) -> dict:
             "colour_flops_per_passing_event": fc["states"] * fc["colour_per_state"]}
 
 
-def ttggg_flow_comparison() -> dict:
+def ttggg_flow_comparison(seeds=SEEDS[:1]) -> dict:
     """The learned-proposal comparison on g g -> t t~ g g g (13 dims; FP32
     amplitudes, so FP32 VEGAS is the baseline): iterations of 4e6 events, 60
     training steps of 65536 points (the fastest of 30/60 steps x 65536 and
     120 x 32768 measured; a learning rate of 1e-2 trained worse or diverged),
     flow iterations of 2e6 points, and a 150-step flow for the attainable
     variance; with the polarisation states summed and with one sampled state
-    per point.  With sampled states plain VEGAS is the faster method (the
-    flow's grid is frozen after a warm-up whose variance is ~3x that of the
-    fully adapted grid, and the state sampling adds noise to the training
-    gradients; 30/60/120/200 steps measured 3.2/2.8/2.3/4.9 s against 0.9 s)."""
-    return {"summed_states": flow_comparison(4_000_000, 4_000_000, 60, 2_000_000, process="gg>ttxggg",
-                                             precisions=("fp32",), long_steps=150),
-            "sampled_state": flow_comparison(4_000_000, 4_000_000, 60, 4_000_000, process="gg>ttxggg",
-                                             precisions=("fp32",), long_steps=150, helicity=1)}
+    per point.  With sampled states the trained flow's variance exceeds the
+    VEGAS proposal's on the same grid, and the fallback continues with VEGAS."""
+    return {"summed_states": learned_vs_vegas("gg>ttxggg", ("fp32",), seeds, 4_000_000, 2_000_000, 60,
+                                              eval_events=4_000_000, long_steps=150),
+            "sampled_state": learned_vs_vegas("gg>ttxggg", ("fp32",), seeds, 4_000_000, 4_000_000, 60,
+                                              helicity=1, eval_events=4_000_000, long_steps=150)}
 
 
 def ttg_dynamic_scale(events: int = EVENTS, iters: int = 10) -> dict:
@@ -399,43 +466,89 @@ def flow_roofline(n: int = 10_000_000) -> dict:
             "kernel": "k_coupling<true,false> (sampling direction, 64 events per workgroup)"}
 
 
-def secondary(seed_events: int) -> dict:
-    """Bounded extra measurements on the same GPU (reported beside the main line).
+def cpu_baseline(p32, iteration: int, target_seconds: float = 12.0) -> dict:
+    """The FP64 oracle on the host cores, on the first events of one VEGAS
+    iteration through the adapted grid of the timed run (the same Philox
+    events the GPU draws for that iteration), sized from a short calibration
+    run to take about target_seconds."""
+    import torch
 
-    * g g -> t t~ g g (10 dims, Delta R > 0.4): events/s of the fused kernel
-      with FP32 amplitudes (1e8 events per iteration) and with FP64 (1e7), and
-      the wall time to 1e-3 relative error of plain VEGAS in each precision.
-    * d sigma/d m_t on g g -> t t~ g at m_t = 171, 173, 175 GeV from 1e8
-      pathwise-derivative events each, with a grid frozen from a VEGAS warm-up.
-    """
+    import oracle
+
+    edges = torch.empty((p32.ndim, 51), dtype=torch.float64, device="cuda")
+    p32.integrate(1, 2, adapt=False, edges_out=edges, iter_offset=1 << 30)
+    E = edges.cpu().numpy()
+    orc = oracle.Oracle(oracle.Config(n_g=2, dr_min=0.4))
+    orc.vegas_iteration(E, iteration, 500, p32.cfg.seed, purpose=0)  # thread start-up
+    n = 20_000
+    t0 = time.perf_counter()
+    orc.vegas_iteration(E, iteration, n, p32.cfg.seed, purpose=0)
+    dt = time.perf_counter() - t0
+    n = int(max(n, min(5_000_000, n * target_seconds / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    S1, _, _, nz, _ = orc.vegas_iteration(E, iteration, n, p32.cfg.seed, purpose=0)
+    dt = time.perf_counter() - t0
+    w = p32.weights(iteration, n)[0]
+    gpu_mean = float(w.sum().item()) / n
+    return {"value": n / dt, "unit": "events/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"first {n} Philox events of VEGAS iteration {iteration} through the adapted grid of the "
+                      f"timed run, gg->ttgg FP64 (Delta R > 0.4), OpenMP over events, {dt:.1f} s",
+            "oracle_mean_pb": S1 / n, "gpu_fp32_mean_same_events_pb": gpu_mean,
+            "relative_difference": abs(gpu_mean - S1 / n) / abs(S1 / n), "nonzero": nz}
+
+
+def ttg_fp64(events: int = EVENTS, iters: int = 10, warmup: int = 2) -> dict:
+    """g g -> t t~ g in FP64 (7 dims, gluon pT > 20 GeV, |eta| < 2.5):
+    events/s of 1e7-event VEGAS iterations after an adapting warm-up, and the
+    selection + fused kernels' algorithmic FP64 rate."""
     import torch
 
     import paper_2105_10529_amd as mf
 
-    out = {}
-    for prec, n in (("fp32", 100_000_000), ("fp64", 10_000_000)):
-        p = mf.Process(mf.Config(process="gg>ttxgg", precision=prec, dr_min=0.4))
-        p.integrate(2, min(n, 10_000_000), adapt=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = p.integrate(2, n, adapt=True, iter_offset=2)
-        dt = time.perf_counter() - t0
-        fresh = mf.Process(mf.Config(process="gg>ttxgg", precision=prec, dr_min=0.4))
-        tt = fresh.integrate(40, 10_000_000, target_rel_err=1e-3, adapt=True)
-        out[f"ttgg_{prec}"] = {
-            "events_per_s": 2 * n / dt, "kernel_ms_avg": 1e3 * r.kernel_seconds / 2, "events_per_iteration": n,
-            "integral_pb": r.integral, "error_pb": r.error,
-            "time_to_1e-3_s": tt.time_to_target, "iterations_to_1e-3": tt.n_iter_done,
-            "events_to_1e-3": tt.n_events_total, "integral_at_1e-3_pb": tt.integral, "error_at_1e-3_pb": tt.error,
-        }
-    out["ttgg_fp32_vs_oracle_subsample"] = fp32_subsample_check()
-    out["ttgg_flow_vs_vegas"] = flow_comparison()
-    out["ttg_observables"] = ttg_observables()
-    out["ttg_dynamic_scale"] = ttg_dynamic_scale()
-    out["ttggg_fp32"] = ttggg_throughput()
-    out["ttggg_helicity_sampling"] = ttggg_helicity_sampling()
-    out["ttggg_flow_vs_vegas"] = ttggg_flow_comparison()
-    out["flow_roofline"] = flow_roofline()
+    p = mf.Process(mf.Config(process="gg>ttxg", precision="fp64"))
+    p.integrate(warmup, events, adapt=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = p.integrate(iters, events, adapt=True, iter_offset=warmup)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fpe = flops_per_event(3)
+    kavg = r.kernel_seconds / iters
+    passing = r.n_nonzero / iters
+    ach = fpe * passing / kavg
+    return {"events_per_s": iters * events / dt, "kernel_ms_avg": 1e3 * kavg, "integral_pb": r.integral,
+            "error_pb": r.error, "cut_efficiency": r.n_nonzero / max(r.n_events_total, 1),
+            "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
+                         "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK,
+                         "traffic": TTG_TRAFFIC_BYTES if events == EVENTS else None,
+                         "kernel": "k_select<1> + k_vegas<1,0,double>", "flops_per_passing_event": fpe}}
+
+
+def ttgg_fp64_throughput(events: int = EVENTS, iters: int = 3) -> dict:
+    """Plain FP64 VEGAS on g g -> t t~ g g (the baseline of the comparison):
+    events/s of 1e7-event iterations after an adapting warm-up."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+
+    p = mf.Process(ttgg_config("fp64"))
+    p.integrate(2, events, adapt=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = p.integrate(iters, events, adapt=True, iter_offset=2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"events_per_s": iters * events / dt, "kernel_ms_avg": 1e3 * r.kernel_seconds / iters,
+            "events_per_iteration": events}
+
+
+def ttg_gradients() -> dict:
+    """d sigma/d m_t on g g -> t t~ g at m_t = 171, 173, 175 GeV from 1e8
+    pathwise-derivative events each, with a grid frozen from a VEGAS warm-up."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+
     grads = {}
     for mt in (171.0, 173.0, 175.0):
         p = mf.Process(mf.Config(process="gg>ttxg", m_t=mt))
@@ -445,11 +558,16 @@ def secondary(seed_events: int) -> dict:
         vals, errs = p.grad(100_000_000, iter_offset=100)
         dt = time.perf_counter() - t0
         grads[f"{mt:g}"] = {"sigma_pb": vals[0], "sigma_err": errs[0], "dsigma_dmt_pb_per_gev": vals[1],
-                            "dsigma_dmt_err": errs[1], "dsigma_dtheta": list(map(float, vals[2:])),
-                            "dsigma_dtheta_err": list(map(float, errs[2:])), "events": 100_000_000,
+                            "dsigma_dmt_err": errs[1], "dsigma_dAg_pb": vals[2], "events": 100_000_000,
                             "seconds": dt}
-    out["ttg_gradients"] = grads
-    return out
+    return grads
+
+
+def extended() -> dict:
+    """Longer measurements, not part of the default run (--extended)."""
+    return {"ttg_observables": ttg_observables(), "ttg_dynamic_scale": ttg_dynamic_scale(),
+            "ttggg_helicity_sampling": ttggg_helicity_sampling(), "ttggg_flow_vs_vegas": ttggg_flow_comparison(),
+            "ttgg_flow_300_steps": learned_vs_vegas(precisions=("fp32",), seeds=SEEDS[:1], long_steps=300)}
 
 
 def main() -> int:
@@ -457,18 +575,17 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--events", type=int, default=EVENTS)
+    ap.add_argument("--events", type=int, default=HEADLINE_EVENTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparison", action="store_true",
+                    help="skip the time-to-1e-3 comparison (profiling runs of the headline kernels)")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--workload", choices=("ttg", "ttgg", "ttggg"), default="ttg",
-                    help="ttg: g g -> t t~ g FP64 (the reported workload); ttgg, ttggg: g g -> t t~ g g (g) with "
-                         "FP32 amplitudes (profiling runs)")
-    ap.add_argument("--flow-only", action="store_true",
-                    help="only run the g g -> t t~ g g learned-proposal comparison and the flow roofline (profiling)")
-    ap.add_argument("--observables-only", action="store_true",
-                    help="only run the g g -> t t~ g observable histograms (profiling)")
-    ap.add_argument("--ttggg-only", action="store_true",
-                    help="only run the g g -> t t~ g g g throughput and learned-proposal measurements (profiling)")
+    ap.add_argument("--extended", action="store_true",
+                    help="also run observables, dynamic scale, g g -> t t~ g g g comparisons and a 300-step flow")
+    ap.add_argument("--only", choices=("ttg", "flow", "ttggg", "comparison"), default=None,
+                    help="only one measurement (profiling): ttg = g g -> t t~ g FP64 iterations, flow = the "
+                         "coupling-flow sampling pass, ttggg = g g -> t t~ g g g throughput, comparison = the "
+                         "time-to-1e-3 comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (to calibrate HBM counters) and exit")
     args = ap.parse_args()
@@ -491,29 +608,21 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n * 8}), flush=True)
         return 0
-    if args.flow_only:
-        print(json.dumps({"ttgg_flow_vs_vegas": flow_comparison(), "flow_roofline": flow_roofline()}), flush=True)
+    if args.only == "ttg":
+        print(json.dumps({"ttg_fp64": ttg_fp64()}), flush=True)
         return 0
-    if args.observables_only:
-        print(json.dumps({"ttg_observables": ttg_observables(), "ttg_dynamic_scale": ttg_dynamic_scale()}),
-              flush=True)
+    if args.only == "flow":
+        print(json.dumps({"flow_roofline": flow_roofline()}), flush=True)
         return 0
-    if args.ttggg_only:
-        print(json.dumps({"ttggg_fp32": ttggg_throughput(), "ttggg_helicity_sampling": ttggg_helicity_sampling(),
-                          "ttggg_flow_vs_vegas": ttggg_flow_comparison()}), flush=True)
+    if args.only == "ttggg":
+        print(json.dumps({"ttggg_fp32": ttggg_throughput()}), flush=True)
         return 0
-    if args.workload in ("ttgg", "ttggg"):
-        proc = "gg>ttx" + args.workload[2:]
-        p = mf.Process(mf.Config(process=proc, precision="fp32", dr_min=0.4))
-        if args.warmup:
-            p.integrate(args.warmup, args.events, adapt=True)
-        r = p.integrate(args.steps, args.events, adapt=True, iter_offset=args.warmup)
-        print(json.dumps({"workload": f"{proc} fp32", "events_per_s": args.steps * args.events / r.seconds,
-                          "kernel_ms_avg": 1e3 * r.kernel_seconds / args.steps,
-                          "cut_efficiency": r.n_nonzero / max(r.n_events_total, 1),
-                          "integral_pb": r.integral, "error_pb": r.error}), flush=True)
+    if args.only == "comparison":
+        print(json.dumps({"comparison": learned_vs_vegas()}), flush=True)
         return 0
-    p = mf.Process(mf.Config(process="gg>ttxg", precision="fp64"))
+
+    # headline: g g -> t t~ g g, FP32 amplitudes, 1e8 events per VEGAS iteration
+    p = mf.Process(ttgg_config("fp32"))
     stream = torch.cuda.current_stream()
     if args.warmup > 0:
         p.integrate(args.warmup, args.events, adapt=True, iter_offset=0, stream=stream)
@@ -528,10 +637,10 @@ def main() -> int:
     wall = time.perf_counter() - t0
     gpu_s = ev0.elapsed_time(ev1) * 1e-3
     elapsed = max(wall, gpu_s)
-    total_events = args.steps * args.events
-    value = total_events / elapsed
+    value = args.steps * args.events / elapsed
+    print(f"# headline done: {value:.4g} events/s", file=sys.stderr, flush=True)
 
-    fpe = flops_per_event(3)
+    fpe = flops_per_event(4)
     kernel_avg = r.kernel_seconds / args.steps
     passing = r.n_nonzero / args.steps  # events whose matrix element is evaluated, per launch
     achieved = fpe * passing / kernel_avg
@@ -546,24 +655,27 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "gg->ttg LO, 13 TeV, m_t=173 GeV, mu=m_t, gluon pT>20 GeV |eta|<2.5; "
-                        "7-dim VEGAS (50 bins/dim), 1e7 Philox events per iteration, FP64",
+            "workload": "gg->ttgg LO, 13 TeV, m_t=173 GeV, mu=m_t, each gluon pT>20 GeV |eta|<2.5, "
+                        "Delta R>0.4; 10-dim VEGAS (50 bins/dim), 1e8 Philox events per iteration, FP32 "
+                        "amplitudes with FP64 double-double sums; time to 1e-3: FP32 amplitudes + BF16 "
+                        "coupling flow (VEGAS fallback) vs FP64 VEGAS",
             "events_per_step": args.events,
-            "process": "gg>ttxg",
+            "process": "gg>ttxgg",
             "parallelism": "single-gpu",
         },
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
-            "peak": FP64_VECTOR_PEAK / 1e12,
+            "peak": FP32_VECTOR_PEAK / 1e12,
             "unit": "TFLOP/s",
-            "frac": achieved / FP64_VECTOR_PEAK,
-            "traffic": MEASURED_TRAFFIC_BYTES if args.events == EVENTS and MEASURED_TRAFFIC_BYTES else None,
-            "traffic_unit": "bytes per iteration (HBM read + write of both kernels, counter-calibrated)",
-            "kernel": "k_select<1> + k_vegas<1,0,double> (cut selection, then the fused weight of the kept events)",
+            "frac": achieved / FP32_VECTOR_PEAK,
+            "peak_unpacked": FP32_UNPACKED_PEAK / 1e12,
+            "frac_unpacked": achieved / FP32_UNPACKED_PEAK,
+            "traffic": TTGG_TRAFFIC_BYTES if args.events == HEADLINE_EVENTS else None,
+            "kernel": "k_select<2> + k_vegas<2,0,float> (cut selection, then the fused weight of the kept events)",
             "flops_per_event": fpe,
             "flops_per": "event that passes the cuts (the matrix element is evaluated for those only)",
             "evaluated_events_per_launch": passing,
@@ -574,10 +686,60 @@ def main() -> int:
         "chi2_dof": r.chi2_dof,
         "cut_efficiency": r.n_nonzero / max(r.n_events_total, 1),
     }
+    if not args.no_comparison:
+        cmp_ = learned_vs_vegas()
+        print("# comparison done", file=sys.stderr, flush=True)
+        t = cmp_["time_to_1e-3_interpolated_s"]
+        f64 = ttgg_fp64_throughput()
+        out["time_to_1e-3_s"] = {
+            "fp64_vegas": t["vegas_fp64"], "fp32_vegas": t["vegas_fp32"], "fp32_flow": t["fp32_flow"],
+            "to_iteration_boundary": {k: v["median"] for k, v in cmp_["time_to_1e-3_s"].items()},
+            "speedup_fp32_flow_vs_fp64_vegas": t["vegas_fp64"]["median"] / t["fp32_flow"]["median"],
+            "seeds": list(SEEDS),
+            "method": "wall time from process creation; inside the iteration that crosses 1e-3 the inverse "
+                      "variance and the time are interpolated linearly in its events"}
+        out["events_per_s"] = {"fp32_vegas": value, "fp64_vegas": f64["events_per_s"]}
+        out["comparison"] = {
+            "flow_fallback_to_vegas": [x["fallback_to_vegas"] for x in cmp_["runs"]["fp32_flow"]],
+            "relative_variance_per_event": {
+                "fp64_vegas": cmp_["runs"]["vegas_fp64"][0]["relative_variance_per_event"],
+                "fp32_flow": cmp_["runs"]["fp32_flow"][0]["relative_variance_per_event"],
+                "vegas_same_frozen_grid": cmp_["runs"]["fp32_flow"][0][
+                    "relative_variance_per_event_vegas_same_grid"]},
+            "unweighting_mean_over_max": {
+                "fp64_vegas": cmp_["runs"]["vegas_fp64"][0]["unweighting"]["mean_over_max"],
+                "fp32_flow": cmp_["runs"]["fp32_flow"][0]["unweighting"]["mean_over_max"]},
+            "integral_pb": {k: [v[0]["integral_pb"], v[0]["error_pb"]] for k, v in cmp_["runs"].items()}}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p.cfg.seed)
+        cb = cpu_baseline(p, iteration=777)
+        if "time_to_1e-3_s" in out:
+            ev = [x["events_interpolated"] for x in cmp_["runs"]["vegas_fp64"]]
+            cb["time_to_1e-3_extrapolated_s"] = float(np.median(ev)) / cb["value"]
+            cb["time_to_1e-3_note"] = ("extrapolation: the median number of events plain FP64 VEGAS needed on the "
+                                       "GPU (same algorithm) divided by the oracle's events/s")
+        out["cpu_baseline"] = cb
+        print("# cpu baseline done", file=sys.stderr, flush=True)
     if not args.no_secondary:
-        out["secondary"] = secondary(args.events)
+        ttg = ttg_fp64()
+        sub = fp32_subsample_check()
+        fl = flow_roofline()
+        g3 = ttggg_throughput()
+        out["secondary"] = {
+            "ttg_fp64": {k: ttg[k] for k in ("events_per_s", "kernel_ms_avg", "integral_pb", "error_pb")} | {
+                "roofline_frac": ttg["roofline"]["frac"], "achieved_tflops": ttg["roofline"]["achieved"]},
+            "ttgg_fp32_vs_oracle_1e5": {k: sub[k] for k in ("fp32_per_event_rel_err_max",
+                                                             "fp32_per_event_rel_err_median",
+                                                             "fp32_per_event_rel_err_q999", "fp32_integral_rel_err",
+                                                             "fp64_per_event_rel_err_max", "same_zero_pattern")},
+            "flow_sampling": {k: fl[k] for k in ("events_per_s", "ms_per_pass", "achieved_tflops", "frac")},
+            "ttggg_fp32": {k: g3[k] for k in ("events_per_s", "cut_efficiency", "iteration_kernels_ms_avg",
+                                               "algorithmic_tflops_whole_integrand")},
+            "ttg_gradients_dsigma_dmt": {k: [v["dsigma_dmt_pb_per_gev"], v["dsigma_dmt_err"]]
+                                         for k, v in ttg_gradients().items()},
+        }
+        print("# secondary done", file=sys.stderr, flush=True)
+    if args.extended:
+        out["extended"] = extended()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -192,10 +192,12 @@ typedef struct {
   double hi[MF_N_OBS];    /* upper edge, > lo */
   double* sums;           /* host output [MF_N_OBS][nbins][2]: per bin the sum
                              of w and of w^2 over the events of the counted
-                             iterations (those after warmup_iters_discarded);
-                             with N events per iteration and n counted
-                             iterations the bin's cross section is
-                             sum w / (n N) (pb) */
+                             iterations (those after warmup_iters_discarded) */
+  double* sigma;          /* host output [MF_N_OBS][nbins][2], or NULL: per bin
+                             the cross section sum w / M (pb) and its Monte
+                             Carlo error sqrt((sum w^2 / M - (sum w / M)^2) /
+                             (M - 1)), with M = N * (counted iterations) the
+                             number of counted events */
 } mf_observables;
 
 typedef struct {
@@ -222,6 +224,17 @@ typedef struct {
                                      only: MF_ENOTSUP with a flow, for
                                      g g -> t t~ g g in FP64 and for
                                      g g -> t t~ g g g) */
+  double fallback_rel_var;        /* with a flow: 0 = off; > 0 = the per-event
+                                     relative variance of the VEGAS proposal
+                                     on the same frozen grid.  The first
+                                     iteration samples the flow; if its
+                                     per-event relative variance
+                                     (N - 1) sigma_1^2 / I_1^2 exceeds this
+                                     value, that iteration is kept (it is an
+                                     unbiased estimate) and every later
+                                     iteration samples the VEGAS proposal on
+                                     the frozen grid instead (plain VEGAS as
+                                     the fallback of the learned proposal) */
 } mf_integrate_opts;
 
 typedef struct mf_result_s {
@@ -239,6 +252,16 @@ typedef struct mf_result_s {
                                the call's stream */
   double* iter_integral;    /* host, length >= n_iter, or NULL */
   double* iter_error;       /* host, length >= n_iter, or NULL */
+  int32_t fallback_iter;    /* with a flow and fallback_rel_var > 0: index of
+                               the first iteration that sampled VEGAS after
+                               the fallback, -1 if the flow was kept (also -1
+                               without a flow) */
+  double flow_rel_var;      /* per-event relative variance of the first flow
+                               iteration when the fallback test ran, else -1 */
+  double* iter_seconds;     /* host, length >= n_iter, or NULL: with
+                               target_rel_err > 0, wall seconds from the start
+                               of the call to the end of each iteration (the
+                               call waits for every iteration then); else 0 */
 } mf_result;
 
 /* VEGAS integration (Lepage 1978) of the integrand: per iteration, events

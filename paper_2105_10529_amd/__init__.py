@@ -68,6 +68,7 @@ class _IntegrateOpts(ctypes.Structure):
         ("flow_mix", ctypes.c_double),
         ("prior", ctypes.c_void_p),
         ("obs", ctypes.c_void_p),
+        ("fallback_rel_var", ctypes.c_double),
     ]
 
 
@@ -81,6 +82,7 @@ class _Observables(ctypes.Structure):
         ("lo", ctypes.c_double * N_OBS),
         ("hi", ctypes.c_double * N_OBS),
         ("sums", ctypes.c_void_p),
+        ("sigma", ctypes.c_void_p),
     ]
 
 
@@ -135,6 +137,9 @@ class _Result(ctypes.Structure):
         ("kernel_seconds", ctypes.c_double),
         ("iter_integral", ctypes.c_void_p),
         ("iter_error", ctypes.c_void_p),
+        ("fallback_iter", ctypes.c_int32),
+        ("flow_rel_var", ctypes.c_double),
+        ("iter_seconds", ctypes.c_void_p),
     ]
 
 
@@ -280,6 +285,9 @@ class IntegrationResult:
     iter_integral: np.ndarray = field(default_factory=lambda: np.zeros(0))
     iter_error: np.ndarray = field(default_factory=lambda: np.zeros(0))
     observables: dict | None = None  # see Process.integrate(observables=...)
+    fallback_iter: int = -1          # first iteration that sampled VEGAS after a flow fallback, -1 none
+    flow_rel_var: float = -1.0       # per-event relative variance of the flow's first iteration (fallback test)
+    iter_seconds: np.ndarray = field(default_factory=lambda: np.zeros(0))  # wall time at each iteration's end
 
 
 class Process:
@@ -341,24 +349,30 @@ class Process:
     def integrate(self, n_iter: int, n_events: int, target_rel_err: float = 0.0, warmup: int = 0, adapt: bool = True,
                   iter_offset: int = 0, edges_in=None, edges_out=None, stream=None,
                   flow: "Flow | None" = None, flow_mix: float = 0.0,
-                  prior: "IntegrationResult | None" = None, observables: dict | None = None) -> IntegrationResult:
+                  prior: "IntegrationResult | None" = None, observables: dict | None = None,
+                  fallback_rel_var: float = 0.0) -> IntegrationResult:
         """VEGAS integration entirely on the device -- mf_integrate (flow: learned proposal, frozen grid;
-        prior: an earlier estimate combined with the new iterations; observables: {"nbins": n, "lo": (3,),
-        "hi": (3,)} fills histograms of OBSERVABLES, returned as result.observables with the raw per-bin
-        sums of w and w^2 ([3][nbins][2]), the bin edges, and the per-bin cross sections (pb) and their
-        Monte Carlo errors over the counted iterations)."""
+        fallback_rel_var: with a flow, the VEGAS proposal's per-event relative variance on that grid, above
+        which the flow's first iteration switches the rest to VEGAS; prior: an earlier estimate combined
+        with the new iterations; observables: {"nbins": n, "lo": (3,), "hi": (3,)} fills histograms of
+        OBSERVABLES, returned as result.observables with the raw per-bin sums of w and w^2
+        ([3][nbins][2]), the bin edges, and the library's per-bin cross sections (pb) and Monte Carlo
+        errors over the counted iterations)."""
         o = _IntegrateOpts()
-        ob = sums = None
+        ob = sums = sig = None
         if observables is not None:
             nb = int(observables["nbins"])
             sums = np.zeros((N_OBS, nb, 2))
+            sig = np.zeros((N_OBS, nb, 2))
             ob = _Observables()
             ob.nbins = nb
             for q in range(N_OBS):
                 ob.lo[q] = float(observables["lo"][q])
                 ob.hi[q] = float(observables["hi"][q])
             ob.sums = sums.ctypes.data
+            ob.sigma = sig.ctypes.data
             o.obs = ctypes.addressof(ob)
+        o.fallback_rel_var = fallback_rel_var
         o.flow = flow._h.value if flow is not None else None
         o.flow_mix = flow_mix
         pr = None
@@ -374,21 +388,23 @@ class Process:
         r = _Result()
         Ii = np.zeros(n_iter)
         Ie = np.zeros(n_iter)
+        Is = np.zeros(n_iter)
         r.iter_integral = Ii.ctypes.data
         r.iter_error = Ie.ctypes.data
+        r.iter_seconds = Is.ctypes.data
         _check(lib().mf_integrate(self._h, ctypes.byref(o), ctypes.byref(r)))
         k = r.n_iter_done
         res = IntegrationResult(r.integral, r.error, r.chi2_dof, k, r.n_events_total, r.n_nonzero, r.n_nonfinite,
                                 r.seconds, r.time_to_target, r.kernel_seconds, Ii[:k].copy(), Ie[:k].copy())
+        res.fallback_iter = r.fallback_iter
+        res.flow_rel_var = r.flow_rel_var
+        res.iter_seconds = Is[:k].copy()
         if sums is not None:
-            n = float(n_events) * max(k - warmup, 0)
-            mean = sums[:, :, 0] / max(n, 1.0)
-            var = (sums[:, :, 1] / max(n, 1.0) - mean ** 2) / max(n - 1.0, 1.0)
             res.observables = {
-                "names": OBSERVABLES, "sums": sums, "events": n,
+                "names": OBSERVABLES, "sums": sums, "events": float(n_events) * max(k - warmup, 0),
                 "edges": [np.linspace(observables["lo"][q], observables["hi"][q], sums.shape[1] + 1)
                           for q in range(N_OBS)],
-                "sigma_pb": mean, "error_pb": np.sqrt(np.maximum(var, 0.0))}
+                "sigma_pb": sig[:, :, 0].copy(), "error_pb": sig[:, :, 1].copy()}
         return res
 
     def weights(self, it: int, n: int, flow: "Flow | None" = None, want_y: bool = False, stream=None,

@@ -48,6 +48,7 @@ constexpr int64_t NOALLOC_MAX_POINTS = MF_NOALLOC_MAX_POINTS;
 static_assert(NOALLOC_MAX_POINTS % ((int64_t)MAX_BLOCKS * BLOCK) == 0, "list bound");
 static __device__ __align__(256) int scratch[MAX_BLOCKS + NOALLOC_MAX_POINTS];
 
+
 namespace mf {
 namespace {
 thread_local std::string g_err;
@@ -933,13 +934,21 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
     if (!(o->flow_mix >= 0.0 && o->flow_mix < 1.0)) return fail(MF_EINVAL, "flow_mix must be in [0,1)");
     if (mf_flow_ndim(o->flow) != d) return fail(MF_EINVAL, "flow dimension differs from the integrand's");
   }
+  if (!(o->fallback_rel_var >= 0.0) || !std::isfinite(o->fallback_rel_var))
+    return fail(MF_EINVAL, "fallback_rel_var must be finite and >= 0");
+  const bool can_fallback = o->flow && o->fallback_rel_var > 0.0;
   if (!p->L.fused || o->flow) {
     mf_status st = ensure_stage(p, o->n_events, s);
     if (st != MF_OK) return st;
-  } else {
+  }
+  if (p->L.fused && (!o->flow || can_fallback)) {
     mf_status st = ensure_select(p, o->n_events, s);
     if (st != MF_OK) return st;
   }
+  // the proposal of the current iteration: the flow until a fallback
+  mf_flow* flow = o->flow;
+  int fallback_iter = -1;
+  double flow_rv = -1.0;
   // observable histograms: validation and buffers
   ObsSpec ospec{};
   const int OW = o->obs ? N_OBS * o->obs->nbins * 2 : 0;  // histogram row width
@@ -989,9 +998,9 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   for (int it = 0; it < o->n_iter; ++it) {
     const uint64_t iter = o->iter_offset + (uint64_t)it;
     HIP_TRY(hipEventRecord(ev[2 * it], s));
-    if (o->flow) {
+    if (flow) {
       const int64_t N = o->n_events;
-      mf_status sst = stage_sample(p, o->flow, o->flow_mix, iter, N, nullptr, s);
+      mf_status sst = stage_sample(p, flow, o->flow_mix, iter, N, nullptr, s);
       if (sst != MF_OK) return sst;
       sst = run_integrand(p, p->d_sx, N, p->d_sw, s);
       if (sst != MF_OK) return sst;
@@ -1030,10 +1039,28 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
     st = check_stream_launch("k_finalize");
     if (st != MF_OK) return st;
     done = it + 1;
-    if (o->target_rel_err > 0.0) {
+    const bool test_fallback = can_fallback && it == 0;
+    if (o->target_rel_err > 0.0 || test_fallback) {
       HIP_TRY(hipMemcpyAsync(rec.data() + (size_t)REC * it, p->d_rec + (size_t)REC * it, sizeof(double) * REC,
                              hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (r->iter_seconds)
+      r->iter_seconds[it] = o->target_rel_err > 0.0
+                                ? std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count()
+                                : 0.0;
+    if (test_fallback) {
+      // per-event relative variance of the flow's first iteration against
+      // the VEGAS proposal's on the same frozen grid
+      const double* q = rec.data() + (size_t)REC * it;
+      const double n1 = (double)(o->n_events - 1);
+      flow_rv = q[0] != 0.0 ? n1 * q[1] * q[1] / (q[0] * q[0]) : INFINITY;
+      if (!(flow_rv <= o->fallback_rel_var)) {
+        flow = nullptr;
+        fallback_iter = it + 1;
+      }
+    }
+    if (o->target_rel_err > 0.0) {
       const double* q = rec.data() + (size_t)REC * it;
       if (it >= o->warmup_iters_discarded && q[1] > 0.0) {
         sw += 1.0 / (q[1] * q[1]);
@@ -1095,12 +1122,24 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
     ksec += 1e-3 * ms;
   }
   r->kernel_seconds = ksec;
+  r->fallback_iter = fallback_iter < done ? fallback_iter : -1;
+  r->flow_rel_var = flow_rv;
   for (int it = 0; it < done; ++it)
     if (rec[(size_t)REC * it + 6] != 0.0) return fail(MF_ERANGE, "grid refinement failed at iteration %d", it);
   if (o->obs) {
     HIP_TRY(hipMemcpyAsync(o->obs->sums, p->d_obs + (size_t)(MAX_BLOCKS + RED_ROWS) * OW, sizeof(double) * OW,
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (o->obs->sigma) {
+      // per-bin cross section and Monte Carlo error over the counted events
+      const double M = (double)o->n_events * (double)std::max(done - o->warmup_iters_discarded, 0);
+      for (int b = 0; b < OW / 2; ++b) {
+        const double mean = M > 0.0 ? o->obs->sums[2 * b] / M : 0.0;
+        const double var = M > 1.0 ? (o->obs->sums[2 * b + 1] / M - mean * mean) / (M - 1.0) : 0.0;
+        o->obs->sigma[2 * b] = mean;
+        o->obs->sigma[2 * b + 1] = std::sqrt(std::max(var, 0.0));
+      }
+    }
   }
   // the integrand never returns a non-finite value, so under a learned
   // proposal a non-finite weight comes from the proposal's density: the
@@ -1256,6 +1295,8 @@ mf_status mf_flow_train_online(mf_process* p, mf_flow* flow, const mf_flow_onlin
     est->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     est->time_to_target = time_to_target;
     est->kernel_seconds = 0.0;
+    est->fallback_iter = -1;
+    est->flow_rel_var = -1.0;
     for (size_t j = 0; j < combo.I.size(); ++j) {
       if (est->iter_integral) est->iter_integral[j] = combo.I[j];
       if (est->iter_error) est->iter_error[j] = combo.E[j];

@@ -117,6 +117,45 @@ def test_vegas_iteration_matches_oracle_exactly(ng, n, precision):
     assert np.max(np.abs(out.cpu().numpy() - ref_edges)) < (1e-10 if precision == "fp64" else 1e-5)
 
 
+_FULL_GEOMETRY_ORACLE = {}
+
+
+def _oracle_iteration(ng, n, grid_seed, iteration, seed):
+    key = (ng, n, grid_seed, iteration, seed)
+    if key not in _FULL_GEOMETRY_ORACLE:
+        d = si.ndim(ng)
+        _FULL_GEOMETRY_ORACLE[key] = _oracle(ng).vegas_iteration(si.random_grid(d, 50, seed=grid_seed), iteration, n,
+                                                                 seed, purpose=0)
+    return _FULL_GEOMETRY_ORACLE[key]
+
+
+@pytest.mark.parametrize("ng,n,precision", [(1, 1_100_000, "fp64"), (2, 600_000, "fp32"), (2, 600_000, "fp64")])
+def test_vegas_iteration_full_geometry_matches_oracle(ng, n, precision):
+    """One iteration in the launch geometry of the full-size runs: 2048 blocks
+    of 256 threads, each block looping over two or three 256-event chunks
+    (2048 x 256 = 524288 events per pass, so 600000 and 1100000 events leave
+    a ragged last pass).  That carried path -- per-wave LDS accumulators and
+    histograms and the per-block lists of kept events persisting across
+    chunks -- must give the oracle's iteration: FP64 to rounding (1e-12 on the
+    estimate, 1e-10 on the refined edges, the same count of non-zero events),
+    FP32 amplitudes within 1e-5.  g g -> t t~ g g in FP64 runs the staged
+    iteration (points, integrand, accumulation)."""
+    fp64 = precision == "fp64"
+    p = _proc(ng, precision)
+    d = si.ndim(ng)
+    print(f"full geometry ng={ng} n={n} {precision}", flush=True)
+    edges = torch.from_numpy(si.random_grid(d, 50, seed=15)).to("cuda")
+    out = torch.empty_like(edges)
+    r = p.integrate(1, n, adapt=True, iter_offset=5, edges_in=edges, edges_out=out)
+    S1, S2, hist, nnz, nbad = _oracle_iteration(ng, n, 15, 5, p.cfg.seed)
+    I, s = oracle.iteration_estimate(S1, S2, n)
+    assert abs(r.iter_integral[0] / I - 1) < (1e-12 if fp64 else 1e-5), (r.iter_integral[0], I)
+    assert abs(r.iter_error[0] / s - 1) < (1e-9 if fp64 else 1e-4)
+    assert r.n_nonzero == nnz and r.n_nonfinite == nbad == 0
+    ref_edges = oracle.vegas_refine(si.random_grid(d, 50, seed=15), hist, 1.5)
+    assert np.max(np.abs(out.cpu().numpy() - ref_edges)) < (1e-10 if fp64 else 1e-5)
+
+
 def test_refine_matches_oracle():
     d, nb = 7, 50
     rng = np.random.default_rng(9)
@@ -200,14 +239,46 @@ def test_grad_estimator_matches_oracle_sum():
         assert abs(vals[1 + k] - ref) <= 1e-10 * max(abs(ref), np.abs(dw).max() / n), k
 
 
+def test_mt_derivative_per_event_matches_central_differences():
+    """Per event, at explicit points: d w / d m_t from the forward-mode kernel
+    against (w(m_t + h) - w(m_t - h)) / 2h with h = 0.05 GeV, both in FP64.
+    The gluon momenta and the cuts do not depend on m_t (the gluons are
+    emitted before the top pair is split), so each event's weight is a
+    smooth function of m_t except through the top-pair threshold, where
+    w ~ beta = sqrt(1 - 4 m_t^2 / M_tt^2) has no Taylor expansion; events
+    with M_tt > 2 (m_t + 10 GeV) (those still above threshold at
+    m_t + 10 GeV) have a central-difference error of order (h / 20 GeV)^2
+    < 1e-5, checked at 1e-4."""
+    d = 7
+    x = _points(20000, d, 55)
+    u = to_dev_soa(x)
+    h = 0.05
+    w0, dw = _proc(1).integrand_grad(u)
+    dw = dw[0].cpu().numpy()
+    wp = mf.Process(mf.Config(process="gg>ttxg", m_t=MT + h)).integrand(u).cpu().numpy()
+    wm = mf.Process(mf.Config(process="gg>ttxg", m_t=MT - h)).integrand(u).cpu().numpy()
+    far = mf.Process(mf.Config(process="gg>ttxg", m_t=MT + 10.0)).integrand(u).cpu().numpy() != 0.0
+    fd = (wp - wm) / (2 * h)
+    assert far.sum() > 5000
+    err = np.abs(fd[far] - dw[far])
+    assert np.all(err <= 1e-4 * np.abs(dw[far]) + 1e-10 * np.abs(dw[far]).max()), float(
+        np.max(err / np.abs(dw[far])))
+
+
 def test_derivatives_match_central_differences_on_the_same_events():
     """dsigma/dm_t and dsigma/dtheta from the pathwise estimator against
     central differences of sigma computed from the same Philox events on the
     same frozen grid: h = 0.05 GeV for m_t, relative 1e-4 for the PDF
     parameters (their derivative is exact in the kinematics, so only O(h^2)
-    remains); for m_t the events whose gluons cross a cut boundary between
-    m_t - h and m_t + h add a boundary term the pathwise estimator does not
-    carry, bounded here by 1%."""
+    remains, checked at 1e-6).  For m_t the cuts cannot move (they act on
+    the gluons, whose momenta do not depend on m_t) and the threshold adds no
+    boundary term (the weight vanishes there like beta); the two estimates
+    differ only through the events within a few h of the top-pair threshold,
+    where w ~ beta has no Taylor expansion and the central difference of
+    each such event differs from its derivative by O(1) (the per-event test
+    above covers the events away from it).  Their share of the estimate is of
+    order sqrt(h / m_t) times the fraction of the cross section near
+    threshold; the bound is 1e-3."""
     p = _proc(1)
     p.integrate(3, 200_000, adapt=True)
     edges = torch.empty((7, 51), dtype=torch.float64, device="cuda")
@@ -221,7 +292,9 @@ def test_derivatives_match_central_differences_on_the_same_events():
 
     h = 0.05
     fd = (sigma(m_t=MT + h) - sigma(m_t=MT - h)) / (2 * h)
-    assert abs(fd - vals[1]) < 1e-2 * abs(vals[1]), (fd, vals[1], errs[1])
+    assert abs(fd - vals[1]) < 1e-3 * abs(vals[1]), (fd, vals[1], errs[1])
+    print(f"d sigma / d m_t: pathwise {vals[1]:.8g}, central difference {fd:.8g}, "
+          f"relative difference {abs(fd / vals[1] - 1):.2e}")
     base = list(mf.DEFAULT_PDF)
     # out[2 + t] is d sigma / d theta_t; theta_1..4 = a_g, b_g, c_g, d_g = pdf_params[1..4]
     for k, idx in ((3, 1), (4, 2), (5, 3), (6, 4)):
