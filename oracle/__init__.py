@@ -52,6 +52,9 @@ def lib():
         L.or_vegas_map.restype = d
         L.or_vegas_refine.argtypes = [P, P, i, i, d]
         L.or_set_colour.argtypes = [i, i, P]
+        L.or_set_colour_qq.argtypes = [P, P]
+        L.or_me_qq.argtypes = [i, P, d, i]
+        L.or_me_qq.restype = d
         L.or_state_create.argtypes = [P]
         L.or_state_create.restype = i
         L.or_state_destroy.argtypes = [i]
@@ -75,6 +78,7 @@ def lib():
         L.or_vegas_iteration_gauss.argtypes = [i, d, P, i, u64, i64, u64, u64, P, P]
         _lib = L
         _install_colour()
+        _install_colour_qq()
     return _lib
 
 
@@ -100,6 +104,15 @@ def _install_colour(ms=(2, 3, 4)):
         _installed.add(m)
 
 
+def _install_colour_qq():
+    from . import colour
+
+    CC = colour.two_line_colour_matrix()
+    re_ = _c(CC.real)
+    im_ = _c(CC.imag)
+    _lib.or_set_colour_qq(_ptr(re_), _ptr(im_))
+
+
 # ------------------------------------------------------------------ constants
 ALPHA_S = 0.118
 GEV2_TO_PB = 3.893793721e8
@@ -111,7 +124,9 @@ PDF_PARAMS = {
     "ubar": (0.2, -0.2, -0.05, 7.0, 0.3),
 }
 FLAVOURS = ("g", "u", "d", "ubar")
-CHANNELS = {"gg": 0, "uu~": 1, "dd~": 2}
+# gg; u u~ and d d~ (both beam assignments); q g = q g -> t t~ q and
+# q~ g -> t t~ q~ for q = u, d (both beam assignments; needs n_g = 1)
+CHANNELS = {"gg": 0, "uu~": 1, "dd~": 2, "qg": 3}
 
 
 class _Cfg(ctypes.Structure):
@@ -150,8 +165,7 @@ class Config:
 
     @property
     def ndim(self) -> int:
-        ng = self.n_g if self.channel == "gg" else 0
-        return 3 * (ng + 2) - 2
+        return 3 * (self.n_g + 2) - 2
 
 
 class Oracle:
@@ -204,7 +218,7 @@ class Oracle:
     def integrand_momenta(self, x: np.ndarray):
         x = _c(x)
         n = x.shape[0]
-        ng = self.cfg.n_g if self.cfg.channel == "gg" else 0
+        ng = self.cfg.n_g
         w = np.zeros(n)
         mom = np.zeros((n, ng + 4, 4))
         lib().or_integrand_mom(self._h, n, _ptr(x), _ptr(w), _ptr(mom))
@@ -345,6 +359,13 @@ def me_gg(m: int, mom: np.ndarray, m_t: float, per_helicity: bool = False):
 
 def me_qqbar(mom: np.ndarray, m_t: float) -> float:
     return lib().or_me_qqbar(_ptr(_c(mom)), m_t)
+
+
+def me_qq(kind: str, mom: np.ndarray, m_t: float, ward: bool = False) -> float:
+    """Colour/helicity-summed |M|^2 (g = 1) with two quark lines: kind "qqg" =
+    q(p1) q~(p2) -> t(p3) t~(p4) g(p5), "qgq" = q(p1) g(p2) -> t(p3) t~(p4) q(p5);
+    mom = (p1, ..., p5); ward: the gluon's polarisation replaced by its momentum."""
+    return lib().or_me_qq({"qqg": 0, "qgq": 1}[kind], _ptr(_c(mom)), m_t, int(ward))
 
 
 def partial_amplitudes(m: int, k: np.ndarray, incoming, pt, ptb, m_t: float, hel: int, ward: int = -1):

@@ -230,3 +230,30 @@ def dressed_me(m: int, mom: np.ndarray, mt: float, helicities=None):
         per.append(float(np.sum(np.abs(amp) ** 2)))
         total += per[-1]
     return total if helicities is None else np.array(per)
+
+
+@functools.lru_cache(maxsize=None)
+def two_line_colour_tensors() -> np.ndarray:
+    """Colour tensors C_d[a, L_row, L_col, T_row, T_col] of the five diagrams of
+    a light quark line and the top line joined by one gluon, with one more
+    external gluon of adjoint index a (see oracle.cpp, two quark lines):
+      d = 0: (t^b t^a)_L (t^b)_T     d = 1: (t^a t^b)_L (t^b)_T
+      d = 2: (t^c)_L (t^a t^c)_T     d = 3: (t^c)_L (t^c t^a)_T
+      d = 4: f^{abc} (t^b)_L (t^c)_T
+    summed over the internal adjoint indices, shape (5, 8, 3, 3, 3, 3)."""
+    t = generators()
+    f = structure_constants()
+    C = np.zeros((5, 8, 3, 3, 3, 3), dtype=np.complex128)
+    C[0] = np.einsum("bij,ajk,blm->aiklm", t, t, t)
+    C[1] = np.einsum("aij,bjk,blm->aiklm", t, t, t)
+    C[2] = np.einsum("cik,alj,cjm->aiklm", t, t, t)
+    C[3] = np.einsum("cik,clj,ajm->aiklm", t, t, t)
+    C[4] = np.einsum("abc,bik,clm->aiklm", f, t, t)
+    return C
+
+
+@functools.lru_cache(maxsize=None)
+def two_line_colour_matrix() -> np.ndarray:
+    """CC[d, d'] = sum over every colour index of C_d C_d'^* (complex 5 x 5)."""
+    C = two_line_colour_tensors().reshape(5, -1)
+    return np.ascontiguousarray(C @ np.conj(C).T)

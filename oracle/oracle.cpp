@@ -471,6 +471,165 @@ R me_qqbar(const P4<R>& p1, const P4<R>& p2, const P4<R>& p3, const P4<R>& p4, R
   return R(2.0) * total;
 }
 
+// ------------------------------------------- two quark lines and one gluon
+// Tree-level |M|^2 of q(p1) q~(p2) -> t(p3) t~(p4) g(p5) and of
+// q(p1) g(p2) -> t(p3) t~(p4) q(p5), written diagram by diagram from the
+// QCD Feynman rules in Feynman gauge: quark-gluon vertex i g gamma^mu t^a,
+// fermion propagator i (pslash + m)/(p^2 - m^2), gluon propagator
+// -i g_{mu nu} delta^{ab} / k^2, three-gluon vertex
+// g f^{abc} [g^{mu nu}(k - p)^rho + g^{nu rho}(p - q)^mu + g^{rho mu}(q - k)^nu]
+// for (a, mu, k), (b, nu, p), (c, rho, q) with all momenta incoming;
+// coupling g = 1, light quarks massless.  Each process has five diagrams d
+// with a Lorentz part K_d (its factors of i included) and a colour tensor
+// C_d over (light-line colours, top-line colours, adjoint index of the
+// external gluon):
+//   d = 0: (t^b t^a)_{L}(t^b)_{T}   d = 1: (t^a t^b)_{L}(t^b)_{T}
+//   d = 2: (t^c)_{L}(t^a t^c)_{T}   d = 3: (t^c)_{L}(t^c t^a)_{T}
+//   d = 4: f^{abc}(t^b)_{L}(t^c)_{T}
+// with L the light line (row index: the antiquark or the outgoing quark,
+// column index: the incoming quark) and T the top line (row: top, column:
+// antitop).  The colour- and helicity-summed |M|^2 is
+//   sum_h sum_{d,d'} K_d K_d'^* CC[d][d'],  CC[d][d'] = sum_colours C_d C_d'^*,
+// with CC supplied by the caller (explicit Gell-Mann matrices).
+static std::vector<double> g_cc_re, g_cc_im;  // [5][5]
+
+// J^mu = row gamma^mu col (contravariant components)
+template <class R> inline C4<R> vec_current(const C4<R>& row, const C4<R>& col) {
+  C4<R> J;
+  for (int mu = 0; mu < 4; ++mu) {
+    C4<R> e = c4zero<R>();
+    e.c[mu] = Cx<R>(R(METRIC[mu]));  // slash(e) = gamma^mu
+    J.c[mu] = rowvec(rowmat(row, slash(e)), col);
+  }
+  return J;
+}
+template <class R> inline P4<R> padd(const P4<R>& a, const P4<R>& b) { return P4<R>{a.e + b.e, a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class R> inline P4<R> psub(const P4<R>& a, const P4<R>& b) { return P4<R>{a.e - b.e, a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class R> inline P4<R> pneg(const P4<R>& a) { return P4<R>{-a.e, -a.x, -a.y, -a.z}; }
+// (pslash + m) as a matrix
+template <class R> inline M4<R> pslash_m(const P4<R>& p, R m) {
+  M4<R> s = slash(fromP4(p));
+  for (int i = 0; i < 4; ++i) s.a[i][i] = s.a[i][i] + Cx<R>(m);
+  return s;
+}
+// three-gluon vertex contracted with the polarisations/currents of its legs:
+// (a, rho, k, ea), (b, nu, p, eb), (c, mu, q, ec), all momenta incoming
+template <class R>
+inline Cx<R> v3g(const C4<R>& ea, const P4<R>& k, const C4<R>& eb, const P4<R>& p, const C4<R>& ec, const P4<R>& q) {
+  return cdot(ea, eb) * cdot(fromP4(psub(k, p)), ec) + cdot(eb, ec) * cdot(fromP4(psub(p, q)), ea) +
+         cdot(ec, ea) * cdot(fromP4(psub(q, k)), eb);
+}
+
+template <class R> inline R colour_contract(const Cx<R>* K) {
+  R t = R(0.0);
+  for (int d = 0; d < 5; ++d)
+    for (int e = 0; e < 5; ++e) {
+      Cx<R> z = K[d] * conj(K[e]);  // K_d K_e^*
+      t = t + z.re * R(g_cc_re[5 * d + e]) - z.im * R(g_cc_im[5 * d + e]);
+    }
+  return t;
+}
+
+// q(p1) q~(p2) -> t(p3) t~(p4) g(p5): colour- and helicity-summed |M|^2, g = 1.
+// ward = true replaces the gluon's polarisation by its momentum (the
+// amplitude must then vanish for every colour).
+template <class R>
+R me_qqbar_g(const P4<R>& p1, const P4<R>& p2, const P4<R>& p3, const P4<R>& p4, const P4<R>& p5, R mt,
+             bool ward = false) {
+  const R zero(0.0);
+  const P4<R> q12 = padd(p1, p2), q34 = padd(p3, p4);
+  const R s12 = mdot(q12, q12), s34 = mdot(q34, q34);
+  const P4<R> a1 = psub(p1, p5), a2 = psub(p5, p2), a3 = padd(p3, p5), a4 = pneg(padd(p4, p5));
+  const R d1 = mdot(a1, a1), d2 = mdot(a2, a2), d3 = mdot(a3, a3) - mt * mt, d4 = mdot(a4, a4) - mt * mt;
+  const Cx<R> mi(R(0.0), R(-1.0));  // -i of the diagrams with two fermion propagators' worth of i
+  R total = R(0.0);
+  for (int h = 0; h < 32; ++h) {
+    const int l1 = (h & 16) ? 1 : -1, l2 = (h & 8) ? 1 : -1, l3 = (h & 4) ? 1 : -1, l4 = (h & 2) ? 1 : -1,
+              l5 = (h & 1) ? 1 : -1;
+    const C4<R> u1 = uspinor(p1, zero, l1);
+    const C4<R> vb2 = dbar(vspinor(p2, zero, l2));
+    const C4<R> ub3 = dbar(uspinor(p3, mt, l3));
+    const C4<R> v4 = vspinor(p4, mt, l4);
+    const C4<R> e5 = ward ? fromP4(p5) : polvec(p5, l5, true);  // eps* of the outgoing gluon
+    const M4<R> E5 = slash(e5);
+    const C4<R> J12 = vec_current(vb2, u1), J34 = vec_current(ub3, v4);
+    Cx<R> K[5];
+    // d0: emission from the incoming quark
+    {
+      const C4<R> L = vec_current(vb2, matvec(slash(fromP4(a1)), matvec(E5, u1)));
+      K[0] = mi * scale(cdot(L, J34), R(1.0) / (d1 * s34));
+    }
+    // d1: emission from the incoming antiquark
+    {
+      const C4<R> L = vec_current(rowmat(rowmat(vb2, E5), slash(fromP4(a2))), u1);
+      K[1] = mi * scale(cdot(L, J34), R(1.0) / (d2 * s34));
+    }
+    // d2: emission from the top
+    {
+      const C4<R> T = vec_current(rowmat(rowmat(ub3, E5), pslash_m(a3, mt)), v4);
+      K[2] = mi * scale(cdot(T, J12), R(1.0) / (d3 * s12));
+    }
+    // d3: emission from the antitop
+    {
+      const C4<R> T = vec_current(ub3, matvec(pslash_m(a4, mt), matvec(E5, v4)));
+      K[3] = mi * scale(cdot(T, J12), R(1.0) / (d4 * s12));
+    }
+    // d4: three-gluon vertex: (a, -p5, e5), (b, p1 + p2, J12), (c, -(p3 + p4), J34)
+    K[4] = scale(v3g(e5, pneg(p5), J12, q12, J34, pneg(q34)), R(1.0) / (s12 * s34));
+    total = total + colour_contract(K);
+  }
+  return total;
+}
+
+// q(p1) g(p2) -> t(p3) t~(p4) q(p5): colour- and helicity-summed |M|^2, g = 1.
+template <class R>
+R me_qg_q(const P4<R>& p1, const P4<R>& p2, const P4<R>& p3, const P4<R>& p4, const P4<R>& p5, R mt,
+          bool ward = false) {
+  const R zero(0.0);
+  const P4<R> q12 = padd(p1, p2), q34 = padd(p3, p4), q15 = psub(p1, p5);
+  const R s12 = mdot(q12, q12), s34 = mdot(q34, q34), t15 = mdot(q15, q15);
+  const P4<R> a2 = psub(p5, p2), a3 = psub(p3, p2), a4 = psub(p2, p4);
+  const R d2 = mdot(a2, a2), d3 = mdot(a3, a3) - mt * mt, d4 = mdot(a4, a4) - mt * mt;
+  const Cx<R> mi(R(0.0), R(-1.0));
+  R total = R(0.0);
+  for (int h = 0; h < 32; ++h) {
+    const int l1 = (h & 16) ? 1 : -1, l2 = (h & 8) ? 1 : -1, l3 = (h & 4) ? 1 : -1, l4 = (h & 2) ? 1 : -1,
+              l5 = (h & 1) ? 1 : -1;
+    const C4<R> u1 = uspinor(p1, zero, l1);
+    const C4<R> e2 = ward ? fromP4(p2) : polvec(p2, l2, false);  // eps of the incoming gluon
+    const M4<R> E2 = slash(e2);
+    const C4<R> ub3 = dbar(uspinor(p3, mt, l3));
+    const C4<R> v4 = vspinor(p4, mt, l4);
+    const C4<R> ub5 = dbar(uspinor(p5, zero, l5));
+    const C4<R> J15 = vec_current(ub5, u1), J34 = vec_current(ub3, v4);
+    Cx<R> K[5];
+    // d0: s-channel quark (the gluon absorbed first)
+    {
+      const C4<R> L = vec_current(ub5, matvec(slash(fromP4(q12)), matvec(E2, u1)));
+      K[0] = mi * scale(cdot(L, J34), R(1.0) / (s12 * s34));
+    }
+    // d1: u-channel quark (the gluon absorbed after the emission of the top pair)
+    {
+      const C4<R> L = vec_current(rowmat(rowmat(ub5, E2), slash(fromP4(a2))), u1);
+      K[1] = mi * scale(cdot(L, J34), R(1.0) / (d2 * s34));
+    }
+    // d2: t-channel gluon, the incoming gluon attached next to the top
+    {
+      const C4<R> T = vec_current(rowmat(rowmat(ub3, E2), pslash_m(a3, mt)), v4);
+      K[2] = mi * scale(cdot(T, J15), R(1.0) / (d3 * t15));
+    }
+    // d3: t-channel gluon, the incoming gluon attached next to the antitop
+    {
+      const C4<R> T = vec_current(ub3, matvec(pslash_m(a4, mt), matvec(E2, v4)));
+      K[3] = mi * scale(cdot(T, J15), R(1.0) / (d4 * t15));
+    }
+    // d4: three-gluon vertex: (a, p2, e2), (b, p1 - p5, J15), (c, -(p3 + p4), J34)
+    K[4] = scale(v3g(e2, p2, J15, q15, J34, pneg(q34)), R(1.0) / (t15 * s34));
+    total = total + colour_contract(K);
+  }
+  return total;
+}
+
 // ----------------------------------------------------------------- Philox
 static inline void mulhilo(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
   unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
@@ -778,7 +937,8 @@ static const double GEV2_TO_PB = 3.893793721e8;
 template <class R>
 static R integrand_T(const State& S, const double* x, R mt, int dir, double* mom_out, int* pass_out) {
   const or_cfg& c = S.cfg;
-  const int ng = (c.channel == 0) ? c.n_g : 0;
+  // gluons (g g channel) or one light parton (quark channels with n_g = 1)
+  const int ng = c.n_g;
   const int n = ng + 2;
   if (pass_out) *pass_out = 0;
   double s = c.sqrt_s * c.sqrt_s;
@@ -844,6 +1004,36 @@ static R integrand_T(const State& S, const double* x, R mt, int dir, double* mom
       f2 = pdf_val(S, 0, x2, mu);
     }
     lum = f1 * f2 / R(x1 * x2);
+  } else if (ng == 1) {
+    // quark channels with one more parton: the light parton is fs[0], the
+    // top pair fs[1], fs[2]
+    auto pdf = [&](int f, double x) -> R {
+      if constexpr (std::is_same<R, Dual>::value) return pdf_dual(S, f, x, mu, dir);
+      else return pdf_val(S, f, x, mu);
+    };
+    if (c.channel == 1 || c.channel == 2) {
+      // q q~ -> t t~ g, the quark from either beam
+      const int q = (c.channel == 1) ? 1 : 2;
+      R m12 = me_qqbar_g<R>(p1, p2, fs[1], fs[2], fs[0], mt);
+      R m21 = me_qqbar_g<R>(p2, p1, fs[1], fs[2], fs[0], mt);
+      R sc = R(gs2 * gs2 * gs2 / 36.0 / (x1 * x2));
+      me = R(1.0);
+      lum = (pdf(q, x1) * pdf(3, x2) * m12 + pdf(3, x1) * pdf(q, x2) * m21) * sc;
+    } else {
+      // q g -> t t~ q for q = u, d from either beam, and q~ g -> t t~ q~ for
+      // q~ = u~, d~ (equal PDFs): by charge conjugation |M(q~ g -> t t~ q~)|^2
+      // is |M(q g -> t t~ q)|^2 with the top and antitop momenta exchanged
+      R mq12 = me_qg_q<R>(p1, p2, fs[1], fs[2], fs[0], mt);
+      R mq21 = me_qg_q<R>(p2, p1, fs[1], fs[2], fs[0], mt);
+      R ma12 = me_qg_q<R>(p1, p2, fs[2], fs[1], fs[0], mt);
+      R ma21 = me_qg_q<R>(p2, p1, fs[2], fs[1], fs[0], mt);
+      R g1 = pdf(0, x1), g2 = pdf(0, x2);
+      R qs1 = pdf(1, x1) + pdf(2, x1), qs2 = pdf(1, x2) + pdf(2, x2);
+      R as1 = R(2.0) * pdf(3, x1), as2 = R(2.0) * pdf(3, x2);
+      R sc = R(gs2 * gs2 * gs2 / 96.0 / (x1 * x2));
+      me = R(1.0);
+      lum = (qs1 * g2 * mq12 + g1 * qs2 * mq21 + as1 * g2 * ma12 + g1 * as2 * ma21) * sc;
+    }
   } else {
     int q = (c.channel == 1) ? 1 : 2;
     R sum12 = me_qqbar<R>(p1, p2, fs[0], fs[1], mt);  // quark from beam 1
@@ -896,6 +1086,21 @@ double or_vegas_map(const double* edges, int d, int nb, const double* y, double*
 
 void or_vegas_refine(double* edges, const double* hist, int d, int nb, double alpha) {
   for (int j = 0; j < d; ++j) refine_dim(edges + (size_t)j * (nb + 1), hist + (size_t)j * nb, nb, alpha);
+}
+
+void or_set_colour_qq(const double* re, const double* im) {
+  g_cc_re.assign(re, re + 25);
+  g_cc_im.assign(im, im + 25);
+}
+
+// The two-quark-line matrix elements at explicit physical momenta
+// mom = (p1, p2, p3, p4, p5) [5][4]; kind 0: q q~ -> t t~ g, 1: q g -> t t~ q;
+// ward = 1: the gluon's polarisation replaced by its momentum.
+double or_me_qq(int kind, const double* mom, double mt, int ward) {
+  P4<double> p[5];
+  for (int i = 0; i < 5; ++i) p[i] = P4<double>{mom[4 * i], mom[4 * i + 1], mom[4 * i + 2], mom[4 * i + 3]};
+  return kind == 0 ? me_qqbar_g<double>(p[0], p[1], p[2], p[3], p[4], mt, ward != 0)
+                   : me_qg_q<double>(p[0], p[1], p[2], p[3], p[4], mt, ward != 0);
 }
 
 void or_set_colour(int m, int nf, const double* C) {
@@ -1051,7 +1256,7 @@ double or_me_qqbar(const double* mom, double mt) {
 // w(x) for x [n][d]; pass flags optional.
 void or_integrand(int h, int64_t n, const double* x, double* w, int* pass, int nthreads) {
   const State& S = *g_states[h];
-  const int ng = (S.cfg.channel == 0) ? S.cfg.n_g : 0;
+  const int ng = S.cfg.n_g;
   const int d = 3 * (ng + 2) - 2;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -1064,7 +1269,7 @@ void or_integrand(int h, int64_t n, const double* x, double* w, int* pass, int n
 // Integrand and its derivative in direction dir (1: m_t, 2..9: theta).
 void or_integrand_grad(int h, int64_t n, const double* x, int dir, double* w, double* dw, int nthreads) {
   const State& S = *g_states[h];
-  const int ng = (S.cfg.channel == 0) ? S.cfg.n_g : 0;
+  const int ng = S.cfg.n_g;
   const int d = 3 * (ng + 2) - 2;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -1081,7 +1286,7 @@ void or_integrand_grad(int h, int64_t n, const double* x, int dir, double* w, do
 // Integrand with momenta output: mom [n][n_ext][4] (p1,p2,t,tb,gluons).
 void or_integrand_mom(int h, int64_t n, const double* x, double* w, double* mom) {
   const State& S = *g_states[h];
-  const int ng = (S.cfg.channel == 0) ? S.cfg.n_g : 0;
+  const int ng = S.cfg.n_g;
   const int d = 3 * (ng + 2) - 2;
   const int next = ng + 4;
   for (int64_t e = 0; e < n; ++e) {
@@ -1097,7 +1302,7 @@ void or_integrand_mom(int h, int64_t n, const double* x, double* w, double* mom)
 void or_vegas_iteration(int h, const double* edges, int nb, uint64_t iter, int64_t ev0, int64_t n, uint64_t seed,
                         uint64_t purpose, double* out, double* hist, int64_t* counts, int nthreads) {
   const State& S = *g_states[h];
-  const int ng = (S.cfg.channel == 0) ? S.cfg.n_g : 0;
+  const int ng = S.cfg.n_g;
   const int d = 3 * (ng + 2) - 2;
   int nt = 1;
 #ifdef _OPENMP
