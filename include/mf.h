@@ -54,7 +54,12 @@ typedef enum {
   MF_DDX_TTX = 2,    /* d d~ -> t t~, both beam assignments  (4 dims)  */
   MF_GG_TTXG = 3,    /* g g -> t t~ g                        (7 dims)  */
   MF_GG_TTXGG = 4,   /* g g -> t t~ g g                      (10 dims) */
-  MF_GG_TTXGGG = 5   /* g g -> t t~ g g g                    (13 dims) */
+  MF_GG_TTXGGG = 5,  /* g g -> t t~ g g g                    (13 dims) */
+  MF_UUX_TTXG = 6,   /* u u~ -> t t~ g, both beam assignments (7 dims) */
+  MF_DDX_TTXG = 7,   /* d d~ -> t t~ g, both beam assignments (7 dims) */
+  MF_QG_TTXQ = 8     /* q g -> t t~ q and q~ g -> t t~ q~ for q = u, d,
+                        both beam assignments (7 dims); the cuts act on
+                        the final light quark as on a gluon */
 } mf_process_id;
 
 typedef enum {
@@ -99,6 +104,18 @@ typedef struct {
                               gluons), with the PDFs interpolated in x and Q
                               on the full knot grid (the derivative entry
                               points are then MF_ENOTSUP) */
+  int32_t colour_form;     /* colour quadratic form of g g -> t t~ g g (other
+                              processes: 0 only, else MF_ENOTSUP):
+                              0 = the default, 1 (the faster form in both
+                                  precisions);
+                              1 = in registers on the vector ALUs, next to
+                                  the amplitudes (FP32: one fused kernel per
+                                  VEGAS iteration; FP64: points, integrand
+                                  and accumulation kernels);
+                              2 = on the matrix cores: the partial amplitudes
+                                  are streamed to a handle-owned buffer and
+                                  Z = C A is formed with FP32 (FP64)
+                                  matrix-core products, then A . Z */
 } mf_config;
 
 typedef struct mf_process mf_process;
@@ -144,9 +161,10 @@ mf_status mf_integrand(mf_process* p, const double* u, int64_t n, double* w, voi
  * the per-block point lists in a fixed device array of the library
  * (16 MiB per device, held until the process ends) instead of the handle.
  * No device memory is allocated or freed.  At most MF_NOALLOC_MAX_POINTS
- * points per call (MF_EINVAL above); MF_ENOTSUP for g g -> t t~ g g g, whose
- * integrand runs as several kernels with a workspace; MF_EINVAL if the
- * current device is not the handle's.
+ * points per call (MF_EINVAL above); MF_ENOTSUP where the integrand runs as
+ * several kernels with a workspace (g g -> t t~ g g g, and g g -> t t~ g g
+ * with the matrix-core colour form); MF_EINVAL if the current device is not
+ * the handle's.
  * Every call on a device shares that device's array, so calls that overlap
  * on one device (different streams or host threads) race; calls ordered on
  * one stream do not.  Nothing in the array needs clearing between calls:

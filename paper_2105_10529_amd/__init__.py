@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmf.so")
 
 MF_OK, MF_EINVAL, MF_ERANGE, MF_ENOMEM, MF_EDEVICE, MF_ENOTSUP = range(6)
-PROCESSES = {"gg>ttx": 0, "uux>ttx": 1, "ddx>ttx": 2, "gg>ttxg": 3, "gg>ttxgg": 4, "gg>ttxggg": 5}
+PROCESSES = {"gg>ttx": 0, "uux>ttx": 1, "ddx>ttx": 2, "gg>ttxg": 3, "gg>ttxgg": 4, "gg>ttxggg": 5,
+             "uux>ttxg": 6, "ddx>ttxg": 7, "qg>ttxq": 8}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 NOALLOC_MAX_POINTS = 1 << 22  # MF_NOALLOC_MAX_POINTS of include/mf.h
 DEFAULT_PDF = (1.6, -0.2, -0.05, 5.0, 0.3,   # g
@@ -50,6 +51,7 @@ class _Config(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("helicity", ctypes.c_int32),
         ("dynamic_scale", ctypes.c_int32),
+        ("colour_form", ctypes.c_int32),
     ]
 
 
@@ -255,6 +257,7 @@ class Config:
     seed: int = 2105105290
     helicity: int = 0  # g g -> t t~ g g g: 0 sum, 1 one sampled state (x64), 2 + k only state k
     dynamic_scale: bool = False  # True: mu = H_T / 2 per event
+    colour_form: int = 0  # g g -> t t~ g g: 0 default, 1 vector ALUs in registers, 2 matrix cores
 
     def _c(self) -> _Config:
         c = _Config()
@@ -267,6 +270,7 @@ class Config:
         c.n_bins, c.alpha, c.seed = self.n_bins, self.alpha, self.seed
         c.helicity = self.helicity
         c.dynamic_scale = int(self.dynamic_scale)
+        c.colour_form = self.colour_form
         return c
 
 

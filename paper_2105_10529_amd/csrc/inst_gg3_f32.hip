@@ -42,8 +42,8 @@ hipError_t integrand(const DevCfg& c, const double* u, int64_t n, double* w, voi
     G3_TRY(hipMalloc(&ws->d_wpre, sizeof(double) * n));
     ws->cap_n = n;
   }
-  hipLaunchKernelGGL(k_g3_zero, dim3(1), dim3(1), 0, s, ws->d_count);
-  hipLaunchKernelGGL(k_g3_select, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, c, u, n, w,
+  hipLaunchKernelGGL(st::k_st_zero, dim3(1), dim3(1), 0, s, ws->d_count);
+  hipLaunchKernelGGL(st::k_st_select<NG>, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, c, u, n, w,
                      ws->d_wpre, ws->d_idx, ws->d_count);
   G3_TRY(hipGetLastError());
   int count = 0;

@@ -99,6 +99,31 @@ __device__ __forceinline__ void grad_event(const DevCfg& c, const double* x, dou
       const double* T = c.pdft + k * NXK;
       dw[1 + k] = r.r1.v * (hermite_x(T, r.t1) * f2 + f1 * hermite_x(T, r.t2));
     }
+  } else if constexpr (CH == 3) {
+    // w = r1 (u1 + d1) g2 + r2 g1 (u2 + d2) + r3 2 ub1 g2 + r4 g1 2 ub2
+    const double* G = c.pdfc;
+    const double *U = c.pdfc + NXK, *D = c.pdfc + 2 * NXK, *A = c.pdfc + 3 * NXK;
+    const double g1 = hermite_x(G, r.t1), g2 = hermite_x(G, r.t2);
+    const double q1 = hermite_x(U, r.t1) + hermite_x(D, r.t1), q2 = hermite_x(U, r.t2) + hermite_x(D, r.t2);
+    const double a1 = 2.0 * hermite_x(A, r.t1), a2 = 2.0 * hermite_x(A, r.t2);
+    if (c.mu_is_mt) {
+      const double* dG = c.pdfd;
+      const double *dU = c.pdfd + NXK, *dD = c.pdfd + 2 * NXK, *dA = c.pdfd + 3 * NXK;
+      const double dg1 = hermite_x(dG, r.t1), dg2 = hermite_x(dG, r.t2);
+      const double dq1 = hermite_x(dU, r.t1) + hermite_x(dD, r.t1), dq2 = hermite_x(dU, r.t2) + hermite_x(dD, r.t2);
+      const double da1 = 2.0 * hermite_x(dA, r.t1), da2 = 2.0 * hermite_x(dA, r.t2);
+      dw[0] += r.r1.v * (dq1 * g2 + q1 * dg2) + r.r2.v * (dg1 * q2 + g1 * dq2) + r.r3.v * (da1 * g2 + a1 * dg2) +
+               r.r4.v * (dg1 * a2 + g1 * da2);
+    }
+    for (int k = 0; k < 5; ++k) {
+      const double* T = c.pdft + k * NXK;
+      const double t1 = hermite_x(T, r.t1), t2 = hermite_x(T, r.t2);
+      dw[1 + k] = r.r1.v * q1 * t2 + r.r2.v * t1 * q2 + r.r3.v * a1 * t2 + r.r4.v * t1 * a2;
+    }
+    const double *TU = c.pdft + 5 * NXK, *TD = c.pdft + 6 * NXK, *TA = c.pdft + 7 * NXK;
+    dw[6] = r.r1.v * hermite_x(TU, r.t1) * g2 + r.r2.v * g1 * hermite_x(TU, r.t2);
+    dw[7] = r.r1.v * hermite_x(TD, r.t1) * g2 + r.r2.v * g1 * hermite_x(TD, r.t2);
+    dw[8] = r.r3.v * 2.0 * hermite_x(TA, r.t1) * g2 + r.r4.v * g1 * 2.0 * hermite_x(TA, r.t2);
   } else {
     const int fq = CH == 1 ? 1 : 2;
     const double* Q = c.pdfc + fq * NXK;

@@ -111,6 +111,13 @@ Launchers launchers_gg2_f64();
 Launchers launchers_gg2_f32();
 Launchers launchers_uu_f64();
 Launchers launchers_dd_f64();
+// the quark channels with one more light parton (FP64)
+Launchers launchers_uug_f64();
+Launchers launchers_ddg_f64();
+Launchers launchers_qg_f64();
 Launchers launchers_gg3_f32();
+// g g -> t t~ g g with the colour sum on the matrix cores (staged kernels)
+Launchers launchers_gg2s_f32();
+Launchers launchers_gg2s_f64();
 
 }  // namespace mf

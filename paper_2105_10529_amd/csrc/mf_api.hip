@@ -563,15 +563,29 @@ struct mf_process {
 
 namespace {
 
+// Massless final-state partons (gluons, or the light quark of q g -> t t~ q).
 int n_final_gluons(int proc) {
   switch (proc) {
-    case MF_GG_TTXG: return 1;
+    case MF_GG_TTXG:
+    case MF_UUX_TTXG:
+    case MF_DDX_TTXG:
+    case MF_QG_TTXQ: return 1;
     case MF_GG_TTXGG: return 2;
     case MF_GG_TTXGGG: return 3;
     default: return 0;
   }
 }
-int channel_of(int proc) { return proc == MF_UUX_TTX ? 1 : (proc == MF_DDX_TTX ? 2 : 0); }
+// 0: g g; 1: u u~; 2: d d~; 3: q g (q = u, d, u~, d~)
+int channel_of(int proc) {
+  switch (proc) {
+    case MF_UUX_TTX:
+    case MF_UUX_TTXG: return 1;
+    case MF_DDX_TTX:
+    case MF_DDX_TTXG: return 2;
+    case MF_QG_TTXQ: return 3;
+    default: return 0;
+  }
+}
 
 double factorial(int n) {
   double f = 1;
@@ -592,13 +606,20 @@ size_t vegas_lds_bytes(int d, int nb) {
          (size_t)d * BLOCK;
 }
 
-Launchers pick_launchers(int ng, int ch, int prec) {
+// Colour form of g g -> t t~ g g when the configuration leaves it open: the
+// in-register form, measured faster in both precisions (FP32: 1.07e8 against
+// 0.89e8 events/s; FP64: 7.3e7 against 3.6e7).
+int default_colour_form(int) { return 1; }
+
+Launchers pick_launchers(int ng, int ch, int prec, int colour_form) {
   const bool f32 = prec == MF_PREC_FP32_AMP;
-  if (ch == 1) return launchers_uu_f64();
-  if (ch == 2) return launchers_dd_f64();
+  if (ch == 1) return ng == 1 ? launchers_uug_f64() : launchers_uu_f64();
+  if (ch == 2) return ng == 1 ? launchers_ddg_f64() : launchers_dd_f64();
+  if (ch == 3) return launchers_qg_f64();
   if (ng == 0) return f32 ? launchers_gg0_f32() : launchers_gg0_f64();
   if (ng == 1) return f32 ? launchers_gg1_f32() : launchers_gg1_f64();
   if (ng == 3) return launchers_gg3_f32();
+  if (colour_form == 2) return f32 ? launchers_gg2s_f32() : launchers_gg2s_f64();
   return f32 ? launchers_gg2_f32() : launchers_gg2_f64();
 }
 
@@ -731,7 +752,7 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
   mf::clear_error();
   if (!cfg || !out) return fail(MF_EINVAL, "NULL argument");
   *out = nullptr;
-  if (cfg->process < MF_GG_TTX || cfg->process > MF_GG_TTXGGG) return fail(MF_EINVAL, "unknown process %d", cfg->process);
+  if (cfg->process < MF_GG_TTX || cfg->process > MF_QG_TTXQ) return fail(MF_EINVAL, "unknown process %d", cfg->process);
   if (cfg->precision != MF_PREC_FP64 && cfg->precision != MF_PREC_FP32_AMP)
     return fail(MF_EINVAL, "unknown precision %d", cfg->precision);
   if (!(cfg->m_t > 0.0)) return fail(MF_EINVAL, "m_t must be positive");
@@ -749,6 +770,9 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
     return fail(MF_ENOTSUP, "polarisation-state sampling is built for g g -> t t~ g g g only");
   if (cfg->dynamic_scale != 0 && cfg->dynamic_scale != 1)
     return fail(MF_EINVAL, "dynamic_scale must be 0 or 1");
+  if (cfg->colour_form < 0 || cfg->colour_form > 2) return fail(MF_EINVAL, "colour_form must be 0, 1 or 2");
+  if (cfg->colour_form != 0 && ng != 2)
+    return fail(MF_ENOTSUP, "the colour form is selectable for g g -> t t~ g g only");
   if (channel_of(cfg->process) != 0 && cfg->precision != MF_PREC_FP64)
     return fail(MF_ENOTSUP, "quark channels are built in FP64 only");
   for (int i = 0; i < 20; i += 5)
@@ -779,9 +803,12 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
   c.lx0 = std::log(std::pow(10.0, -9.0));
   c.ihx = (NXK - 1) / (0.0 - c.lx0);
   double g2 = 4.0 * M_PI * cfg->alpha_s;
+  // coupling g^(2 n), initial spin and colour average, final-state symmetry
   if (c.channel == 0) c.norm = std::pow(g2, ng + 2) / 256.0 / factorial(ng) * GEV2_PB;
-  else c.norm = g2 * g2 / 36.0 * GEV2_PB;
-  p->L = pick_launchers(ng, c.channel, cfg->precision);
+  else if (c.channel == 3) c.norm = g2 * g2 * g2 / 96.0 * GEV2_PB;
+  else c.norm = std::pow(g2, ng + 2) / 36.0 * GEV2_PB;
+  const int colour_form = cfg->colour_form != 0 ? cfg->colour_form : default_colour_form(cfg->precision);
+  p->L = pick_launchers(ng, c.channel, cfg->precision, ng == 2 ? colour_form : 1);
   p->pstride = PART_HEAD + p->ndim * p->nb;
   p->rec_cap = 4096;
   auto cleanup = [&](mf_status s) {

@@ -12,6 +12,7 @@
 #include "gen/me_gg_m2.h"
 #include "gen/me_gg_m3.h"
 #include "gen/me_gg_m4.h"
+#include "qq.h"
 
 namespace mf {
 
@@ -380,7 +381,7 @@ __device__ __forceinline__ Dual<double> to_k(Dual<float> a, Dual<double>*) {
 // w = r1 q(x1) q~(x2) + r2 q~(x1) q(x2).  r1, r2 hold every factor but the
 // PDFs (they carry the m_t derivative in the dual case).
 template <class R> struct EventOut {
-  R w, r1, r2;
+  R w, r1, r2, r3, r4;
   double t1, t2;  // PDF table positions of x1, x2
   int pass;
 };
@@ -432,17 +433,67 @@ __device__ __forceinline__ EventOut<RK> event_weight(const DevCfg& c, const doub
     RK w = r1 * RK(pdf_at(c, pdf, 0, out.t1, tq) * pdf_at(c, pdf, 0, out.t2, tq));
     out.r1 = ok ? r1 : zero;
     out.r2 = zero;
+    out.r3 = zero;
+    out.r4 = zero;
     out.w = ok ? w : zero;
-  } else {
+  } else if constexpr (NG == 0 || CH != 3) {
+    // q q~ -> t t~ (+ g): the quark from beam 1 (r1) or from beam 2 (r2)
     V4<double> p1{E, 0.0, 0.0, E}, p2{E, 0.0, 0.0, -E};
-    RK r1 = pre * to_k(me_qqbar<RA, RK>(p1, p2, top, atop, mt), (RK*)nullptr);
-    RK r2 = pre * to_k(me_qqbar<RA, RK>(p2, p1, top, atop, mt), (RK*)nullptr);
+    RK r1, r2;
+    if constexpr (NG == 0) {
+      r1 = pre * to_k(me_qqbar<RA, RK>(p1, p2, top, atop, mt), (RK*)nullptr);
+      r2 = pre * to_k(me_qqbar<RA, RK>(p2, p1, top, atop, mt), (RK*)nullptr);
+    } else {
+      const V4<RA> a = to_amp<RA, double>(p1), b = to_amp<RA, double>(p2), k = to_amp<RA, double>(gl[0]);
+      const V4<RA> t = to_amp<RA, RK>(top), tb = to_amp<RA, RK>(atop);
+      const RA m_a = to_amp_s(mt, (RA*)nullptr);
+      // one copy of the matrix-element code for both beam assignments
+      r1 = r2 = zero;
+#pragma unroll 1
+      for (int j = 0; j < 2; ++j) {
+        const RK rj = pre * to_k(me_qqbar_g<RA>(j ? b : a, j ? a : b, t, tb, k, m_a), (RK*)nullptr);
+        r1 = j ? r1 : rj;
+        r2 = j ? rj : r2;
+      }
+    }
     const int fq = CH == 1 ? 1 : 2, fa = 3;
     double q1 = pdf_at(c, pdf, fq, out.t1, tq), a2 = pdf_at(c, pdf, fa, out.t2, tq),
            a1 = pdf_at(c, pdf, fa, out.t1, tq), q2 = pdf_at(c, pdf, fq, out.t2, tq);
     RK w = r1 * RK(q1 * a2) + r2 * RK(a1 * q2);
     out.r1 = ok ? r1 : zero;
     out.r2 = ok ? r2 : zero;
+    out.r3 = zero;
+    out.r4 = zero;
+    out.w = ok ? w : zero;
+  } else {
+    // q g -> t t~ q (q = u, d) from either beam (r1: quark from beam 1, r2:
+    // from beam 2) and q~ g -> t t~ q~ (q~ = u~, d~, equal PDFs): by charge
+    // conjugation its |M|^2 is that of q g -> t t~ q with the top and
+    // antitop momenta exchanged (r3: antiquark from beam 1, r4: from beam 2)
+    V4<double> p1{E, 0.0, 0.0, E}, p2{E, 0.0, 0.0, -E};
+    const V4<RA> a = to_amp<RA, double>(p1), b = to_amp<RA, double>(p2), k = to_amp<RA, double>(gl[0]);
+    const V4<RA> t = to_amp<RA, RK>(top), tb = to_amp<RA, RK>(atop);
+    const RA m_a = to_amp_s(mt, (RA*)nullptr);
+    // one copy of the matrix-element code for the four assignments
+    RK r1 = zero, r2 = zero, r3 = zero, r4 = zero;
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+      const bool sw = (j & 1) != 0, cc = (j & 2) != 0;
+      const RK rj = pre * to_k(me_qg_q<RA>(sw ? b : a, sw ? a : b, cc ? tb : t, cc ? t : tb, k, m_a), (RK*)nullptr);
+      r1 = j == 0 ? rj : r1;
+      r2 = j == 1 ? rj : r2;
+      r3 = j == 2 ? rj : r3;
+      r4 = j == 3 ? rj : r4;
+    }
+    const double g1 = pdf_at(c, pdf, 0, out.t1, tq), g2 = pdf_at(c, pdf, 0, out.t2, tq);
+    const double qs1 = pdf_at(c, pdf, 1, out.t1, tq) + pdf_at(c, pdf, 2, out.t1, tq);
+    const double qs2 = pdf_at(c, pdf, 1, out.t2, tq) + pdf_at(c, pdf, 2, out.t2, tq);
+    const double as1 = 2.0 * pdf_at(c, pdf, 3, out.t1, tq), as2 = 2.0 * pdf_at(c, pdf, 3, out.t2, tq);
+    RK w = r1 * RK(qs1 * g2) + r2 * RK(g1 * qs2) + r3 * RK(as1 * g2) + r4 * RK(g1 * as2);
+    out.r1 = ok ? r1 : zero;
+    out.r2 = ok ? r2 : zero;
+    out.r3 = ok ? r3 : zero;
+    out.r4 = ok ? r4 : zero;
     out.w = ok ? w : zero;
   }
   return out;

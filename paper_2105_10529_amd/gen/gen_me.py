@@ -83,6 +83,96 @@ def trace_sum(word, N=3):
     return total
 
 
+def multi_trace_sum(words, N=3):
+    """sum over repeated adjoint labels of the product of traces
+    Tr(t^{w_0} ...) Tr(t^{v_0} ...) ..., exact (every label appears twice;
+    an empty word is a trace of the identity).  The same slot network as
+    trace_sum, with the trace joins taken within each word."""
+    pos = []  # (word index, position) of each generator, in order
+    for wi, w_ in enumerate(words):
+        for p_ in range(len(w_)):
+            pos.append((wi, p_))
+    n = len(pos)
+    start = {}
+    k = 0
+    for wi, w_ in enumerate(words):
+        start[wi] = k
+        k += len(w_)
+    labels = [w_[p_] for wi, w_ in enumerate(words) for p_ in range(len(w_))]
+    pairs = {}
+    for g, a in enumerate(labels):
+        pairs.setdefault(a, []).append(g)
+    plist = [tuple(v) for v in pairs.values()]
+    assert all(len(v) == 2 for v in plist)
+    empty = sum(1 for w_ in words if len(w_) == 0)
+    total = Fraction(0)
+    for choice in itertools.product((0, 1), repeat=len(plist)):
+        link = [None] * (2 * n)
+        coef = Fraction(1)
+        for (p_, q_), c in zip(plist, choice):
+            coef *= Fraction(1, 2)
+            if c == 0:
+                link[2 * p_], link[2 * q_ + 1] = 2 * q_ + 1, 2 * p_
+                link[2 * q_], link[2 * p_ + 1] = 2 * p_ + 1, 2 * q_
+            else:
+                coef *= Fraction(-1, N)
+                link[2 * p_], link[2 * p_ + 1] = 2 * p_ + 1, 2 * p_
+                link[2 * q_], link[2 * q_ + 1] = 2 * q_ + 1, 2 * q_
+        succ = [0] * n
+        for g in range(n):
+            col = link[2 * g] // 2
+            wi, p_ = pos[col]
+            succ[g] = start[wi] + (p_ + 1) % len(words[wi])
+        total += coef * Fraction(N) ** (_count_cycles(succ) + empty)
+    return total
+
+
+# Colour tensors of the five diagrams of q q~ -> t t~ g (and, with the light
+# line read from the outgoing quark, of q g -> t t~ q): a light-quark line L
+# and the top line T joined by one gluon, and one external gluon of adjoint
+# index "a".  Each is a sum of terms (coefficient, closed traces, L word,
+# T word); f^{abc} = -2i Tr([t^a, t^b] t^c).
+TWO_LINE_TENSORS = [
+    [((1, 0), (), ("b", "a"), ("b",))],
+    [((1, 0), (), ("a", "b"), ("b",))],
+    [((1, 0), (), ("c",), ("a", "c"))],
+    [((1, 0), (), ("c",), ("c", "a"))],
+    [((0, -2), (("a", "b", "c"),), ("b",), ("c",)), ((0, 2), (("b", "a", "c"),), ("b",), ("c",))],
+]
+
+
+@functools.lru_cache(maxsize=None)
+def two_line_colour_matrix():
+    """CC[d][d'] = sum over all colours of C_d C_d'^* for the tensors above,
+    as exact complex rationals (re, im): the conjugate of a string of
+    generators is the reversed string, so every product closes into traces
+    (L with L'^dagger, T with T'^dagger, each closed trace of C_d' reversed);
+    the internal labels of d' are renamed, the external gluon's is shared."""
+    def ren(w_):
+        return tuple(x if x == "a" else x + "'" for x in w_)
+
+    def cmul(a, b):
+        return (a[0] * b[0] - a[1] * b[1], a[0] * b[1] + a[1] * b[0])
+
+    out = []
+    for d in TWO_LINE_TENSORS:
+        row = []
+        for e in TWO_LINE_TENSORS:
+            re_, im_ = Fraction(0), Fraction(0)
+            for c1, cl1, L1, T1 in d:
+                for c2, cl2, L2, T2 in e:
+                    coef = cmul((Fraction(c1[0]), Fraction(c1[1])), (Fraction(c2[0]), -Fraction(c2[1])))
+                    words = list(cl1) + [tuple(reversed(ren(w_))) for w_ in cl2]
+                    words.append(tuple(L1) + tuple(reversed(ren(L2))))
+                    words.append(tuple(T1) + tuple(reversed(ren(T2))))
+                    v = multi_trace_sum(words)
+                    re_ += coef[0] * v
+                    im_ += coef[1] * v
+            row.append((re_, im_))
+        out.append(row)
+    return out
+
+
 @functools.lru_cache(maxsize=None)
 def colour_matrix(m):
     perms = list(itertools.permutations(range(m)))
@@ -412,6 +502,158 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False) -> str:
     return "\n".join(L) + "\n"
 
 
+def emit_amp_store(m: int) -> str:
+    """Partial amplitudes of m gluons for a range of gluon polarisation
+    states, stored for a separate colour sum (no colour form here): the same
+    per-ordering Berends-Giele steps, and the same sharing of each ordering's
+    gluon currents between the two antitop helicities, as
+    emit_me_per_ordering(m, share_antitop=True).  The per-event constants
+    (propagator factors, polarisation vectors, momenta, antitop spinors) are
+    read from per-lane LDS tables inside each ordering, through an opaque
+    zero offset, so that they do not stay live in registers across the
+    orderings.  For gluon state hg, antitop helicity h and top helicity t the
+    amplitude of ordering k goes to
+      out[slice * sstride + (k / 4) * ld4 + k % 4],
+      slice = (((hg - hg0) * 2 + h) * 2 + t) * 2 + (0: re, 1: im).
+    Tables (each pointer already at the lane's column, stride AW):
+      gt[S * AW]: -1 / P_S^2 for gluon subsets S with >= 2 gluons;
+      qt[S * AW]: -1 / ((p_tb + P_S)^2 - m_t^2) for S != all;
+      et[(2 i + p) * AW]: polarisation p of gluon i; kt[i * AW]: momentum of
+      gluon i; vt[h * AW]: v(antitop) of helicity h."""
+    perms, Z, den = colour_matrix(m)
+    nf = len(perms)
+    L = []
+    w = L.append
+    w(f"// Generated by gen_me.py for g g -> t t~ + {m - 2} g ({m} gluons on the top line,")
+    w(f"// {nf} colour orderings, {4 << m} helicity/polarisation states): partial")
+    w("// amplitudes stored for the colour sum on the matrix cores. Do not edit.")
+    w("#pragma once")
+    w('#include "amp.h"')
+    w("namespace mf {")
+    w(f"constexpr int AMPS_M{m}_NF = {nf};")
+    w(f"constexpr int AMPS_M{m}_NQ = {nf // 4};  // groups of four orderings")
+    w(f"constexpr int AMPS_M{m}_HG = {1 << m};  // gluon polarisation states")
+    w("template <class R, int AW>")
+    w(f"__device__ __forceinline__ void amp_gg_m{m}_store(const R* gt, const R* qt, const V4<R>* et, const V4<R>* kt,")
+    w("                                               const Sp<R>* vt, const Sp<R>* UB, const V4<R>& PB, R MT,")
+    w("                                               int hg0, int nhg, R* out, int64_t sstride, int64_t ld4) {")
+    w("#pragma unroll 1")
+    w("  for (int hg = hg0; hg < hg0 + nhg; ++hg) {")
+    w("    R* const o_hg = out + (int64_t)((hg - hg0) * 8) * sstride;")
+    ind = "    "
+    for k, seq in enumerate(perms):
+        w(f"{ind}{{  // ordering {seq}")
+        ii = ind + "  "
+        w(f"{ii}int z_ = 0;")
+        w(f"{ii}asm volatile(\"\" : \"+v\"(z_));")
+        for i in range(m):
+            w(f"{ii}const V4<R> J{i} = et[(2 * {i} + ((hg >> {m - 1 - i}) & 1)) * AW + z_];")
+            w(f"{ii}const V4<R> k{i} = kt[{i} * AW + z_];")
+        w(f"{ii}V4<R> pb = PB;")
+        w(f"{ii}opaque4(pb);")
+        done = set(f"J{i}" for i in range(m))
+        psum = set()
+        consts = set()
+
+        def P(sq):
+            s_ = _mask(sq)
+            nm = f"p{s_}"
+            if len(sq) == 1:
+                return f"k{sq[0]}"
+            if nm not in psum:
+                w(f"{ii}const V4<R> {nm} = " + " + ".join(f"k{i}" for i in sorted(sq)) + ";")
+                psum.add(nm)
+            return nm
+
+        def G(sq):
+            s_ = _mask(sq)
+            if f"G{s_}" not in consts:
+                w(f"{ii}const R G{s_} = gt[{s_} * AW + z_];")
+                consts.add(f"G{s_}")
+            return f"G{s_}"
+
+        def IQ(sq):
+            s_ = _mask(sq)
+            if f"IQ{s_}" not in consts:
+                w(f"{ii}const R IQ{s_} = qt[{s_} * AW + z_];")
+                consts.add(f"IQ{s_}")
+            return f"IQ{s_}"
+
+        def J(sq):
+            nm = f"J{_name(sq)}"
+            if nm in done:
+                return nm
+            t3 = [f"v3({J(sq[:j])}, {J(sq[j:])}, {P(sq[:j])}, {P(sq[j:])})" for j in range(1, len(sq))]
+            t4 = [f"w4({J(sq[:j])}, {J(sq[j:l])}, {J(sq[l:])})" for j in range(1, len(sq) - 1)
+                  for l in range(j + 1, len(sq))]
+            expr = " + ".join(t3)
+            if t4:
+                expr = f"({expr}) - (" + " + ".join(t4) + ")"
+            g = G(sq)
+            w(f"{ii}const V4<R> {nm} = {g} * ({expr});")
+            done.add(nm)
+            return nm
+
+        def S(sq, hs):
+            nm = f"S{hs}_{_name(sq)}"
+            if nm in done:
+                return nm
+            terms = [f"slash({J(sq[:j])}, {S(sq[j:], hs)})" for j in range(1, len(sq) + 1)]
+            q = IQ(sq)
+            w(f"{ii}const Sp<R> {nm} = prop(R(-1.0) * (pb + {P(sq)}), MT, {q}, " + " + ".join(terms) + ");")
+            done.add(nm)
+            return nm
+
+        for j in range(1, m + 1):
+            J(seq[:j])
+        for h in (0, 1):
+            hs = f"h{h}"
+            w(f"{ii}const Sp<R> S{hs}_ = vt[{h} * AW + z_];")
+            done.add(f"S{hs}_")
+            terms = [f"slash({J(seq[:j])}, {S(seq[j:], hs)})" for j in range(1, m + 1)]
+            w(f"{ii}const Sp<R> F{hs} = " + " + ".join(terms) + ";")
+            w(f"{ii}{{")
+            w(f"{ii}  const C2<R> a0 = ubar_dot(UB[0], F{hs}), a1 = ubar_dot(UB[1], F{hs});")
+            w(f"{ii}  R* o_ = o_hg + (int64_t)({h * 4}) * sstride + (int64_t)({k >> 2}) * ld4 + {k & 3};")
+            w(f"{ii}  o_[0] = a0.re;")
+            w(f"{ii}  o_[sstride] = a0.im;")
+            w(f"{ii}  o_[2 * sstride] = a1.re;")
+            w(f"{ii}  o_[3 * sstride] = a1.im;")
+            w(f"{ii}}}")
+        w(f"{ind}}}")
+    w("  }")
+    w("}")
+    vals = ", ".join(str(v) for row in Z for v in row)
+    w(f"// colour matrix numerators C[s][s'] * {den}, row-major")
+    w(f"constexpr double AMPS_M{m}_COLOUR_DEN = {den}.0;")
+    w(f"__device__ const float AMPS_M{m}_COLOUR[{nf * nf}] = {{{vals}}};")
+    w("}  // namespace mf")
+    return "\n".join(L) + "\n"
+
+
+def emit_colour_qq() -> str:
+    """The colour matrix of the five diagrams of the two-quark-line channels
+    (q q~ -> t t~ g, q g -> t t~ q) over a common denominator."""
+    CC = two_line_colour_matrix()
+    den = 1
+    for row in CC:
+        for re_, im_ in row:
+            for v in (re_, im_):
+                den = den * v.denominator // math.gcd(den, v.denominator)
+    re_s = ", ".join(f"{int(re_ * den)}.0" for row in CC for re_, _ in row)
+    im_s = ", ".join(f"{int(im_ * den)}.0" for row in CC for _, im_ in row)
+    L = ["// Generated by gen_me.py: colour matrix CC[d][d'] = sum_colours C_d C_d'^* of the",
+         "// five diagrams of q q~ -> t t~ g and q g -> t t~ q (two quark lines joined by a",
+         "// gluon, one more external gluon), by colour-flow loop counting.  Do not edit.",
+         "#pragma once",
+         "namespace mf {",
+         f"constexpr double QQ_CC_DEN = {den}.0;",
+         f"__device__ const double QQ_CC_RE[25] = {{{re_s}}};",
+         f"__device__ const double QQ_CC_IM[25] = {{{im_s}}};",
+         "}  // namespace mf"]
+    return "\n".join(L) + "\n"
+
+
 def emit_amp_tables(m: int) -> str:
     """Tables for the streamed partial amplitudes of m gluons (the per-ordering
     routine itself is hand-written in gg3.h):
@@ -545,6 +787,14 @@ def main(outdir: str, ms=(2, 3, 4, 5)) -> None:
             path = os.path.join(outdir, f"me_gg_m{m}.h")
             text = emit_me(m) if SCHEDULE[m] == "memo" else emit_me_per_ordering(
                 m, share_antitop=SCHEDULE[m] == "per_ordering_shared_antitop")
+        old = open(path).read() if os.path.exists(path) else None
+        if old != text:
+            with open(path, "w") as f:
+                f.write(text)
+    # g g -> t t~ g g: the amplitudes stored for the matrix-core colour sum;
+    # the colour matrix of the quark channels
+    for name, text in (("amps_gg_m4.h", emit_amp_store(4)), ("colour_qq.h", emit_colour_qq())):
+        path = os.path.join(outdir, name)
         old = open(path).read() if os.path.exists(path) else None
         if old != text:
             with open(path, "w") as f:

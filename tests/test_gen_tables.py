@@ -102,3 +102,23 @@ def test_shared_antitop_counts():
     for m, before in ((3, 66474), (4, 929978)):
         fc = gen_me.flop_count(m)
         assert fc["total"] == before - (fc["states"] // 2) * fc["gluon_currents_per_polarisation"]
+
+
+def test_two_line_colour_matrix_matches_oracle():
+    """The generator's colour matrix of the quark channels (Fierz loop
+    counting over products of traces) equals the oracle's explicit Gell-Mann
+    sum."""
+    from oracle import colour
+
+    CC = gen_me.two_line_colour_matrix()
+    got = np.array([[float(re_) + 1j * float(im_) for re_, im_ in row] for row in CC])
+    assert np.allclose(got, colour.two_line_colour_matrix(), atol=1e-13)
+
+
+def test_multi_trace_sum_small_cases():
+    from fractions import Fraction
+
+    assert gen_me.multi_trace_sum([()]) == 3  # Tr(1) = N
+    assert gen_me.multi_trace_sum([(0,), (0,)]) == 0  # Tr(t^a) = 0
+    assert gen_me.multi_trace_sum([(0, 1), (0, 1)]) == 2  # Tr(t^a t^b)^2 = (N^2 - 1)/4
+    assert gen_me.multi_trace_sum([(0, 1, 0, 1)]) == gen_me.trace_sum((0, 1, 0, 1)) == Fraction(-2, 3)

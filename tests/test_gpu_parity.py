@@ -31,9 +31,9 @@ def _oracle(ng, channel="gg", dr=None):
     return oracle.Oracle(oracle.Config(n_g=ng, channel=channel, dr_min=(0.4 if ng >= 2 else 0.0) if dr is None else dr))
 
 
-def _proc(ng, precision="fp64", process=None, dr=None):
+def _proc(ng, precision="fp64", process=None, dr=None, colour_form=0):
     return mf.Process(mf.Config(process=process or PROC[ng], precision=precision,
-                                dr_min=(0.4 if ng >= 2 else 0.0) if dr is None else dr))
+                                dr_min=(0.4 if ng >= 2 else 0.0) if dr is None else dr, colour_form=colour_form))
 
 
 def _points(n, d, seed):
@@ -129,8 +129,10 @@ def _oracle_iteration(ng, n, grid_seed, iteration, seed):
     return _FULL_GEOMETRY_ORACLE[key]
 
 
-@pytest.mark.parametrize("ng,n,precision", [(1, 1_100_000, "fp64"), (2, 600_000, "fp32"), (2, 600_000, "fp64")])
-def test_vegas_iteration_full_geometry_matches_oracle(ng, n, precision):
+@pytest.mark.parametrize("ng,n,precision,form", [(1, 1_100_000, "fp64", 0), (2, 600_000, "fp32", 1),
+                                                 (2, 600_000, "fp32", 2), (2, 600_000, "fp64", 1),
+                                                 (2, 600_000, "fp64", 2)])
+def test_vegas_iteration_full_geometry_matches_oracle(ng, n, precision, form):
     """One iteration in the launch geometry of the full-size runs: 2048 blocks
     of 256 threads, each block looping over two or three 256-event chunks
     (2048 x 256 = 524288 events per pass, so 600000 and 1100000 events leave
@@ -138,12 +140,15 @@ def test_vegas_iteration_full_geometry_matches_oracle(ng, n, precision):
     histograms and the per-block lists of kept events persisting across
     chunks -- must give the oracle's iteration: FP64 to rounding (1e-12 on the
     estimate, 1e-10 on the refined edges, the same count of non-zero events),
-    FP32 amplitudes within 1e-5.  g g -> t t~ g g in FP64 runs the staged
-    iteration (points, integrand, accumulation)."""
+    FP32 amplitudes within 1e-5.  g g -> t t~ g g with the colour form in
+    registers (form 1; a fused kernel in FP32, a staged iteration -- points,
+    integrand, accumulation -- in FP64) and on the matrix cores (form 2;
+    staged, the integrand as selection, amplitude and colour kernels over
+    chunks of at most 65536 passing events, so ~2.5 chunks here)."""
     fp64 = precision == "fp64"
-    p = _proc(ng, precision)
+    p = _proc(ng, precision, colour_form=form)
     d = si.ndim(ng)
-    print(f"full geometry ng={ng} n={n} {precision}", flush=True)
+    print(f"full geometry ng={ng} n={n} {precision} colour form {form}", flush=True)
     edges = torch.from_numpy(si.random_grid(d, 50, seed=15)).to("cuda")
     out = torch.empty_like(edges)
     r = p.integrate(1, n, adapt=True, iter_offset=5, edges_in=edges, edges_out=out)
@@ -154,6 +159,46 @@ def test_vegas_iteration_full_geometry_matches_oracle(ng, n, precision):
     assert r.n_nonzero == nnz and r.n_nonfinite == nbad == 0
     ref_edges = oracle.vegas_refine(si.random_grid(d, 50, seed=15), hist, 1.5)
     assert np.max(np.abs(out.cpu().numpy() - ref_edges)) < (1e-10 if fp64 else 1e-5)
+
+
+_TTGG_POINTS = {}
+
+
+def _ttgg_points_and_oracle(n):
+    if n not in _TTGG_POINTS:
+        x = _points(n, 10, 210)
+        _TTGG_POINTS[n] = (x, _oracle(2).integrand(x))
+    return _TTGG_POINTS[n]
+
+
+@pytest.mark.parametrize("precision,form", [("fp64", 1), ("fp64", 2), ("fp32", 1), ("fp32", 2)])
+def test_gg_ttgg_colour_forms_match_oracle(precision, form):
+    """g g -> t t~ g g per event against the FP64 oracle with the colour form
+    in registers (1) and on the matrix cores (2; products of the exact
+    integer numerators of the colour matrix, FP32 or FP64 accumulation), on
+    140000 points (about 70000 pass the cuts: two chunks of the matrix-core
+    path, the second ragged) plus the extreme uniforms."""
+    x, ref = _ttgg_points_and_oracle(140_000)
+    print(f"ttgg colour form {form} {precision}", flush=True)
+    got = _proc(2, precision, colour_form=form).integrand(to_dev_soa(x)).cpu().numpy()
+    assert np.count_nonzero(ref) > 65536
+    assert_close(got, ref, 1e-11 if precision == "fp64" else 1e-5)
+
+
+def test_gg_ttgg_fp64_colour_forms_agree():
+    """The two FP64 colour forms sum the same exact quadratic form in a
+    different order: per event they agree to rounding."""
+    x = _points(3000, 10, 211)
+    u = to_dev_soa(x)
+    a = _proc(2, "fp64", colour_form=1).integrand(u).cpu().numpy()
+    b = _proc(2, "fp64", colour_form=2).integrand(u).cpu().numpy()
+    assert_close(b, a, 1e-13)
+    with pytest.raises(mf.MFError) as e:
+        _proc(1, colour_form=2)
+    assert e.value.status == mf.MF_ENOTSUP
+    with pytest.raises(mf.MFError) as e:
+        _proc(2, colour_form=3)
+    assert e.value.status == mf.MF_EINVAL
 
 
 def test_refine_matches_oracle():
@@ -354,3 +399,73 @@ def test_vjp_is_the_ordered_contraction():
         got = mf.vjp(torch.from_numpy(dw).cuda(), torch.from_numpy(g).cuda()).cpu().numpy()
         ref = dw @ g
         assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(dw).sum(axis=1).max())
+
+
+QUARK_PROCS = [("uux>ttxg", "uu~"), ("ddx>ttxg", "dd~"), ("qg>ttxq", "qg")]
+
+
+@pytest.mark.parametrize("process,channel", QUARK_PROCS)
+def test_quark_channels_with_a_jet_match_oracle(process, channel):
+    """u u~ -> t t~ g, d d~ -> t t~ g and q g -> t t~ q (+ q~ g) per event
+    against the FP64 oracle's five-diagram evaluation (1e-11), points above
+    threshold plus the extreme uniforms."""
+    x = _points(3000, 7, 230)
+    ref = oracle.Oracle(oracle.Config(n_g=1, channel=channel)).integrand(x)
+    print(f"quark channel {process}", flush=True)
+    got = mf.Process(mf.Config(process=process)).integrand(to_dev_soa(x)).cpu().numpy()
+    assert np.count_nonzero(ref) > 1000
+    assert_close(got, ref, 1e-11)
+
+
+@pytest.mark.parametrize("process,channel", QUARK_PROCS)
+def test_quark_channel_iteration_and_derivatives_match_oracle(process, channel):
+    """One on-device VEGAS iteration equals the oracle's on the same Philox
+    stream (1e-12), and the forward-mode derivatives in m_t and the eight PDF
+    parameters equal the oracle's dual numbers per event (1e-10 of the largest
+    value); the quark normalisations A_u, A_d, A_u~ now enter (non-zero
+    derivatives), and d w / d A_f = w_f / A_f for the part of w with that
+    flavour."""
+    p = mf.Process(mf.Config(process=process))
+    orc = oracle.Oracle(oracle.Config(n_g=1, channel=channel))
+    edges = torch.from_numpy(si.random_grid(7, 50, seed=25)).to("cuda")
+    out = torch.empty_like(edges)
+    n = 20000
+    r = p.integrate(1, n, adapt=True, iter_offset=4, edges_in=edges, edges_out=out)
+    S1, S2, hist, nnz, _ = orc.vegas_iteration(si.random_grid(7, 50, seed=25), 4, n, p.cfg.seed, purpose=0)
+    I, s = oracle.iteration_estimate(S1, S2, n)
+    assert abs(r.iter_integral[0] / I - 1) < 1e-12 and r.n_nonzero == nnz
+    assert np.max(np.abs(out.cpu().numpy() - oracle.vegas_refine(si.random_grid(7, 50, seed=25), hist))) < 1e-10
+    x = _points(400, 7, 231)
+    w, dw = p.integrand_grad(to_dev_soa(x))
+    w, dw = w.cpu().numpy(), dw.cpu().numpy()
+    for k, direction in enumerate(range(1, 10)):
+        rw, rdw = orc.integrand_grad(x, direction)
+        if k == 0:
+            assert_close(w, rw, 1e-11)
+        scale = max(np.max(np.abs(rdw)), 1e-300)
+        assert np.max(np.abs(dw[k] - rdw)) < 1e-10 * scale, (process, k)
+    # the quark normalisations the channel uses have non-zero derivatives
+    used = {"uux>ttxg": (6, 8), "ddx>ttxg": (7, 8), "qg>ttxq": (6, 7, 8)}[process]
+    for k in used:
+        assert np.count_nonzero(dw[k]) > 100, (process, k)
+    for k in set((6, 7, 8)) - set(used):
+        assert np.all(dw[k] == 0.0), (process, k)
+
+
+def test_quark_channel_derivative_matches_central_difference():
+    """d sigma / d A_u of q g -> t t~ q from the pathwise estimator against a
+    central difference of sigma on the same Philox events (h = 1e-4 A_u):
+    sigma is linear in A_u, so they agree to rounding (1e-8)."""
+    p = mf.Process(mf.Config(process="qg>ttxq"))
+    n = 200_000
+    vals, _ = p.grad(n, iter_offset=3)
+    base = list(mf.DEFAULT_PDF)
+    hp = 1e-4 * base[5]
+
+    def sigma(a_u):
+        pp = list(base)
+        pp[5] = a_u
+        return mf.Process(mf.Config(process="qg>ttxq", pdf_params=tuple(pp))).grad(n, iter_offset=3)[0][0]
+
+    fd = (sigma(base[5] + hp) - sigma(base[5] - hp)) / (2 * hp)
+    assert abs(fd - vals[2 + 5]) < 1e-8 * abs(vals[2 + 5]), (fd, vals[2 + 5])

@@ -26,7 +26,9 @@ def _proc(name, **kw):
 def test_noalloc_matches_integrand(name, prec, ng, sizes):
     import torch
 
-    p = _proc(name, precision=prec, dr_min=0.4 if ng == 2 else 0.0)
+    # g g -> t t~ g g with the in-register colour form (single integrand kernel)
+    kw = {"dr_min": 0.4, "colour_form": 1} if ng == 2 else {}
+    p = _proc(name, precision=prec, **kw)
     for k, n in enumerate(sizes):
         print(f"noalloc {name} {prec} n={n}", flush=True)
         x = si.points_above_threshold(n, si.ndim(ng), 13000.0, 173.0, seed=900 + k)
@@ -51,8 +53,9 @@ def test_noalloc_limits():
     w = torch.empty(n, dtype=torch.float64, device="cuda")
     with pytest.raises(mf.MFError, match="at most"):
         p.integrand_noalloc(u, w)
-    p2 = _proc("gg>ttxggg", precision="fp32", dr_min=0.4)
-    u2 = torch.full((13, 8), 0.5, dtype=torch.float64, device="cuda")
-    w2 = torch.empty(8, dtype=torch.float64, device="cuda")
-    with pytest.raises(mf.MFError, match="workspace"):
-        p2.integrand_noalloc(u2, w2)
+    for name, d, kw in (("gg>ttxggg", 13, {}), ("gg>ttxgg", 10, {"colour_form": 2})):
+        p2 = _proc(name, precision="fp32", dr_min=0.4, **kw)
+        u2 = torch.full((d, 8), 0.5, dtype=torch.float64, device="cuda")
+        w2 = torch.empty(8, dtype=torch.float64, device="cuda")
+        with pytest.raises(mf.MFError, match="workspace"):
+            p2.integrand_noalloc(u2, w2)
