@@ -173,7 +173,10 @@ mf_status mf_integrand(mf_process* p, const double* u, int64_t n, double* w, voi
 #define MF_NOALLOC_MAX_POINTS (1 << 22)
 mf_status mf_integrand_noalloc(mf_process* p, const double* u, int64_t n, double* w, void* stream);
 
-/* The same integrand and its derivatives (forward mode) at the same points:
+/* The same integrand and its derivatives (forward mode) at the same points.
+ * The paper computes no derivatives: this extends its event weight (Sec. 2.1)
+ * with the derivatives in the top mass and the PDF parameters, by dual
+ * numbers through the same steps:
  *   dw: device, [9][n] FP64: d w / d m_t, then d w / d theta_k for
  *       theta = (A_g, a_g, b_g, c_g, d_g, A_u, A_d, A_u~), i.e. pdf_params
  *       entries 0..4, 5, 10, 15.  m_t enters the top momenta, the phase-space
@@ -334,7 +337,8 @@ mf_status mf_weight_stats(const double* w, int64_t n, double q, double* out, voi
  * k in 1..64, n >= 1.  Takes a small stream-ordered scratch allocation. */
 mf_status mf_vjp(const double* dw, int32_t k, const double* g, int64_t n, double* out, void* stream);
 
-/* Pathwise Monte Carlo estimate of sigma and its parameter derivatives with
+/* Pathwise Monte Carlo estimate of sigma and its parameter derivatives (an
+ * extension: the paper integrates sigma only, Sec. 2.1 and 3) with
  * a frozen grid (the current grid of the handle, or o->edges_in): events as
  * in mf_integrate with iteration word o->iter_offset, o->n_events events.
  *   out:  host [10]: sigma, d sigma/d m_t, d sigma / d theta_k (k = 0..7)
