@@ -18,11 +18,12 @@
  *    allocates device memory only inside an mf_process handle (tables, the
  *    VEGAS grid, reduction partials, staging buffers) and frees it in
  *    mf_process_destroy.
- *  - g g -> t t~ g g g (FP32 amplitudes only) evaluates the integrand in
- *    stages: kinematics and cuts, then the partial amplitudes of the events
- *    that pass, streamed through a handle-owned buffer of up to 2 GiB, then
- *    the colour sum on the matrix cores.  Its integrand calls synchronise
- *    `stream` once (to read the number of passing events).
+ *  - g g -> t t~ g g g (and g g -> t t~ g g with the matrix-core colour
+ *    form) evaluates the integrand in stages: kinematics and cuts, then the
+ *    partial amplitudes of the events that pass, streamed through a
+ *    handle-owned buffer of up to 2 GiB, then the colour sum on the matrix
+ *    cores.  These integrand calls synchronise `stream` once (to read the
+ *    number of passing events).
  *  - `stream` is a hipStream_t passed as void*; NULL means the default
  *    stream.  Calls taking a stream are asynchronous with respect to the
  *    host unless stated otherwise.
@@ -126,8 +127,8 @@ typedef struct mf_process mf_process;
  * allocates the VEGAS grid (uniform).  *out receives the handle.
  * MF_EINVAL for sqrt_s <= 2 m_t, non-positive masses/couplings, a scale
  * outside the Q grid or an unknown process; MF_ENOTSUP for a precision the
- * process does not provide (g g -> t t~ g g g: FP32 amplitudes only; the
- * quark channels: FP64 only); MF_ENOMEM / MF_EDEVICE on HIP failures. */
+ * process does not provide (the quark channels: FP64 only);
+ * MF_ENOMEM / MF_EDEVICE on HIP failures. */
 mf_status mf_process_create(const mf_config* cfg, mf_process** out);
 
 /* Release every device allocation of the handle (NULL is accepted). */

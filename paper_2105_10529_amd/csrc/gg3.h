@@ -48,6 +48,8 @@ constexpr int CT = 32;                 // events per colour tile (two 16-column 
 constexpr int CBLOCK = 256;            // colour kernel block: 4 waves x 8 slices
 constexpr int CMAX_BLOCKS = 512;       // two 65-KB-LDS blocks per CU
 constexpr int64_t NCMAX = 131072;      // passing events per chunk (fills 256 CUs x 2 waves x 4 SIMDs)
+// FP64 amplitudes: half the chunk (the same buffer size)
+template <class R> constexpr int64_t NCMAX_R = std::is_same<R, float>::value ? NCMAX : NCMAX / 2;
 
 // Workspace owned by the process handle (grown on demand, freed with it).
 struct Ws {
@@ -299,78 +301,111 @@ __global__ void __launch_bounds__(AWAVE) k_g3_amp(DevCfg c, const double* __rest
   }
 }
 
-typedef float f4 __attribute__((ext_vector_type(4)));
+template <class R> struct G3Mfma;
+template <> struct G3Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 step(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct G3Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 step(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
 
-__device__ __forceinline__ f4 load_f4(const float* p) { return *reinterpret_cast<const f4*>(p); }
+// Colour index that lane group g (= lane / 16) supplies at step (s, r) of a
+// 16 x 16 x 4 product, chosen so that the four indices a lane supplies for
+// block s = rb are the four rows of Z it receives: the FP32 product returns
+// rows 4 g + i to lane group g, the FP64 product rows g + 4 i (i = 0..3).
+template <class R> __device__ __forceinline__ constexpr int g3_kidx(int s, int g, int r) {
+  return std::is_same<R, float>::value ? 16 * s + 4 * g + r : 16 * s + g + 4 * r;
+}
 
 // Colour sum of one pass over the nsl slices (a multiple of 4) of the buffer for the nc
-// events of the chunk.  C in LDS in A-operand order: entry
-// ((rb * 8 + s) * 64 + l) * 4 + r holds C[16 rb + l % 16][16 s + 4 (l / 16) + r]
-// (zero beyond the 120 orderings).  For the MFMA step (s, r) lane l supplies
-// that entry and B[16 s + 4 (l / 16) + r][event l % 16], so the four lanes
-// groups cover colour indices 16 s .. 16 s + 15 over the four r; the result
-// lane l holds Z[16 rb + 4 (l / 16) + i][event l % 16], whose matching
+// events of the chunk.  C in LDS in A-operand order (exact integer numerators,
+// held as FP32): entry ((rb * 8 + s) * 64 + l) * 4 + r holds
+// C[16 rb + l % 16][g3_kidx(s, l / 16, r)] (zero beyond the 120 orderings).
+// For the MFMA step (s, r) lane l supplies that entry and
+// B[g3_kidx(s, l / 16, r)][event l % 16], so the four lane groups cover colour
+// indices 16 s .. 16 s + 15 over the four r; the result lane l holds
+// Z[g3_kidx(rb, l / 16, i)][event l % 16] in element i, whose matching
 // amplitudes are the B values the lane loaded for s = rb.
 // first: the pass overwrites me[]; last: it also writes the event weights.
-__global__ void __launch_bounds__(CBLOCK) k_g3_colour(const float* __restrict__ amp, int64_t ld, int64_t nc,
+template <class R>
+__global__ void __launch_bounds__(CBLOCK) k_g3_colour(const R* __restrict__ amp, int64_t ld, int64_t nc,
                                                       int nsl, int first, int last, double* __restrict__ me,
                                                       const int* __restrict__ idx, const double* __restrict__ wpre,
                                                       double* __restrict__ w, double inv_den) {
+  typedef typename G3Mfma<R>::v4 v4;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  // 16-event column blocks per tile: two in FP32, one in FP64 (register budget)
+  constexpr int NCB = std::is_same<R, float>::value ? 2 : 1;
+  constexpr int CTR = 16 * NCB;
   __shared__ float cs[8 * 8 * 64 * 4];
   __shared__ double part[CBLOCK / 64][CT];
   for (int i = threadIdx.x; i < 8 * 8 * 64 * 4; i += CBLOCK) {
     const int r = i & 3, l = (i >> 2) & 63, s = (i >> 8) & 7, rb = i >> 11;
-    const int row = 16 * rb + (l & 15), col = 16 * s + 4 * (l >> 4) + r;
+    const int row = 16 * rb + (l & 15), col = g3_kidx<R>(s, l >> 4, r);
     cs[i] = (row < NF && col < NF) ? AMP_M5_COLOUR[row * NF + col] : 0.0f;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, c16 = lane & 15;
-  const int64_t ntile = (nc + CT - 1) / CT;
+  const int64_t ntile = (nc + CTR - 1) / CTR;
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    const int64_t c0 = tile * CT;
+    const int64_t c0 = tile * CTR;
     double sum[2] = {0.0, 0.0};
 #pragma unroll 1
     for (int sl = wave * (nsl / 4); sl < (wave + 1) * (nsl / 4); ++sl) {
-      const float* base = amp + (int64_t)sl * NQ * ld * 4;
-      f4 bv[8][2];
+      const R* base = amp + (int64_t)sl * NQ * ld * 4;
+      v4 bv[8][NCB];
 #pragma unroll
       for (int s = 0; s < 8; ++s)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
-          bv[s][cb] = load_f4(base + ((int64_t)(4 * s + g) * ld + c0 + 16 * cb + c16) * 4);
-      float acc[2] = {0.0f, 0.0f};
+        for (int cb = 0; cb < NCB; ++cb) {
+          const int64_t col = c0 + 16 * cb + c16;
+          if constexpr (std::is_same<R, float>::value) {
+            bv[s][cb] = *reinterpret_cast<const v4*>(base + ((int64_t)(4 * s + g) * ld + col) * 4);
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bv[s][cb][r] = base[((int64_t)(4 * s + r) * ld + col) * 4 + g];
+          }
+        }
+      R acc[2] = {R(0.0), R(0.0)};
 #pragma unroll
       for (int rb = 0; rb < 8; ++rb) {
-        f4 zz[2] = {f4{0.0f, 0.0f, 0.0f, 0.0f}, f4{0.0f, 0.0f, 0.0f, 0.0f}};
+        v4 zz[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) zz[cb] = v4{R(0.0), R(0.0), R(0.0), R(0.0)};
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
           const f4 a = *reinterpret_cast<const f4*>(&cs[((rb * 8 + s) * 64 + lane) * 4]);
 #pragma unroll
           for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-              zz[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], bv[s][cb][r], zz[cb], 0, 0, 0);
+            for (int cb = 0; cb < NCB; ++cb) zz[cb] = G3Mfma<R>::step(R(a[r]), bv[s][cb][r], zz[cb]);
         }
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) acc[cb] = fmaf(zz[cb][i], bv[rb][cb][i], acc[cb]);
+          for (int i = 0; i < 4; ++i) acc[cb] = fma(zz[cb][i], bv[rb][cb][i], acc[cb]);
       }
       sum[0] += (double)acc[0];
       sum[1] += (double)acc[1];
     }
     // the four lane groups hold disjoint rows of the same events
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
+    for (int cb = 0; cb < NCB; ++cb) {
       sum[cb] += __shfl_xor(sum[cb], 16);
       sum[cb] += __shfl_xor(sum[cb], 32);
     }
     if (g == 0) {
-      part[wave][c16] = sum[0];
-      part[wave][16 + c16] = sum[1];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) part[wave][16 * cb + c16] = sum[cb];
     }
     __syncthreads();
-    if (threadIdx.x < CT) {
+    if (threadIdx.x < CTR) {
       const int64_t col = c0 + threadIdx.x;
       if (col < nc) {
         double v = part[0][threadIdx.x];
@@ -387,6 +422,105 @@ __global__ void __launch_bounds__(CBLOCK) k_g3_colour(const float* __restrict__ 
     }
     __syncthreads();
   }
+}
+
+inline void ws_free(void* p) {
+  Ws* ws = static_cast<Ws*>(p);
+  if (!ws) return;
+  (void)hipFree(ws->d_idx);
+  (void)hipFree(ws->d_count);
+  (void)hipFree(ws->d_wpre);
+  (void)hipFree(ws->d_me);
+  (void)hipFree(ws->d_amp);
+  delete ws;
+}
+
+#define G3_TRY(expr)                  \
+  do {                                \
+    hipError_t e_ = (expr);           \
+    if (e_ != hipSuccess) return e_;  \
+  } while (0)
+
+template <class R>
+hipError_t integrand(const DevCfg& c, const double* u, int64_t n, double* w, void** wsp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  Ws* ws = static_cast<Ws*>(*wsp);
+  if (!ws) {
+    ws = new Ws();
+    *wsp = ws;
+    G3_TRY(hipMalloc(&ws->d_count, sizeof(int)));
+  }
+  if (ws->cap_n < n) {
+    G3_TRY(hipStreamSynchronize(s));
+    (void)hipFree(ws->d_idx);
+    (void)hipFree(ws->d_wpre);
+    ws->d_idx = nullptr;
+    ws->d_wpre = nullptr;
+    ws->cap_n = 0;
+    G3_TRY(hipMalloc(&ws->d_idx, sizeof(int) * n));
+    G3_TRY(hipMalloc(&ws->d_wpre, sizeof(double) * n));
+    ws->cap_n = n;
+  }
+  hipLaunchKernelGGL(st::k_st_zero, dim3(1), dim3(1), 0, s, ws->d_count);
+  hipLaunchKernelGGL(st::k_st_select<NG>, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, c, u, n, w,
+                     ws->d_wpre, ws->d_idx, ws->d_count);
+  G3_TRY(hipGetLastError());
+  int count = 0;
+  G3_TRY(hipMemcpyAsync(&count, ws->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+  G3_TRY(hipStreamSynchronize(s));
+  if (count <= 0) return hipSuccess;
+  // chunk width: the passing events, up to NCMAX, rounded to the amplitude block
+  int64_t want = count < NCMAX_R<R> ? (int64_t)count : NCMAX_R<R>;
+  want = (want + AWAVE - 1) / AWAVE * AWAVE;
+  if (ws->ld < want) {
+    (void)hipFree(ws->d_amp);
+    (void)hipFree(ws->d_me);
+    ws->d_amp = nullptr;
+    ws->d_me = nullptr;
+    ws->ld = 0;
+    const size_t bytes = sizeof(R) * (size_t)SLICES * NQ * (size_t)want * 4;
+    G3_TRY(hipMalloc(&ws->d_amp, bytes));
+    G3_TRY(hipMalloc(&ws->d_me, sizeof(double) * want));
+    ws->ld = want;
+    ws->amp_bytes = bytes;
+  }
+  const int64_t ld = ws->ld;
+  R* amp = static_cast<R*>(ws->d_amp);
+  // all states in passes of SP, or one state per point in a single pass
+  const bool own = c.helicity != 0;
+  const int NPASS = own ? 1 : STATES / SP, ns = own ? 1 : SP, nsl = 4 * ns;
+  const double inv_den = (c.helicity == 1 ? (double)STATES : 1.0) / AMP_M5_COLOUR_DEN;
+  for (int64_t c0 = 0; c0 < count; c0 += ld) {
+    const int64_t nc = (count - c0) < ld ? (count - c0) : ld;
+    const int* idx = ws->d_idx + c0;
+    const unsigned ablk = (unsigned)((nc + AWAVE - 1) / AWAVE);
+    const int64_t ntile = (nc + (std::is_same<R, float>::value ? CT : CT / 2) - 1) /
+                          (std::is_same<R, float>::value ? CT : CT / 2);
+    const unsigned cblk = (unsigned)(ntile < CMAX_BLOCKS ? ntile : CMAX_BLOCKS);
+    for (int pass = 0; pass < NPASS; ++pass) {
+      hipLaunchKernelGGL((k_g3_amp<R>), dim3(ablk), dim3(AWAVE), 0, s, c, u, n, idx, nc, pass * SP, ns, amp, ld);
+      hipLaunchKernelGGL((k_g3_colour<R>), dim3(cblk), dim3(CBLOCK), 0, s, amp, ld, nc, nsl, pass == 0 ? 1 : 0,
+                         pass == NPASS - 1 ? 1 : 0, ws->d_me, idx, ws->d_wpre, w, inv_den);
+    }
+    G3_TRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+#undef G3_TRY
+
+template <class R>
+Launchers launchers() {
+  Launchers L;
+  L.fused = false;
+  L.integrand = nullptr;
+  L.vegas = nullptr;
+  L.integrand_grad = nullptr;
+  L.grad_vegas = nullptr;
+  L.observables = nullptr;
+  L.integrand_ws = integrand<R>;
+  L.ws_free = ws_free;
+  return L;
 }
 
 }  // namespace g3

@@ -116,6 +116,7 @@ Launchers launchers_uug_f64();
 Launchers launchers_ddg_f64();
 Launchers launchers_qg_f64();
 Launchers launchers_gg3_f32();
+Launchers launchers_gg3_f64();
 // g g -> t t~ g g with the colour sum on the matrix cores (staged kernels)
 Launchers launchers_gg2s_f32();
 Launchers launchers_gg2s_f64();

@@ -618,7 +618,7 @@ Launchers pick_launchers(int ng, int ch, int prec, int colour_form) {
   if (ch == 3) return launchers_qg_f64();
   if (ng == 0) return f32 ? launchers_gg0_f32() : launchers_gg0_f64();
   if (ng == 1) return f32 ? launchers_gg1_f32() : launchers_gg1_f64();
-  if (ng == 3) return launchers_gg3_f32();
+  if (ng == 3) return f32 ? launchers_gg3_f32() : launchers_gg3_f64();
   if (colour_form == 2) return f32 ? launchers_gg2s_f32() : launchers_gg2s_f64();
   return f32 ? launchers_gg2_f32() : launchers_gg2_f64();
 }
@@ -763,8 +763,6 @@ mf_status mf_process_create(const mf_config* cfg, mf_process** out) {
   double mu = cfg->mu > 0.0 ? cfg->mu : cfg->m_t;
   if (!(mu >= PDF_Q0 && mu <= PDF_QMAX)) return fail(MF_ERANGE, "scale %g outside the PDF grid", mu);
   const int ng = n_final_gluons(cfg->process);
-  if (ng == 3 && cfg->precision != MF_PREC_FP32_AMP)
-    return fail(MF_ENOTSUP, "g g -> t t~ g g g is built with FP32 amplitudes only");
   if (cfg->helicity < 0 || cfg->helicity > 2 + 63) return fail(MF_EINVAL, "helicity mode %d", cfg->helicity);
   if (cfg->helicity != 0 && ng != 3)
     return fail(MF_ENOTSUP, "polarisation-state sampling is built for g g -> t t~ g g g only");
