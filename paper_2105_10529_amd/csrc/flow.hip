@@ -40,7 +40,7 @@ constexpr int NOP = 80;       // NO padded to five 16-column MFMA tiles
 constexpr int KA = 32;        // first-layer k width: inputs split as BF16 hi (k < 16) + lo (k >= 16)
 constexpr int KLO = 16;       // offset of the low parts
 constexpr int T = 64;         // events per workgroup of the layer kernel
-constexpr int LDO = NOP + 1;  // LDS row stride (floats) of one coordinate's logits
+constexpr int LDO = 68;       // LDS row stride (floats) of one coordinate's 64 leading logits (16-byte rows)
 constexpr int FMAXD = 16;
 constexpr int MAXL = 8;
 constexpr float SLOPE = 0.01f;
@@ -83,7 +83,21 @@ __device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
 // fall in different banks.
 __device__ __forceinline__ int hs(int m, int k) { return m * H + ((((k >> 3) ^ (m & 15))) << 3) + (k & 7); }
 
-__device__ __forceinline__ float leaky(float v) { return v > 0.0f ? v : SLOPE * v; }
+// The median of (v, 0.01 v, FLT_MAX) is max(v, 0.01 v) for finite v: v for v >= 0 and 0.01 v
+// below, the LeakyReLU in two operations (fmaxf would add a canonicalising
+// instruction per input in IEEE mode)
+__device__ __forceinline__ float leaky(float v) { return __builtin_amdgcn_fmed3f(v, SLOPE * v, 3.40282347e38f); }
+
+// Exchanges inside an aligned group of four lanes through DPP quad
+// permutations (no LDS round trip): lane ^ 1, lane ^ 2, and the group's lane
+// 0, 1 or 2 broadcast to all four.
+constexpr int QX1 = 0xB1, QX2 = 0x4E, QB0 = 0x00, QB1 = 0x55, QB2 = 0xAA;
+template <int CTRL> __device__ __forceinline__ float qdpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ int qdpp(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
 
 // ------------------------------------------------------------ PQ transform
 // Softmax widths and normalised vertex heights from the 2K+1 logits.
@@ -140,83 +154,102 @@ __device__ __forceinline__ Bin find_bin(const float* W, const float* V, float t,
 }
 
 // Epilogue of a transposed dense layer: acc[jt][mt][i] is feature
-// 64 wave + 16 jt + 4 quad + i of event 16 mt + row; adds the bias, applies
-// the LeakyReLU, rounds to BF16 and stores the four features with one 8-byte
-// write into the permuted [T][H] activation tile.
-__device__ __forceinline__ void store_features(bf16* h, const f32x4 (&acc)[4][4], const float* __restrict__ bias,
-                                               int wave, int row, int quad) {
+// 64 wave + 16 jt + 4 quad + i of event 16 mt + row, bias included (it is
+// the accumulator's initial value); applies the LeakyReLU, rounds to BF16 and
+// stores the four features with one 8-byte write into the permuted [T][H]
+// activation tile.
+__device__ __forceinline__ void store_features(bf16* h, const f32x4 (&acc)[4][4], int wave, int row, int quad) {
 #pragma unroll
   for (int jt = 0; jt < 4; ++jt) {
     const int f0 = 64 * wave + 16 * jt + 4 * quad;
-    float bb[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) bb[i] = bias[f0 + i];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
       bf16x4 v;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] = (bf16)leaky(acc[jt][mt][i] + bb[i]);
+      for (int i = 0; i < 4; ++i) v[i] = (bf16)leaky(acc[jt][mt][i]);
       *reinterpret_cast<bf16x4*>(h + hs(16 * mt + row, f0)) = v;
     }
   }
 }
 
+// The bias of the four features 64 wave + 16 jt + 4 quad + i (i = 0..3) as an
+// accumulator tile.
+__device__ __forceinline__ f32x4 bias4(const float* __restrict__ b, int wave, int jt, int quad) {
+  const float* p = b + 64 * wave + 16 * jt + 4 * quad;
+  return f32x4{p[0], p[1], p[2], p[3]};
+}
+
 // The PQ transform of one coordinate with four lanes per event: lane part p
 // holds the bins [8p, 8p+8) and the vertices [8p, 8p+8] of the 2K+1 logits
-// o (in LDS); maxima, sums and the bin's owner are combined with shuffles
-// inside each aligned group of four lanes.  Same bin rule as find_bin: the
-// largest k >= 1 whose left edge (running width, or running area for the
-// sampling direction) is <= t, else 0.  Every lane of the group returns the
-// result (y or z) and the density.
+// (the first 2K in LDS at o, the last one, vlast, in a register of the
+// p = 3 lane); maxima, sums, prefix offsets and the bin's owner are combined
+// with DPP quad exchanges.  Same bin rule as find_bin: the largest k >= 1
+// whose left edge (running width, or running area for the sampling
+// direction) is <= t, else 0.  Every lane of the group returns the result
+// (y or z) and the density.  Reciprocals use the hardware approximation
+// (1 ulp).
 template <bool INVERSE>
-__device__ __forceinline__ void pq_quad(const float* o, float t, int p, int lane, float& res, float& pdf) {
+__device__ __forceinline__ void pq_quad(const float* o, float vlast, float t, int p, float& res, float& pdf) {
   constexpr int KP = KB / 4;
   float w[KP], v[KP + 1];
 #pragma unroll
   for (int k = 0; k < KP; ++k) w[k] = o[KP * p + k];
 #pragma unroll
-  for (int k = 0; k <= KP; ++k) v[k] = o[KB + KP * p + k];
+  for (int k = 0; k < KP; ++k) v[k] = o[KB + KP * p + k];
+  {
+    // the part's last vertex: the next part's first, or the 2K+1-th logit
+    const float vn = o[KB + KP * p + (p < 3 ? KP : 0)];
+    v[KP] = p < 3 ? vn : vlast;
+  }
+  // exp(x - m) as 2^(x log2 e - m log2 e), one FMA and the hardware exp2
+  constexpr float L2E = 1.4426950408889634f;
   float mw = w[0];
 #pragma unroll
   for (int k = 1; k < KP; ++k) mw = fmaxf(mw, w[k]);
-  mw = fmaxf(mw, __shfl_xor(mw, 1));
-  mw = fmaxf(mw, __shfl_xor(mw, 2));
+  mw = fmaxf(mw, qdpp<QX1>(mw));
+  mw = fmaxf(mw, qdpp<QX2>(mw));
+  const float mwl = mw * L2E;
   float sw = 0.0f;
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    w[k] = __expf(w[k] - mw);
+    w[k] = __builtin_amdgcn_exp2f(fmaf(w[k], L2E, -mwl));
     sw += w[k];
   }
-  sw += __shfl_xor(sw, 1);
-  sw += __shfl_xor(sw, 2);
-  const float isw = 1.0f / sw;
+  sw += qdpp<QX1>(sw);
+  sw += qdpp<QX2>(sw);
+  const float isw = __builtin_amdgcn_rcpf(sw);
 #pragma unroll
   for (int k = 0; k < KP; ++k) w[k] *= isw;
   float mv = v[0];
 #pragma unroll
   for (int k = 1; k <= KP; ++k) mv = fmaxf(mv, v[k]);
-  mv = fmaxf(mv, __shfl_xor(mv, 1));
-  mv = fmaxf(mv, __shfl_xor(mv, 2));
+  mv = fmaxf(mv, qdpp<QX1>(mv));
+  mv = fmaxf(mv, qdpp<QX2>(mv));
+  const float mvl = mv * L2E;
 #pragma unroll
-  for (int k = 0; k <= KP; ++k) v[k] = __expf(v[k] - mv);
+  for (int k = 0; k <= KP; ++k) v[k] = __builtin_amdgcn_exp2f(fmaf(v[k], L2E, -mvl));
+  // bin areas with the unnormalised heights, twice over: ar_k = (v_k + v_k+1) w_k
+  float ar[KP];
   float nl = 0.0f;
 #pragma unroll
-  for (int k = 0; k < KP; ++k) nl += 0.5f * (v[k] + v[k + 1]) * w[k];
-  nl += __shfl_xor(nl, 1);
-  nl += __shfl_xor(nl, 2);
-  const float inl = 1.0f / nl;
-#pragma unroll
-  for (int k = 0; k <= KP; ++k) v[k] *= inl;
-  // exclusive offsets of the running width and area at the part's first bin
-  float sp = 0.0f, ap = 0.0f;
-#pragma unroll
   for (int k = 0; k < KP; ++k) {
-    sp += w[k];
-    ap += 0.5f * (v[k] + v[k + 1]) * w[k];
+    ar[k] = (v[k] + v[k + 1]) * w[k];
+    nl += ar[k];
   }
-  const int base = lane & ~3;
-  const float s0 = __shfl(sp, base), s1 = __shfl(sp, base + 1), s2 = __shfl(sp, base + 2);
-  const float a0 = __shfl(ap, base), a1 = __shfl(ap, base + 1), a2 = __shfl(ap, base + 2);
+  const float part_area = nl;
+  nl += qdpp<QX1>(nl);
+  nl += qdpp<QX2>(nl);
+  // the heights are divided by the total area sum ar / 2; a bin's area is
+  // then ar_k / sum ar
+  const float iar = __builtin_amdgcn_rcpf(nl);
+  const float inl = 2.0f * iar;
+  // exclusive offsets of the running width and area at the part's first bin
+  float sp = 0.0f;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) sp += w[k];
+  const float ap = part_area * iar;
+  const float s0 = qdpp<QB0>(sp), s1 = qdpp<QB1>(sp), s2 = qdpp<QB2>(sp);
+  const float a0 = qdpp<QB0>(ap), a1 = qdpp<QB1>(ap), a2 = qdpp<QB2>(ap);
   float S = (p > 0 ? s0 : 0.0f) + (p > 1 ? s1 : 0.0f) + (p > 2 ? s2 : 0.0f);
   float A = (p > 0 ? a0 : 0.0f) + (p > 1 ? a1 : 0.0f) + (p > 2 ? a2 : 0.0f);
   int bl = -1;
@@ -232,42 +265,76 @@ __device__ __forceinline__ void pq_quad(const float* o, float t, int p, int lane
     Vb = take ? v[k] : Vb;
     Vb1 = take ? v[k + 1] : Vb1;
     S += w[k];
-    A += 0.5f * (v[k] + v[k + 1]) * w[k];
+    A += ar[k] * iar;
   }
+  Vb *= inl;
+  Vb1 *= inl;
   int b = bl;
-  b = max(b, __shfl_xor(b, 1));
-  b = max(b, __shfl_xor(b, 2));
+  b = max(b, qdpp<QX1>(b));
+  b = max(b, qdpp<QX2>(b));
   const float dV = Vb1 - Vb;
+  const float iW = __builtin_amdgcn_rcpf(Wb);
   float r, q;
   if (!INVERSE) {
-    const float al = fminf(fmaxf((t - Sb) / Wb, 0.0f), 1.0f);
+    const float al = fminf(fmaxf((t - Sb) * iW, 0.0f), 1.0f);
     r = Ab + Wb * (al * Vb + 0.5f * al * al * dV);
     q = Vb + al * dV;
   } else {
-    const float cc = (t - Ab) / Wb;
+    const float cc = (t - Ab) * iW;
     const float disc = fmaxf(Vb * Vb + 2.0f * dV * cc, 0.0f);
-    float al = 2.0f * cc / (Vb + sqrtf(disc));
+    float al = 2.0f * cc * __builtin_amdgcn_rcpf(Vb + sqrtf(disc));
     al = fminf(fmaxf(al, 0.0f), 1.0f);
     r = Sb + al * Wb;
     q = Vb + al * dV;
   }
-  const int owner = base + b / KP;
-  res = __shfl(r, owner);
-  pdf = __shfl(q, owner);
+  // only the owner of bin b holds the right values: a sum over the group
+  // with the other three lanes contributing exact zeros
+  const bool own = b / KP == p;
+  float rr = own ? r : 0.0f, qq = own ? q : 0.0f;
+  rr += qdpp<QX1>(rr);
+  qq += qdpp<QX1>(qq);
+  res = rr + qdpp<QX2>(rr);
+  pdf = qq + qdpp<QX2>(qq);
 }
 
 // --------------------------------------------------------- coupling layer
+// Copy of the [T][H] activation tile into an event-contiguous cache: eight
+// events of one feature per 16-byte store.
+__device__ __forceinline__ void cache_hidden(const bf16* h, bf16* __restrict__ dst, int64_t ldn, int64_t e0,
+                                             int64_t n, int tid) {
+  for (int idx = tid; idx < H * (T / 8); idx += 256) {
+    const int ch = idx % (T / 8), f = idx / (T / 8);
+    const int m0 = 8 * ch;
+    const int64_t e = e0 + m0;
+    if (e >= n) continue;
+    bf16x8 v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = h[hs(m0 + i, f)];
+    if (e + 8 <= n) {
+      *reinterpret_cast<bf16x8*>(dst + (int64_t)f * ldn + e) = v;
+    } else {
+      for (int i = 0; e + i < n; ++i) dst[(int64_t)f * ldn + e + i] = v[i];
+    }
+  }
+}
+
 // One layer for events [64 blockIdx.x, +64): y is [d][ld] (n <= ld events
 // used) and is transformed in place (the kept coordinates are only read).
 // INVERSE selects the sampling direction.  logq[e] is set (first layer) or
 // accumulated.  The caches use row length n.
+//
+// LDS: one [T][H] BF16 tile that holds the first hidden layer and then the
+// second (written over the first once every wave has read it), and one
+// [T][LDO] FP32 tile for the 64 leading logits of the current coordinate
+// (before that, its first 4 KB hold the first-layer inputs): 49.0 KiB, so
+// that three workgroups share a compute unit.
 template <bool INVERSE, bool CACHE>
-__global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict__ y, int64_t n, int64_t ld,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE ? 2 : 3))) k_coupling(LayerDev L, float* __restrict__ y, int64_t n, int64_t ld,
                                                   float* __restrict__ logq, int first, LayerCache C, int d) {
-  __shared__ __attribute__((aligned(16))) bf16 h1[T * H];  // also the logits of one coordinate (FP32)
-  __shared__ __attribute__((aligned(16))) bf16 h2[T * H];  // also the first-layer inputs
-  bf16* xa = h2;                                           // [T][KA]
-  float* out = reinterpret_cast<float*>(h1);               // [T][LDO]
+  __shared__ __attribute__((aligned(16))) bf16 h[T * H];
+  __shared__ __attribute__((aligned(16))) float out[T * LDO];
+  static_assert(T * KA * sizeof(bf16) <= T * LDO * sizeof(float), "first-layer inputs must fit the logit tile");
+  bf16* xa = reinterpret_cast<bf16*>(out);  // [T][KA]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t e0 = (int64_t)blockIdx.x * T;
   const int row = lane & 15, quad = lane >> 4;
@@ -316,18 +383,23 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
       b[mt] = *reinterpret_cast<const bf16x8*>(xa + m * KA + ((quad ^ (m & 3)) << 3));
     }
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt)
+    for (int jt = 0; jt < 4; ++jt) {
+      const f32x4 bias = bias4(L.b1, wave, jt, quad);
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = mfma16(a[jt], b[mt], f32x4{0.0f, 0.0f, 0.0f, 0.0f});
-    store_features(h1, acc, L.b1, wave, row, quad);
+      for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = mfma16(a[jt], b[mt], bias);
+    }
+    store_features(h, acc, wave, row, quad);
   }
   __syncthreads();
+  if (CACHE) cache_hidden(h, C.h1, C.ldn, e0, n, tid);
   {
     f32x4 acc[4][4];
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt)
+    for (int jt = 0; jt < 4; ++jt) {
+      const f32x4 bias = bias4(L.b2, wave, jt, quad);
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = bias;
+    }
     const bf16* W2 = L.W2t + (64 * wave + row) * H + 8 * quad;
 #pragma unroll
     for (int ks = 0; ks < H / 32; ++ks) {
@@ -336,110 +408,99 @@ __global__ void __launch_bounds__(256) k_coupling(LayerDev L, float* __restrict_
       for (int jt = 0; jt < 4; ++jt) a[jt] = *reinterpret_cast<const bf16x8*>(W2 + 16 * jt * H + 32 * ks);
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
-        b[mt] = *reinterpret_cast<const bf16x8*>(h1 + hs(16 * mt + row, 32 * ks + 8 * quad));
+        b[mt] = *reinterpret_cast<const bf16x8*>(h + hs(16 * mt + row, 32 * ks + 8 * quad));
 #pragma unroll
       for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = mfma16(a[jt], b[mt], acc[jt][mt]);
     }
-    store_features(h2, acc, L.b2, wave, row, quad);
+    // every wave has read the first layer (and the cache copy is done)
+    // before the second overwrites it
+    __syncthreads();
+    store_features(h, acc, wave, row, quad);
   }
   __syncthreads();
-  if (CACHE) {
-    // event-contiguous copies: eight events of one feature per 16-byte store
-    for (int idx = tid; idx < H * (T / 8); idx += 256) {
-      const int ch = idx % (T / 8), f = idx / (T / 8);
-      const int m0 = 8 * ch;
-      const int64_t e = e0 + m0;
-      if (e >= n) continue;
-      bf16x8 v1, v2;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        v1[i] = h1[hs(m0 + i, f)];
-        v2[i] = h2[hs(m0 + i, f)];
-      }
-      if (e + 8 <= n) {
-        *reinterpret_cast<bf16x8*>(C.h1 + (int64_t)f * C.ldn + e) = v1;
-        *reinterpret_cast<bf16x8*>(C.h2 + (int64_t)f * C.ldn + e) = v2;
-      } else {
-        for (int i = 0; e + i < n; ++i) {
-          C.h1[(int64_t)f * C.ldn + e + i] = v1[i];
-          C.h2[(int64_t)f * C.ldn + e + i] = v2[i];
-        }
-      }
-    }
-    __syncthreads();
-  }
+  if (CACHE) cache_hidden(h, C.h2, C.ldn, e0, n, tid);
 
   // The 65th logit of every transformed coordinate at once: one more MFMA
   // tile per wave, D[coordinate][event] for the wave's 16 events, with the
   // weight rows of the coordinates' last outputs as A fragments (rows past
-  // d_B are zero).  Kept in LDS after the logits of one coordinate.
-  float* last = out + T * LDO;  // [T][16]
+  // d_B repeat coordinate 0 and are never read).  Lane l keeps coordinates
+  // 4 (l >> 4) + i of event 16 wave + (l & 15) in registers until their PQ
+  // transforms.
+  f32x4 lastv = {0.0f, 0.0f, 0.0f, 0.0f};
   {
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    const bool live = row < L.dB;
-    const bf16* wl = L.W3t + ((int64_t)(live ? row : 0) * NOP + 2 * KB) * H + 8 * quad;
+    const bf16* wl = L.W3t + ((int64_t)(row < L.dB ? row : 0) * NOP + 2 * KB) * H + 8 * quad;
 #pragma unroll
     for (int ks = 0; ks < H / 32; ++ks) {
-      bf16x8 a = *reinterpret_cast<const bf16x8*>(wl + 32 * ks);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) a[i] = live ? a[i] : (bf16)0.0f;
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(h2 + hs(16 * wave + row, 32 * ks + 8 * quad));
-      acc = mfma16(a, b, acc);
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(wl + 32 * ks);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(h + hs(16 * wave + row, 32 * ks + 8 * quad));
+      lastv = mfma16(a, b, lastv);
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) last[(16 * wave + row) * 16 + 4 * quad + i] = acc[i];
   }
-  __syncthreads();
 
   // dense layer 3 and the PQ transform, one transformed coordinate at a time:
   // the 64 leading logits of a coordinate are four 16-column MFMA tiles, one
   // per wave over all 64 events (each wave streams only its own weight
   // columns).
   float lq = 0.0f;
+  // the eight weight fragments of this wave's columns of coordinate c; those
+  // of coordinate c + 1 are requested before the PQ transform of c, so their
+  // L2 latency overlaps it
+  bf16x8 bw[H / 32];
+  {
+    const bf16* W3 = L.W3t + ((int64_t)(16 * wave + row)) * H + 8 * quad;
+#pragma unroll
+    for (int ks = 0; ks < H / 32; ++ks) bw[ks] = *reinterpret_cast<const bf16x8*>(W3 + 32 * ks);
+  }
+  // the PQ transform's event (16 per wave, four lanes each) and part
+  const int m = tid >> 2, part = tid & 3;
+  const int64_t em = e0 + m;
+  const bool live = em < n;
   for (int c = 0; c < L.dB; ++c) {
     {
+      const int col = 16 * wave + row;
+      const float bias = L.b3p[c * NOP + col];
       f32x4 acc[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      // all eight weight fragments of this wave's columns are requested first
-      const bf16* W3 = L.W3t + ((int64_t)c * NOP + 16 * wave + row) * H + 8 * quad;
-      bf16x8 bw[H / 32];
-#pragma unroll
-      for (int ks = 0; ks < H / 32; ++ks) bw[ks] = *reinterpret_cast<const bf16x8*>(W3 + 32 * ks);
+      for (int r = 0; r < 4; ++r) acc[r] = f32x4{bias, bias, bias, bias};
 #pragma unroll
       for (int ks = 0; ks < H / 32; ++ks) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(h2 + hs(16 * r + row, 32 * ks + 8 * quad));
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(h + hs(16 * r + row, 32 * ks + 8 * quad));
           acc[r] = mfma16(a, bw[ks], acc[r]);
         }
       }
-      const int col = 16 * wave + row;
-      const float bias = L.b3p[c * NOP + col];
+      if (c + 1 < L.dB) {
+        const bf16* W3 = L.W3t + ((int64_t)(c + 1) * NOP + 16 * wave + row) * H + 8 * quad;
+#pragma unroll
+        for (int ks = 0; ks < H / 32; ++ks) bw[ks] = *reinterpret_cast<const bf16x8*>(W3 + 32 * ks);
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[(16 * r + 4 * quad + i) * LDO + col] = acc[r][i] + bias;
-      if (tid < T) out[tid * LDO + 2 * KB] = last[tid * 16 + c] + L.b3p[c * NOP + 2 * KB];
+        for (int i = 0; i < 4; ++i) out[(16 * r + 4 * quad + i) * LDO + col] = acc[r][i];
     }
+    // the 65th logit of (event m, coordinate c) from the lane of this wave
+    // that holds it
+    const int ci = c & 3;
+    const float lsel = ci == 0 ? lastv[0] : ci == 1 ? lastv[1] : ci == 2 ? lastv[2] : lastv[3];
+    const float vlast = __shfl(lsel, (lane >> 2) + 16 * (c >> 2)) + L.b3p[c * NOP + 2 * KB];
     __syncthreads();
     if (CACHE) {
-      for (int idx = tid; idx < T * NO; idx += 256) {
-        const int m = idx / NO, col = idx % NO;
-        const int64_t e = e0 + m;
-        if (e < n) C.o[(e * L.dB + c) * NOP + col] = out[m * LDO + col];
+      for (int idx = tid; idx < T * 2 * KB; idx += 256) {
+        const int mm = idx / (2 * KB), col = idx % (2 * KB);
+        const int64_t e = e0 + mm;
+        if (e < n) C.o[(e * L.dB + c) * NOP + col] = out[mm * LDO + col];
       }
+      if (live && part == 3) C.o[(em * L.dB + c) * NOP + 2 * KB] = vlast;
     }
     {
-      const int m = tid >> 2, part = tid & 3;
-      const int64_t e = e0 + m;
-      const bool live = e < n;
-      float* yp = y + (int64_t)L.b_idx[c] * ld + (live ? e : e0);
+      float* yp = y + (int64_t)L.b_idx[c] * ld + (live ? em : e0);
       const float t = live ? *yp : 0.5f;
       float res, pdf;
-      pq_quad<INVERSE>(out + m * LDO, t, part, lane, res, pdf);
+      pq_quad<INVERSE>(out + m * LDO, vlast, t, part, res, pdf);
       if (live && part == 0) {
         *yp = res;
         lq += __logf(pdf);
