@@ -102,12 +102,37 @@ __device__ __forceinline__ V4<R> v3(const V4<R>& X, const V4<R>& Y, const V4<R>&
   return V4<R>{a * X.t + c * (PY.t - PX.t) - d * Y.t, a * X.x + c * (PY.x - PX.x) - d * Y.x,
                a * X.y + c * (PY.y - PX.y) - d * Y.y, a * X.z + c * (PY.z - PX.z) - d * Y.z};
 }
+// o + v3(X, Y, PX, PY): the vertex added into an accumulated current, each
+// component one chain of fused multiply-adds (sums of vertices are formed
+// this way instead of adding separately rounded vertices).
+template <class R>
+__device__ __forceinline__ V4<R> v3_acc(const V4<R>& X, const V4<R>& Y, const V4<R>& PX, const V4<R>& PY, V4<R> o) {
+  R a = R(2.0) * mdot(PX, Y) + mdot(PY, Y);
+  R d = mdot(PX, X) + R(2.0) * mdot(PY, X);
+  R c = mdot(X, Y);
+  o.t = ((o.t + a * X.t) + c * (PY.t - PX.t)) - d * Y.t;
+  o.x = ((o.x + a * X.x) + c * (PY.x - PX.x)) - d * Y.x;
+  o.y = ((o.y + a * X.y) + c * (PY.y - PX.y)) - d * Y.y;
+  o.z = ((o.z + a * X.z) + c * (PY.z - PX.z)) - d * Y.z;
+  return o;
+}
 // Colour-ordered four-gluon vertex with three adjacent currents:
 //   2B(A.C) - A(B.C) - C(A.B)
 template <class R> __device__ __forceinline__ V4<R> w4(const V4<R>& A, const V4<R>& B, const V4<R>& C) {
   R ac = R(2.0) * mdot(A, C), bc = mdot(B, C), ab = mdot(A, B);
   return V4<R>{ac * B.t - bc * A.t - ab * C.t, ac * B.x - bc * A.x - ab * C.x, ac * B.y - bc * A.y - ab * C.y,
                ac * B.z - bc * A.z - ab * C.z};
+}
+
+// o - w4(A, B, C) as chains of fused multiply-adds.
+template <class R>
+__device__ __forceinline__ V4<R> w4_sub(const V4<R>& A, const V4<R>& B, const V4<R>& C, V4<R> o) {
+  R ac = R(2.0) * mdot(A, C), bc = mdot(B, C), ab = mdot(A, B);
+  o.t = ((o.t - ac * B.t) + bc * A.t) + ab * C.t;
+  o.x = ((o.x - ac * B.x) + bc * A.x) + ab * C.x;
+  o.y = ((o.y - ac * B.y) + bc * A.y) + ab * C.y;
+  o.z = ((o.z - ac * B.z) + bc * A.z) + ab * C.z;
+  return o;
 }
 
 // ---------------------------------------------------------------- complex
@@ -122,6 +147,11 @@ template <class R> __device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b) {
 template <class R> __device__ __forceinline__ R cabs2(C2<R> a) { return a.re * a.re + a.im * a.im; }
 // Re(a^* b)
 template <class R> __device__ __forceinline__ R cre_dot(C2<R> a, C2<R> b) { return a.re * b.re + a.im * b.im; }
+// acc + |a|^2 and acc + Re(a^* b), two fused multiply-adds each
+template <class R> __device__ __forceinline__ R cabs2_acc(C2<R> a, R acc) { return (acc + a.re * a.re) + a.im * a.im; }
+template <class R> __device__ __forceinline__ R cre_dot_acc(C2<R> a, C2<R> b, R acc) {
+  return (acc + a.re * b.re) + a.im * b.im;
+}
 
 // ---------------------------------------------------------------- spinors
 template <class R> struct Sp {
@@ -143,6 +173,33 @@ template <class R> __device__ __forceinline__ Sp<R> slash(const V4<R>& J, const 
   o.s3 = C2<R>{a * p.s1.re + (c * p.s0.re - d * p.s0.im), a * p.s1.im + (c * p.s0.im + d * p.s0.re)};
   return o;
 }
+// o + slash(J) psi, each component one chain of fused multiply-adds.
+template <class R> __device__ __forceinline__ Sp<R> slash_acc(const V4<R>& J, const Sp<R>& p, Sp<R> o) {
+  R a = J.t - J.z, b = J.t + J.z, c = J.x, d = J.y;
+  o.s0.re = ((o.s0.re + a * p.s2.re) - c * p.s3.re) - d * p.s3.im;
+  o.s0.im = ((o.s0.im + a * p.s2.im) - c * p.s3.im) + d * p.s3.re;
+  o.s1.re = ((o.s1.re + b * p.s3.re) - c * p.s2.re) + d * p.s2.im;
+  o.s1.im = ((o.s1.im + b * p.s3.im) - c * p.s2.im) - d * p.s2.re;
+  o.s2.re = ((o.s2.re + b * p.s0.re) + c * p.s1.re) + d * p.s1.im;
+  o.s2.im = ((o.s2.im + b * p.s0.im) + c * p.s1.im) - d * p.s1.re;
+  o.s3.re = ((o.s3.re + a * p.s1.re) + c * p.s0.re) - d * p.s0.im;
+  o.s3.im = ((o.s3.im + a * p.s1.im) + c * p.s0.im) + d * p.s0.re;
+  return o;
+}
+// fm phi + slash(J) phi with the slash given by its coefficients
+// a = J0 - J3, b = J0 + J3, c = J1, d = J2 (already scaled by the caller).
+template <class R> __device__ __forceinline__ Sp<R> pslash(R fm, R a, R b, R c, R d, const Sp<R>& p) {
+  Sp<R> o;
+  o.s0.re = ((fm * p.s0.re + a * p.s2.re) - c * p.s3.re) - d * p.s3.im;
+  o.s0.im = ((fm * p.s0.im + a * p.s2.im) - c * p.s3.im) + d * p.s3.re;
+  o.s1.re = ((fm * p.s1.re + b * p.s3.re) - c * p.s2.re) + d * p.s2.im;
+  o.s1.im = ((fm * p.s1.im + b * p.s3.im) - c * p.s2.im) - d * p.s2.re;
+  o.s2.re = ((fm * p.s2.re + b * p.s0.re) + c * p.s1.re) + d * p.s1.im;
+  o.s2.im = ((fm * p.s2.im + b * p.s0.im) + c * p.s1.im) - d * p.s1.re;
+  o.s3.re = ((fm * p.s3.re + a * p.s1.re) + c * p.s0.re) - d * p.s0.im;
+  o.s3.im = ((fm * p.s3.im + a * p.s1.im) + c * p.s0.im) + d * p.s0.re;
+  return o;
+}
 template <class R> __device__ __forceinline__ void opaque_sp(Sp<R>& p) {
   opaque(p.s0.re);
   opaque(p.s0.im);
@@ -153,19 +210,36 @@ template <class R> __device__ __forceinline__ void opaque_sp(Sp<R>& p) {
   opaque(p.s3.re);
   opaque(p.s3.im);
 }
-// Fermion propagator applied to an off-shell spinor: f * (Qslash + m) phi.
+// Fermion propagator applied to an off-shell spinor: f * (Qslash + m) phi,
+// with f folded into the slash coefficients and the mass.
 template <class R> __device__ __forceinline__ Sp<R> prop(const V4<R>& Q, R m, R f, const Sp<R>& phi) {
-  Sp<R> q = slash(Q, phi);
-  Sp<R> o;
-  o.s0 = C2<R>{f * (q.s0.re + m * phi.s0.re), f * (q.s0.im + m * phi.s0.im)};
-  o.s1 = C2<R>{f * (q.s1.re + m * phi.s1.re), f * (q.s1.im + m * phi.s1.im)};
-  o.s2 = C2<R>{f * (q.s2.re + m * phi.s2.re), f * (q.s2.im + m * phi.s2.im)};
-  o.s3 = C2<R>{f * (q.s3.re + m * phi.s3.re), f * (q.s3.im + m * phi.s3.im)};
-  return o;
+  return pslash(f * m, f * (Q.t - Q.z), f * (Q.t + Q.z), f * Q.x, f * Q.y, phi);
 }
-// Row spinor (ubar) times column spinor.
+// The same for Q = -P: f * (m - Pslash) phi.
+template <class R> __device__ __forceinline__ Sp<R> prop_neg(const V4<R>& P, R m, R f, const Sp<R>& phi) {
+  const R g = R(0.0) - f;
+  return pslash(f * m, g * (P.t - P.z), g * (P.t + P.z), g * P.x, g * P.y, phi);
+}
+// Row spinor (ubar) times column spinor, real and imaginary parts as single
+// chains of fused multiply-adds.
 template <class R> __device__ __forceinline__ C2<R> ubar_dot(const Sp<R>& u, const Sp<R>& p) {
-  return cmul(u.s0, p.s0) + cmul(u.s1, p.s1) + cmul(u.s2, p.s2) + cmul(u.s3, p.s3);
+  R re = u.s0.re * p.s0.re;
+  re = re - u.s0.im * p.s0.im;
+  re = re + u.s1.re * p.s1.re;
+  re = re - u.s1.im * p.s1.im;
+  re = re + u.s2.re * p.s2.re;
+  re = re - u.s2.im * p.s2.im;
+  re = re + u.s3.re * p.s3.re;
+  re = re - u.s3.im * p.s3.im;
+  R im = u.s0.re * p.s0.im;
+  im = im + u.s0.im * p.s0.re;
+  im = im + u.s1.re * p.s1.im;
+  im = im + u.s1.im * p.s1.re;
+  im = im + u.s2.re * p.s2.im;
+  im = im + u.s2.im * p.s2.re;
+  im = im + u.s3.re * p.s3.im;
+  im = im + u.s3.im * p.s3.re;
+  return C2<R>{re, im};
 }
 
 // ------------------------------------------------- external wavefunctions

@@ -89,26 +89,15 @@ __device__ __forceinline__ void gluon_stage(V4<R> (&J)[5][5], V4<R> (&P)[5][5], 
     if (SUFFIX != (a >= 2)) continue;
     const int b = a + len - 1;
     P[a][b] = P[a][b - 1] + P[b][b];
-    V4<R> t3 = v3(J[a][a], J[a + 1][b], P[a][a], P[a + 1][b]);
+    // the vertices accumulate into one current (fused multiply-add chains)
+    V4<R> t = v3(J[a][a], J[a + 1][b], P[a][a], P[a + 1][b]);
 #pragma unroll
-    for (int j = a + 1; j < b; ++j) t3 = t3 + v3(J[a][j], J[j + 1][b], P[a][j], P[j + 1][b]);
-    if (b - a >= 2) {
-      V4<R> t4 = w4(J[a][a], J[a + 1][a + 1], J[a + 2][b]);
-      bool first = true;
+    for (int j = a + 1; j < b; ++j) t = v3_acc(J[a][j], J[j + 1][b], P[a][j], P[j + 1][b], t);
 #pragma unroll
-      for (int j = a; j < b - 1; ++j)
+    for (int j = a; j < b - 1; ++j)
 #pragma unroll
-        for (int l = j + 1; l < b; ++l) {
-          if (first) {
-            first = false;
-            continue;
-          }
-          t4 = t4 + w4(J[a][j], J[j + 1][l], J[l + 1][b]);
-        }
-      J[a][b] = g[r] * (t3 - t4);
-    } else {
-      J[a][b] = g[r] * t3;
-    }
+      for (int l = j + 1; l < b; ++l) t = w4_sub(J[a][j], J[j + 1][l], J[l + 1][b], t);
+    J[a][b] = g[r] * t;
   }
 }
 
@@ -121,13 +110,13 @@ __device__ __forceinline__ void spinor_stage(const V4<R> (&J)[5][5], const V4<R>
     if (SUFFIX != (a >= 2)) continue;
     Sp<R> acc = slash(J[a][a], S[a + 1]);
 #pragma unroll
-    for (int j = a + 1; j < 5; ++j) acc = acc + slash(J[a][j], S[j + 1]);
-    S[a] = prop(R(-1.0) * (pb + P[a][4]), MT, iq[a - 1], acc);
+    for (int j = a + 1; j < 5; ++j) acc = slash_acc(J[a][j], S[j + 1], acc);
+    S[a] = prop_neg(pb + P[a][4], MT, iq[a - 1], acc);
   }
   if (!SUFFIX) {
     Sp<R> F = slash(J[0][0], S[1]);
 #pragma unroll
-    for (int j = 1; j < 5; ++j) F = F + slash(J[0][j], S[j + 1]);
+    for (int j = 1; j < 5; ++j) F = slash_acc(J[0][j], S[j + 1], F);
     A0 = ubar_dot(UB[0], F);
     A1 = ubar_dot(UB[1], F);
   }

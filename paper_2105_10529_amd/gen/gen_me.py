@@ -194,11 +194,54 @@ def _mask(seq):
     return sum(1 << i for i in seq)
 
 
+def _vsum(t3, t4):
+    """Sum of three-gluon vertices minus four-gluon vertices as one nested
+    accumulation (v3, then v3_acc for the other v3 terms, then w4_sub): every
+    component is a single chain of fused multiply-adds.  t3: tuples
+    (X, Y, PX, PY); t4: tuples (A, B, C)."""
+    e = f"v3({', '.join(t3[0])})"
+    for a in t3[1:]:
+        e = f"v3_acc({', '.join(a)}, {e})"
+    for a in t4:
+        e = f"w4_sub({', '.join(a)}, {e})"
+    return e
+
+
+def _ssum(terms):
+    """Sum of slashed currents on spinors, (J, S) tuples, as one accumulation."""
+    e = f"slash({terms[0][0]}, {terms[0][1]})"
+    for J_, S_ in terms[1:]:
+        e = f"slash_acc({J_}, {S_}, {e})"
+    return e
+
+
+def _colour_lines(w, ind, groups, name):
+    """total += sum over coefficient groups c * (sum of |A_i|^2 or
+    Re(A_i^* A_j)); each group's sum is one chain of fused multiply-adds.
+    name(i) is the amplitude variable of ordering i."""
+    for c, lst in sorted(groups.items()):
+        calls = []
+        for k_, (i, j) in enumerate(lst):
+            if k_ == 0:
+                first = f"cabs2({name(i)})" if i == j else f"cre_dot({name(i)}, {name(j)})"
+                continue
+            calls.append(f"s = cabs2_acc({name(i)}, s);" if i == j else f"s = cre_dot_acc({name(i)}, {name(j)}, s);")
+        w(f"{ind}{{")
+        w(f"{ind}  R s = {first};")
+        for q in range(0, len(calls), 3):
+            w(f"{ind}  " + " ".join(calls[q:q + 3]))
+        w(f"{ind}  total = total + R({c}.0) * s;")
+        w(f"{ind}}}")
+
+
 # Real-flop cost of each device routine in amp.h (a fused multiply-add counts
 # as two flops): Minkowski product 7; v3 63; w4 42; scaling a four-vector 4;
-# adding four-vectors 4; slash(real J, spinor) 42; prop 66; adding spinors 8;
-# ubar_dot 30; cabs2 and cre_dot 3.
-COST = {"v3": 63, "w4": 42, "vscale": 4, "vadd": 4, "slash": 42, "prop": 66, "sadd": 8, "ubar": 30,
+# adding four-vectors 4; slash(real J, spinor) 42; prop 63 (five coefficient
+# products, two sums, then 8 x (one product + three fused multiply-adds));
+# adding spinors 8; ubar_dot 30; cabs2 and cre_dot 3.  The accumulating forms
+# (v3_acc, w4_sub, slash_acc, cabs2_acc, cre_dot_acc) cost exactly the plain
+# routine plus the addition they absorb.
+COST = {"v3": 63, "w4": 42, "vscale": 4, "vadd": 4, "slash": 42, "prop": 63, "sadd": 8, "ubar": 30,
         "abs2": 3, "redot": 3, "mdot": 7}
 
 
@@ -275,16 +318,13 @@ def emit_me(m: int, with_cost: bool = False):
         terms3 = []
         for j in range(1, len(seq)):
             a, b = seq[:j], seq[j:]
-            terms3.append(f"v3({need_J(a)}, {need_J(b)}, P{_mask(a)}, P{_mask(b)})")
+            terms3.append((need_J(a), need_J(b), f"P{_mask(a)}", f"P{_mask(b)}"))
         terms4 = []
         for j in range(1, len(seq) - 1):
             for l in range(j + 1, len(seq)):
                 a, b, c = seq[:j], seq[j:l], seq[l:]
-                terms4.append(f"w4({need_J(a)}, {need_J(b)}, {need_J(c)})")
-        expr = " + ".join(terms3)
-        if terms4:
-            expr = f"({expr}) - (" + " + ".join(terms4) + ")"
-        w(f"{ind}const V4<R> {nm} = G{_mask(seq)} * ({expr});")
+                terms4.append((need_J(a), need_J(b), need_J(c)))
+        w(f"{ind}const V4<R> {nm} = G{_mask(seq)} * ({_vsum(terms3, terms4)});")
         c_ = (len(terms3) * COST["v3"] + len(terms4) * COST["w4"]
               + (len(terms3) + len(terms4) - 1) * COST["vadd"] + COST["vscale"])
         cost["body"] += c_
@@ -299,9 +339,9 @@ def emit_me(m: int, with_cost: bool = False):
         terms = []
         for j in range(1, len(seq) + 1):
             a, b = seq[:j], seq[j:]
-            terms.append(f"slash({need_J(a)}, {need_S(b)})")
+            terms.append((need_J(a), need_S(b)))
         s_ = _mask(seq)
-        w(f"{ind}const Sp<R> {nm} = prop(Q{s_}, MT, IQ{s_}, " + " + ".join(terms) + ");")
+        w(f"{ind}const Sp<R> {nm} = prop(Q{s_}, MT, IQ{s_}, {_ssum(terms)});")
         cost["body"] += len(terms) * COST["slash"] + (len(terms) - 1) * COST["sadd"] + COST["prop"]
         emitted.add(nm)
         return nm
@@ -310,8 +350,8 @@ def emit_me(m: int, with_cost: bool = False):
         terms = []
         for j in range(1, m + 1):
             a, b = seq[:j], seq[j:]
-            terms.append(f"slash({need_J(a)}, {need_S(b)})")
-        w(f"{ind}const Sp<R> F{k} = " + " + ".join(terms) + ";")
+            terms.append((need_J(a), need_S(b)))
+        w(f"{ind}const Sp<R> F{k} = {_ssum(terms)};")
         cost["body"] += len(terms) * COST["slash"] + (len(terms) - 1) * COST["sadd"]
         for t in range(2):
             w(f"{ind}const C2<R> A{t}_{k} = ubar_dot(UB[{t}], F{k});")
@@ -322,17 +362,9 @@ def emit_me(m: int, with_cost: bool = False):
             c = Z[i][j] * (1 if i == j else 2)
             groups.setdefault(c, []).append((i, j))
     for t in range(2):
-        parts = []
+        _colour_lines(w, ind, groups, lambda i, t=t: f"A{t}_{i}")
         for c, lst in sorted(groups.items()):
-            terms = []
-            for (i, j) in lst:
-                if i == j:
-                    terms.append(f"cabs2(A{t}_{i})")
-                else:
-                    terms.append(f"cre_dot(A{t}_{i}, A{t}_{j})")
-            parts.append(f"R({c}.0) * (" + " + ".join(terms) + ")")
-            cost["body"] += 3 * len(terms) + (len(terms) - 1) + 2
-        w(f"{ind}total = total + (" + f"\n{ind}    + ".join(parts) + ");")
+            cost["body"] += 3 * len(lst) + (len(lst) - 1) + 2
     w("    }")
     w("  }")
     w(f"  return total * R(1.0 / {den}.0);")
@@ -446,13 +478,10 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False) -> str:
             nm = f"J{_name(sq)}"
             if nm in done:
                 return nm
-            t3 = [f"v3({J(sq[:j])}, {J(sq[j:])}, {P(sq[:j])}, {P(sq[j:])})" for j in range(1, len(sq))]
-            t4 = [f"w4({J(sq[:j])}, {J(sq[j:l])}, {J(sq[l:])})" for j in range(1, len(sq) - 1)
+            t3 = [(J(sq[:j]), J(sq[j:]), P(sq[:j]), P(sq[j:])) for j in range(1, len(sq))]
+            t4 = [(J(sq[:j]), J(sq[j:l]), J(sq[l:])) for j in range(1, len(sq) - 1)
                   for l in range(j + 1, len(sq))]
-            expr = " + ".join(t3)
-            if t4:
-                expr = f"({expr}) - (" + " + ".join(t4) + ")"
-            w(f"{ii}const V4<R> {nm} = G{_mask(sq)} * ({expr});")
+            w(f"{ii}const V4<R> {nm} = G{_mask(sq)} * ({_vsum(t3, t4)});")
             done.add(nm)
             return nm
 
@@ -460,9 +489,9 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False) -> str:
             nm = f"S{hs}_{_name(sq)}"
             if nm in done:
                 return nm
-            terms = [f"slash({J(sq[:j])}, {S(sq[j:], hs)})" for j in range(1, len(sq) + 1)]
+            terms = [(J(sq[:j]), S(sq[j:], hs)) for j in range(1, len(sq) + 1)]
             s_ = _mask(sq)
-            w(f"{ii}const Sp<R> {nm} = prop(R(-1.0) * (pb + {P(sq)}), MT, IQ{s_}, " + " + ".join(terms) + ");")
+            w(f"{ii}const Sp<R> {nm} = prop_neg(pb + {P(sq)}, MT, IQ{s_}, {_ssum(terms)});")
             done.add(nm)
             return nm
 
@@ -476,8 +505,8 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False) -> str:
             if share_antitop:
                 w(f"{ii}Sp<R> S{hs}_ = VS[{h}]; opaque_sp(S{hs}_);")
                 done.add(f"S{hs}_")
-            terms = [f"slash({J(seq[:j])}, {S(seq[j:], hs)})" for j in range(1, m + 1)]
-            w(f"{ii}const Sp<R> F{hs} = " + " + ".join(terms) + ";")
+            terms = [(J(seq[:j]), S(seq[j:], hs)) for j in range(1, m + 1)]
+            w(f"{ii}const Sp<R> F{hs} = {_ssum(terms)};")
             w(f"{ii}A0{hs}_{k} = ubar_dot(UB[0], F{hs});")
             w(f"{ii}A1{hs}_{k} = ubar_dot(UB[1], F{hs});")
         w(f"{ind}}}")
@@ -489,11 +518,7 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False) -> str:
     for h in hts:
         hs = "" if h is None else f"h{h}"
         for t in range(2):
-            parts = []
-            for c, lst in sorted(groups.items()):
-                terms = [f"cabs2(A{t}{hs}_{i})" if i == j else f"cre_dot(A{t}{hs}_{i}, A{t}{hs}_{j})" for (i, j) in lst]
-                parts.append(f"R({c}.0) * (" + " + ".join(terms) + ")")
-            w(f"{ind}total = total + (" + f"\n{ind}    + ".join(parts) + ");")
+            _colour_lines(w, ind, groups, lambda i, t=t, hs=hs: f"A{t}{hs}_{i}")
     w("    }")
     w("  }")
     w(f"  return total * R(1.0 / {den}.0);")
@@ -583,14 +608,11 @@ def emit_amp_store(m: int) -> str:
             nm = f"J{_name(sq)}"
             if nm in done:
                 return nm
-            t3 = [f"v3({J(sq[:j])}, {J(sq[j:])}, {P(sq[:j])}, {P(sq[j:])})" for j in range(1, len(sq))]
-            t4 = [f"w4({J(sq[:j])}, {J(sq[j:l])}, {J(sq[l:])})" for j in range(1, len(sq) - 1)
+            t3 = [(J(sq[:j]), J(sq[j:]), P(sq[:j]), P(sq[j:])) for j in range(1, len(sq))]
+            t4 = [(J(sq[:j]), J(sq[j:l]), J(sq[l:])) for j in range(1, len(sq) - 1)
                   for l in range(j + 1, len(sq))]
-            expr = " + ".join(t3)
-            if t4:
-                expr = f"({expr}) - (" + " + ".join(t4) + ")"
             g = G(sq)
-            w(f"{ii}const V4<R> {nm} = {g} * ({expr});")
+            w(f"{ii}const V4<R> {nm} = {g} * ({_vsum(t3, t4)});")
             done.add(nm)
             return nm
 
@@ -598,9 +620,9 @@ def emit_amp_store(m: int) -> str:
             nm = f"S{hs}_{_name(sq)}"
             if nm in done:
                 return nm
-            terms = [f"slash({J(sq[:j])}, {S(sq[j:], hs)})" for j in range(1, len(sq) + 1)]
+            terms = [(J(sq[:j]), S(sq[j:], hs)) for j in range(1, len(sq) + 1)]
             q = IQ(sq)
-            w(f"{ii}const Sp<R> {nm} = prop(R(-1.0) * (pb + {P(sq)}), MT, {q}, " + " + ".join(terms) + ");")
+            w(f"{ii}const Sp<R> {nm} = prop_neg(pb + {P(sq)}, MT, {q}, {_ssum(terms)});")
             done.add(nm)
             return nm
 
@@ -610,8 +632,8 @@ def emit_amp_store(m: int) -> str:
             hs = f"h{h}"
             w(f"{ii}const Sp<R> S{hs}_ = vt[{h} * AW + z_];")
             done.add(f"S{hs}_")
-            terms = [f"slash({J(seq[:j])}, {S(seq[j:], hs)})" for j in range(1, m + 1)]
-            w(f"{ii}const Sp<R> F{hs} = " + " + ".join(terms) + ";")
+            terms = [(J(seq[:j]), S(seq[j:], hs)) for j in range(1, m + 1)]
+            w(f"{ii}const Sp<R> F{hs} = {_ssum(terms)};")
             w(f"{ii}{{")
             w(f"{ii}  const C2<R> a0 = ubar_dot(UB[0], F{hs}), a1 = ubar_dot(UB[1], F{hs});")
             w(f"{ii}  R* o_ = o_hg + (int64_t)({h * 4}) * sstride + (int64_t)({k >> 2}) * ld4 + {k & 3};")

@@ -514,19 +514,26 @@ def test_trained_flow_beats_vegas_on_gg_ttgg():
     assert abs(r.integral - ref.integral) < 4.0 * np.hypot(r.error, ref.error), (r.integral, ref.integral)
 
 
-def test_fallback_fires_on_sampled_polarisation_states_of_gg_ttggg():
-    """g g -> t t~ g g g with one sampled polarisation state per point: the
+def test_fallback_on_sampled_polarisation_states_of_gg_ttggg():
+    """g g -> t t~ g g g with one sampled polarisation state per point.  The
     state sampling multiplies each weight by a noisy factor the flow cannot
-    learn, so after the 60-step recipe the flow's first iteration has a larger
-    per-event relative variance than VEGAS on the same grid, and the rest of
-    the run samples VEGAS; the decision follows the two measured variances,
-    and the estimate stays consistent with plain VEGAS."""
+    learn, and after the 60-step recipe the flow's per-event relative variance
+    lands close to that of VEGAS on the same grid (on either side, depending
+    on the training trajectory: 1.2e3 against 1.5e2 and 2.1e2 against 2.2e2
+    have both been measured).  The run keeps or drops the flow exactly as the
+    two measured variances say, and its estimate stays consistent with plain
+    VEGAS.  A flow far from the target (random parameters, the same mixture)
+    has a clearly larger variance: it falls back after its first iteration,
+    and the estimate still agrees."""
     p = mf.Process(mf.Config(process="gg>ttxggg", precision="fp32", dr_min=0.4, helicity=1))
     rv = _warm_rel_var(p)
     f = mf.Flow(13, max_batch=65536)
     p.train_flow_online(f, 60, batch=65536, lr=5e-3, loss="variance", flow_mix=0.2)
     r = p.integrate(4, 2_000_000, adapt=False, flow=f, flow_mix=0.2, iter_offset=5000, fallback_rel_var=rv)
-    assert (r.fallback_iter == 1) == (r.flow_rel_var > rv)
-    assert r.fallback_iter == 1, (r.flow_rel_var, rv)
+    assert (r.fallback_iter == 1) == (r.flow_rel_var > rv), (r.flow_rel_var, rv)
     ref = p.integrate(4, 2_000_000, adapt=False, iter_offset=7000)
     assert abs(r.integral - ref.integral) < 4.0 * np.hypot(r.error, ref.error), (r.integral, ref.integral)
+    g, _, _ = _flow_and_params(13, 1.0, seed=91, max_batch=65536)
+    rb = p.integrate(4, 2_000_000, adapt=False, flow=g, flow_mix=0.2, iter_offset=9000, fallback_rel_var=rv)
+    assert rb.fallback_iter == 1 and rb.flow_rel_var > rv, (rb.flow_rel_var, rv)
+    assert abs(rb.integral - ref.integral) < 4.0 * np.hypot(rb.error, ref.error), (rb.integral, ref.integral)
