@@ -282,8 +282,8 @@ def ttggg_helicity_sampling(events: int = 4_000_000) -> dict:
     return out
 
 
-def ttggg_throughput(events: int = 4_000_000, iters: int = 3) -> dict:
-    """g g -> t t~ g g g with FP32 amplitudes: events/s of staged VEGAS
+def ttggg_throughput(events: int = 4_000_000, iters: int = 3, prec: str = "fp32") -> dict:
+    """g g -> t t~ g g g with FP32 (or FP64) amplitudes: events/s of staged VEGAS
     iterations (after a warm-up that adapts the grid), and the algorithmic
     FLOP/s of the amplitude and colour kernels from their statically counted
     flops per passing event and the kernel times of the iterations (HIP events
@@ -296,7 +296,7 @@ def ttggg_throughput(events: int = 4_000_000, iters: int = 3) -> dict:
     import gen_me
 
     fc = gen_me.amp_flop_count(5)
-    p = mf.Process(mf.Config(process="gg>ttxggg", precision="fp32", dr_min=0.4))
+    p = mf.Process(mf.Config(process="gg>ttxggg", precision=prec, dr_min=0.4))
     p.integrate(3, 1_000_000, adapt=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -316,14 +316,14 @@ def ttggg_throughput(events: int = 4_000_000, iters: int = 3) -> dict:
 
 def ttggg_flow_comparison(seeds=SEEDS[:1]) -> dict:
     """The learned-proposal comparison on g g -> t t~ g g g (13 dims; FP32
-    amplitudes, so FP32 VEGAS is the baseline): iterations of 4e6 events, 60
+    amplitudes + flow against FP64 and FP32 VEGAS): iterations of 4e6 events, 60
     training steps of 65536 points (the fastest of 30/60 steps x 65536 and
     120 x 32768 measured; a learning rate of 1e-2 trained worse or diverged),
     flow iterations of 2e6 points, and a 150-step flow for the attainable
     variance; with the polarisation states summed and with one sampled state
     per point.  With sampled states the trained flow's variance exceeds the
     VEGAS proposal's on the same grid, and the fallback continues with VEGAS."""
-    return {"summed_states": learned_vs_vegas("gg>ttxggg", ("fp32",), seeds, 4_000_000, 2_000_000, 60,
+    return {"summed_states": learned_vs_vegas("gg>ttxggg", ("fp64", "fp32"), seeds, 4_000_000, 2_000_000, 60,
                                               eval_events=4_000_000, long_steps=150),
             "sampled_state": learned_vs_vegas("gg>ttxggg", ("fp32",), seeds, 4_000_000, 4_000_000, 60,
                                               helicity=1, eval_events=4_000_000, long_steps=150)}
@@ -563,6 +563,32 @@ def ttg_gradients() -> dict:
     return grads
 
 
+def ttj_channels(events: int = EVENTS, iters: int = 5) -> dict:
+    """The hadronic t t~ + jet rate at leading order by partonic channel (FP64,
+    jet = the light parton with pT > 20 GeV, |eta| < 2.5): g g -> t t~ g,
+    u u~ -> t t~ g, d d~ -> t t~ g and q g -> t t~ q (+ q~ g), each from
+    3 adapting + `iters` iterations of 1e7 events; events/s of the latter."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+
+    out = {}
+    total, var = 0.0, 0.0
+    for proc in ("gg>ttxg", "uux>ttxg", "ddx>ttxg", "qg>ttxq"):
+        p = mf.Process(mf.Config(process=proc))
+        p.integrate(3, events, adapt=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = p.integrate(iters, events, adapt=True, iter_offset=3)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[proc] = {"sigma_pb": r.integral, "error_pb": r.error, "events_per_s": iters * events / dt}
+        total += r.integral
+        var += r.error ** 2
+    out["total_pb"] = [total, var ** 0.5]
+    return out
+
+
 def extended() -> dict:
     """Longer measurements, not part of the default run (--extended)."""
     return {"ttg_observables": ttg_observables(), "ttg_dynamic_scale": ttg_dynamic_scale(),
@@ -582,10 +608,11 @@ def main() -> int:
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--extended", action="store_true",
                     help="also run observables, dynamic scale, g g -> t t~ g g g comparisons and a 300-step flow")
-    ap.add_argument("--only", choices=("ttg", "flow", "ttggg", "comparison"), default=None,
+    ap.add_argument("--only", choices=("ttg", "flow", "ttggg", "comparison", "ttj", "ttgg64"), default=None,
                     help="only one measurement (profiling): ttg = g g -> t t~ g FP64 iterations, flow = the "
                          "coupling-flow sampling pass, ttggg = g g -> t t~ g g g throughput, comparison = the "
-                         "time-to-1e-3 comparison")
+                         "time-to-1e-3 comparison, ttj = the t t~ + jet channels, ttgg64 = FP64 g g -> t t~ g g "
+                         "throughput")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (to calibrate HBM counters) and exit")
     args = ap.parse_args()
@@ -615,7 +642,14 @@ def main() -> int:
         print(json.dumps({"flow_roofline": flow_roofline()}), flush=True)
         return 0
     if args.only == "ttggg":
-        print(json.dumps({"ttggg_fp32": ttggg_throughput()}), flush=True)
+        print(json.dumps({"ttggg_fp32": ttggg_throughput(),
+                          "ttggg_fp64": ttggg_throughput(prec="fp64")}), flush=True)
+        return 0
+    if args.only == "ttgg64":
+        print(json.dumps({"ttgg_fp64": ttgg_fp64_throughput()}), flush=True)
+        return 0
+    if args.only == "ttj":
+        print(json.dumps({"ttj_by_channel": ttj_channels()}), flush=True)
         return 0
     if args.only == "comparison":
         print(json.dumps({"comparison": learned_vs_vegas()}), flush=True)
@@ -736,6 +770,7 @@ def main() -> int:
                                                "algorithmic_tflops_whole_integrand")},
             "ttg_gradients_dsigma_dmt": {k: [v["dsigma_dmt_pb_per_gev"], v["dsigma_dmt_err"]]
                                          for k, v in ttg_gradients().items()},
+            "ttj_by_channel": ttj_channels(),
         }
         print("# secondary done", file=sys.stderr, flush=True)
     if args.extended:

@@ -384,7 +384,7 @@ def emit_me(m: int, with_cost: bool = False):
     return text
 
 
-def emit_me_per_ordering(m: int, share_antitop: bool = False) -> str:
+def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings: bool = False) -> str:
     """Lower-register schedule: each colour ordering builds its own currents.
 
     Only per-event scalars (propagator factors, formed in the kinematic type),
@@ -449,11 +449,24 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False) -> str:
     ind = "      "
     for i in range(m):
         w(f"{ind}const V4<R> E{i} = ((hg >> {m - 1 - i}) & 1) ? E[{i}][1] : E[{i}][0];")
-    for k, seq in enumerate(perms):
-        for h in hts:
-            hs = "" if h is None else f"h{h}"
-            w(f"{ind}C2<R> A0{hs}_{k}, A1{hs}_{k};")
-        w(f"{ind}{{  // ordering {seq}")
+    # orderings handled together: pairs that differ by the swap of their
+    # first two gluons share the currents of positions 2.. (gluon and top-line
+    # spinor currents), and their leading two-gluon currents differ in sign
+    if pair_orderings:
+        index = {seq: k for k, seq in enumerate(perms)}
+        order = []
+        for k, seq in enumerate(perms):
+            k2 = index[(seq[1], seq[0]) + seq[2:]]
+            if k < k2:
+                order.append((k, k2))
+    else:
+        order = [(k,) for k in range(nf)]
+    for grp in order:
+        for k in grp:
+            for h in hts:
+                hs = "" if h is None else f"h{h}"
+                w(f"{ind}C2<R> A0{hs}_{k}, A1{hs}_{k};")
+        w(f"{ind}{{  // ordering" + ("s " if len(grp) > 1 else " ") + ", ".join(str(perms[k]) for k in grp))
         ii = ind + "  "
         for i in range(m):
             w(f"{ii}V4<R> J{i} = E{i}; opaque4(J{i});")
@@ -478,6 +491,12 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False) -> str:
             nm = f"J{_name(sq)}"
             if nm in done:
                 return nm
+            rev = f"J{_name(sq[::-1])}"
+            if len(sq) == 2 and rev in done:
+                # J(b, a) = -J(a, b): the three-gluon vertex is antisymmetric
+                w(f"{ii}const V4<R> {nm} = R(-1.0) * {rev};")
+                done.add(nm)
+                return nm
             t3 = [(J(sq[:j]), J(sq[j:]), P(sq[:j]), P(sq[j:])) for j in range(1, len(sq))]
             t4 = [(J(sq[:j]), J(sq[j:l]), J(sq[l:])) for j in range(1, len(sq) - 1)
                   for l in range(j + 1, len(sq))]
@@ -498,17 +517,20 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False) -> str:
         # with share_antitop: the gluon currents first (shared by both antitop
         # helicities), then the top line for each antitop helicity
         if share_antitop:
-            for j in range(1, m + 1):
-                J(seq[:j])
+            for k in grp:
+                for j in range(1, m + 1):
+                    J(perms[k][:j])
         for h in hts:
             hs = "" if h is None else f"h{h}"
             if share_antitop:
                 w(f"{ii}Sp<R> S{hs}_ = VS[{h}]; opaque_sp(S{hs}_);")
                 done.add(f"S{hs}_")
-            terms = [(J(seq[:j]), S(seq[j:], hs)) for j in range(1, m + 1)]
-            w(f"{ii}const Sp<R> F{hs} = {_ssum(terms)};")
-            w(f"{ii}A0{hs}_{k} = ubar_dot(UB[0], F{hs});")
-            w(f"{ii}A1{hs}_{k} = ubar_dot(UB[1], F{hs});")
+            for k in grp:
+                seq = perms[k]
+                terms = [(J(seq[:j]), S(seq[j:], hs)) for j in range(1, m + 1)]
+                w(f"{ii}const Sp<R> F{hs}_{k} = {_ssum(terms)};")
+                w(f"{ii}A0{hs}_{k} = ubar_dot(UB[0], F{hs}_{k});")
+                w(f"{ii}A1{hs}_{k} = ubar_dot(UB[1], F{hs}_{k});")
         w(f"{ind}}}")
     groups = {}
     for i in range(nf):
@@ -797,6 +819,9 @@ def amp_flop_count(m: int) -> dict:
 
 
 SCHEDULE = {2: "memo", 3: "per_ordering_shared_antitop", 4: "per_ordering_shared_antitop", 5: "amplitudes"}
+# per-ordering schedules that handle the orderings in pairs sharing their
+# suffix currents
+PAIR_ORDERINGS = {2: False, 3: True, 4: True, 5: False}
 
 
 def main(outdir: str, ms=(2, 3, 4, 5)) -> None:
@@ -808,7 +833,7 @@ def main(outdir: str, ms=(2, 3, 4, 5)) -> None:
         else:
             path = os.path.join(outdir, f"me_gg_m{m}.h")
             text = emit_me(m) if SCHEDULE[m] == "memo" else emit_me_per_ordering(
-                m, share_antitop=SCHEDULE[m] == "per_ordering_shared_antitop")
+                m, share_antitop=SCHEDULE[m] == "per_ordering_shared_antitop", pair_orderings=PAIR_ORDERINGS[m])
         old = open(path).read() if os.path.exists(path) else None
         if old != text:
             with open(path, "w") as f:
