@@ -384,7 +384,7 @@ def emit_me(m: int, with_cost: bool = False):
     return text
 
 
-def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings: bool = False) -> str:
+def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings=False) -> str:
     """Lower-register schedule: each colour ordering builds its own currents.
 
     Only per-event scalars (propagator factors, formed in the kinematic type),
@@ -452,7 +452,9 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings: bo
     # orderings handled together: pairs that differ by the swap of their
     # first two gluons share the currents of positions 2.. (gluon and top-line
     # spinor currents), and their leading two-gluon currents differ in sign
-    if pair_orderings:
+    if pair_orderings == "all":
+        order = [tuple(range(nf))]
+    elif pair_orderings:
         index = {seq: k for k, seq in enumerate(perms)}
         order = []
         for k, seq in enumerate(perms):
@@ -492,11 +494,13 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings: bo
             if nm in done:
                 return nm
             rev = f"J{_name(sq[::-1])}"
-            if len(sq) == 2 and rev in done:
-                # J(b, a) = -J(a, b): the three-gluon vertex is antisymmetric
-                w(f"{ii}const V4<R> {nm} = R(-1.0) * {rev};")
-                done.add(nm)
-                return nm
+            if rev in done:
+                # reflection of a colour-ordered current: J(n..1) = (-1)^(n+1) J(1..n)
+                if len(sq) % 2 == 0:
+                    w(f"{ii}const V4<R> {nm} = R(-1.0) * {rev};")
+                    done.add(nm)
+                    return nm
+                return rev
             t3 = [(J(sq[:j]), J(sq[j:]), P(sq[:j]), P(sq[j:])) for j in range(1, len(sq))]
             t4 = [(J(sq[:j]), J(sq[j:l]), J(sq[l:])) for j in range(1, len(sq) - 1)
                   for l in range(j + 1, len(sq))]
@@ -820,8 +824,10 @@ def amp_flop_count(m: int) -> dict:
 
 SCHEDULE = {2: "memo", 3: "per_ordering_shared_antitop", 4: "per_ordering_shared_antitop", 5: "amplitudes"}
 # per-ordering schedules that handle the orderings in pairs sharing their
-# suffix currents
-PAIR_ORDERINGS = {2: False, 3: True, 4: True, 5: False}
+# suffix currents ("all": every ordering in one block, so that besides the
+# suffix currents the reflected currents J(n..1) = (-1)^(n+1) J(1..n) are
+# shared too)
+PAIR_ORDERINGS = {2: False, 3: "all", 4: True, 5: False}
 
 
 def main(outdir: str, ms=(2, 3, 4, 5)) -> None:
