@@ -8,10 +8,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "amp.h"
 #include "gen/me_gg_m2.h"
 #include "gen/me_gg_m3.h"
 #include "gen/me_gg_m4.h"
+#include "gen/me_gg_m4_grouped.h"
 #include "qq.h"
 
 namespace mf {
@@ -313,6 +316,7 @@ __device__ __forceinline__ RA me_gg(double E, const V4<double>* gl, const V4<RK>
   Sp<RA> VS[2] = {v_spinor(tb, m_a, -1), v_spinor(tb, m_a, 1)};
   if constexpr (m == 2) return me_gg_m2<RA, RK>(K, Ep, UB, VS, atop, mt);
   else if constexpr (m == 3) return me_gg_m3<RA, RK>(K, Ep, UB, VS, atop, mt);
+  else if constexpr (std::is_same<RA, float>::value) return me_gg_m4_grouped<RA, RK>(K, Ep, UB, VS, atop, mt);
   else return me_gg_m4<RA, RK>(K, Ep, UB, VS, atop, mt);
 }
 

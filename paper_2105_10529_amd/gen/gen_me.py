@@ -384,7 +384,7 @@ def emit_me(m: int, with_cost: bool = False):
     return text
 
 
-def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings=False) -> str:
+def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings=False, suffix: str = "") -> str:
     """Lower-register schedule: each colour ordering builds its own currents.
 
     Only per-event scalars (propagator factors, formed in the kinematic type),
@@ -406,16 +406,19 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings=Fal
     w = L.append
     w(f"// Generated by gen_me.py for g g -> t t~ + {m - 2} g ({m} gluons on the top line,")
     w(f"// {nf} colour orderings, {1 << (m + 2)} helicity/polarisation states),")
-    w("// per-ordering schedule. Do not edit.")
+    grouping = {"all": "all orderings in one block", "last": "orderings grouped by their last gluon",
+                True: "orderings in pairs"}.get(pair_orderings, "one ordering at a time")
+    w(f"// per-ordering schedule, {grouping}. Do not edit.")
     w("#pragma once")
     w('#include "amp.h"')
     w("namespace mf {")
-    w(f"constexpr int ME_M{m}_NF = {nf};")
-    w(f"constexpr double ME_M{m}_COLOUR_DEN = {den}.0;")
+    if not suffix:
+        w(f"constexpr int ME_M{m}_NF = {nf};")
+        w(f"constexpr double ME_M{m}_COLOUR_DEN = {den}.0;")
     w("// Colour- and polarisation-summed |M|^2 with g = 1 (argument meaning as in")
     w("// the shared-current schedule).")
     w("template <class R, class RK>")
-    w(f"__device__ __forceinline__ R me_gg_m{m}(const V4<RK>* K, const V4<R> (*E)[2], const Sp<R>* UB,")
+    w(f"__device__ __forceinline__ R me_gg_m{m}{suffix}(const V4<RK>* K, const V4<R> (*E)[2], const Sp<R>* UB,")
     w("                                         const Sp<R>* VS, const V4<RK>& PTB, RK MTK) {")
     w("  const R MT = cvt<R>(MTK);")
     subsets = list(range(1, 1 << m))
@@ -452,18 +455,23 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings=Fal
     # orderings handled together: pairs that differ by the swap of their
     # first two gluons share the currents of positions 2.. (gluon and top-line
     # spinor currents), and their leading two-gluon currents differ in sign
+    # each block is a list of sub-blocks: the gluon currents of a sub-block
+    # are built, then its top-line currents for each antitop helicity, before
+    # the next sub-block starts; whatever the sub-blocks of one block share is
+    # built once
+    index = {seq: k for k, seq in enumerate(perms)}
+    pairs = [(k, index[(seq[1], seq[0]) + seq[2:]]) for k, seq in enumerate(perms)]
+    pairs = [pr for pr in pairs if pr[0] < pr[1]]
     if pair_orderings == "all":
-        order = [tuple(range(nf))]
+        order = [[tuple(range(nf))]]
+    elif pair_orderings == "last":
+        order = [[pr for pr in pairs if perms[pr[0]][-1] == d] for d in range(m)]
     elif pair_orderings:
-        index = {seq: k for k, seq in enumerate(perms)}
-        order = []
-        for k, seq in enumerate(perms):
-            k2 = index[(seq[1], seq[0]) + seq[2:]]
-            if k < k2:
-                order.append((k, k2))
+        order = [[pr] for pr in pairs]
     else:
-        order = [(k,) for k in range(nf)]
-    for grp in order:
+        order = [[(k,)] for k in range(nf)]
+    for block in order:
+        grp = [k for sub in block for k in sub]
         for k in grp:
             for h in hts:
                 hs = "" if h is None else f"h{h}"
@@ -520,21 +528,22 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings=Fal
 
         # with share_antitop: the gluon currents first (shared by both antitop
         # helicities), then the top line for each antitop helicity
-        if share_antitop:
-            for k in grp:
-                for j in range(1, m + 1):
-                    J(perms[k][:j])
-        for h in hts:
-            hs = "" if h is None else f"h{h}"
+        for sub in block:
             if share_antitop:
-                w(f"{ii}Sp<R> S{hs}_ = VS[{h}]; opaque_sp(S{hs}_);")
-                done.add(f"S{hs}_")
-            for k in grp:
-                seq = perms[k]
-                terms = [(J(seq[:j]), S(seq[j:], hs)) for j in range(1, m + 1)]
-                w(f"{ii}const Sp<R> F{hs}_{k} = {_ssum(terms)};")
-                w(f"{ii}A0{hs}_{k} = ubar_dot(UB[0], F{hs}_{k});")
-                w(f"{ii}A1{hs}_{k} = ubar_dot(UB[1], F{hs}_{k});")
+                for k in sub:
+                    for j in range(1, m + 1):
+                        J(perms[k][:j])
+            for h in hts:
+                hs = "" if h is None else f"h{h}"
+                if share_antitop and f"S{hs}_" not in done:
+                    w(f"{ii}Sp<R> S{hs}_ = VS[{h}]; opaque_sp(S{hs}_);")
+                    done.add(f"S{hs}_")
+                for k in sub:
+                    seq = perms[k]
+                    terms = [(J(seq[:j]), S(seq[j:], hs)) for j in range(1, m + 1)]
+                    w(f"{ii}const Sp<R> F{hs}_{k} = {_ssum(terms)};")
+                    w(f"{ii}A0{hs}_{k} = ubar_dot(UB[0], F{hs}_{k});")
+                    w(f"{ii}A1{hs}_{k} = ubar_dot(UB[1], F{hs}_{k});")
         w(f"{ind}}}")
     groups = {}
     for i in range(nf):
@@ -828,6 +837,9 @@ SCHEDULE = {2: "memo", 3: "per_ordering_shared_antitop", 4: "per_ordering_shared
 # suffix currents the reflected currents J(n..1) = (-1)^(n+1) J(1..n) are
 # shared too)
 PAIR_ORDERINGS = {2: False, 3: "all", 4: True, 5: False}
+# a second function with a wider grouping, me_gg_m4_grouped (the six orderings
+# that end with the same gluon in one block), for the FP32 amplitudes: it needs
+# more registers, which the FP32 kernel has and the FP64 one does not
 
 
 def main(outdir: str, ms=(2, 3, 4, 5)) -> None:
@@ -844,9 +856,10 @@ def main(outdir: str, ms=(2, 3, 4, 5)) -> None:
         if old != text:
             with open(path, "w") as f:
                 f.write(text)
-    # g g -> t t~ g g: the amplitudes stored for the matrix-core colour sum;
-    # the colour matrix of the quark channels
-    for name, text in (("amps_gg_m4.h", emit_amp_store(4)), ("colour_qq.h", emit_colour_qq())):
+    # g g -> t t~ g g: the wider grouping for FP32; the amplitudes stored for
+    # the matrix-core colour sum; the colour matrix of the quark channels
+    for name, text in (("me_gg_m4_grouped.h", emit_me_per_ordering(4, True, "last", "_grouped")),
+                       ("amps_gg_m4.h", emit_amp_store(4)), ("colour_qq.h", emit_colour_qq())):
         path = os.path.join(outdir, name)
         old = open(path).read() if os.path.exists(path) else None
         if old != text:
