@@ -50,7 +50,7 @@ TARGET = 1e-3
 TTGG_TRAFFIC_BYTES_PER_KEPT_EVENT = 1483.0
 # the same for k_select<1> + k_vegas<1,0,double> at 1e7 events
 # (profiles/traffic_k_vegas_gg_ttg_fp64_1e7.md)
-TTG_TRAFFIC_BYTES = 66.9e6
+TTG_TRAFFIC_BYTES = 82.2e6
 
 
 def flops_per_event(m: int) -> int:

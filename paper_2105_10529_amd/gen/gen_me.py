@@ -315,6 +315,15 @@ def emit_me(m: int, with_cost: bool = False):
         nm = f"J{_name(seq)}"
         if nm in emitted:
             return nm
+        rev = f"J{_name(seq[::-1])}"
+        if rev in emitted:
+            # reflection of a colour-ordered current: J(n..1) = (-1)^(n+1) J(1..n),
+            # no arithmetic (a sign flip folds into the consumers)
+            if len(seq) % 2 == 1:
+                return rev
+            w(f"{ind}const V4<R> {nm} = R(-1.0) * {rev};")
+            emitted.add(nm)
+            return nm
         terms3 = []
         for j in range(1, len(seq)):
             a, b = seq[:j], seq[j:]

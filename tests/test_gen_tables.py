@@ -99,7 +99,7 @@ def test_shared_antitop_counts():
     """g g -> t t~ g and g g -> t t~ g g build each ordering's gluon currents
     once per gluon polarisation state for both antitop helicities: the count
     drops by one set of gluon currents per gluon polarisation state."""
-    for m, before in ((3, 66042), (4, 926138)):
+    for m, before in ((3, 54186), (4, 713978)):
         fc = gen_me.flop_count(m)
         assert fc["total"] == before - (fc["states"] // 2) * fc["gluon_currents_per_polarisation"]
 
