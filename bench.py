@@ -526,6 +526,30 @@ def ttg_fp64(events: int = EVENTS, iters: int = 10, warmup: int = 2) -> dict:
                          "kernel": "k_select<1> + k_vegas<1,0,double>", "flops_per_passing_event": fpe}}
 
 
+def colour_forms(iters: int = 2) -> dict:
+    """A/B of the two colour forms of g g -> t t~ g g: the quadratic form in
+    registers inside the fused kernel (colour_form 1, the default) against
+    the staged form with the colour sum on the matrix cores (colour_form 2),
+    events/s of VEGAS iterations after two adapting ones; FP32 at 1e8 and
+    FP64 at 1e7 events per iteration."""
+    import torch
+
+    import paper_2105_10529_amd as mf
+
+    out = {}
+    for prec, n in (("fp32", HEADLINE_EVENTS), ("fp64", EVENTS)):
+        for form in (1, 2):
+            p = mf.Process(ttgg_config(prec, colour_form=form))
+            p.integrate(2, EVENTS, adapt=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = p.integrate(iters, n, adapt=True, iter_offset=2)
+            torch.cuda.synchronize()
+            out[f"{prec}_colour_form_{form}"] = {"events_per_s": iters * n / (time.perf_counter() - t0),
+                                                 "integral_pb": r.integral, "error_pb": r.error}
+    return out
+
+
 def ttgg_fp64_throughput(events: int = EVENTS, iters: int = 3) -> dict:
     """Plain FP64 VEGAS on g g -> t t~ g g (the baseline of the comparison):
     events/s of 1e7-event iterations after an adapting warm-up."""
@@ -610,11 +634,12 @@ def main() -> int:
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--extended", action="store_true",
                     help="also run observables, dynamic scale, g g -> t t~ g g g comparisons and a 300-step flow")
-    ap.add_argument("--only", choices=("ttg", "flow", "ttggg", "comparison", "ttj", "ttgg64"), default=None,
+    ap.add_argument("--only", choices=("ttg", "flow", "ttggg", "comparison", "ttj", "ttgg64", "colour_forms"),
+                    default=None,
                     help="only one measurement (profiling): ttg = g g -> t t~ g FP64 iterations, flow = the "
                          "coupling-flow sampling pass, ttggg = g g -> t t~ g g g throughput, comparison = the "
                          "time-to-1e-3 comparison, ttj = the t t~ + jet channels, ttgg64 = FP64 g g -> t t~ g g "
-                         "throughput")
+                         "throughput, colour_forms = the A/B of the two colour forms of g g -> t t~ g g")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (to calibrate HBM counters) and exit")
     args = ap.parse_args()
@@ -646,6 +671,9 @@ def main() -> int:
     if args.only == "ttggg":
         print(json.dumps({"ttggg_fp32": ttggg_throughput(),
                           "ttggg_fp64": ttggg_throughput(prec="fp64")}), flush=True)
+        return 0
+    if args.only == "colour_forms":
+        print(json.dumps({"colour_forms": colour_forms()}), flush=True)
         return 0
     if args.only == "ttgg64":
         print(json.dumps({"ttgg_fp64": ttgg_fp64_throughput()}), flush=True)
