@@ -17,7 +17,8 @@
  *    host memory.  The caller owns every buffer it passes.  The library
  *    allocates device memory only inside an mf_process handle (tables, the
  *    VEGAS grid, reduction partials, staging buffers) and frees it in
- *    mf_process_destroy.
+ *    mf_process_destroy; the calls without a handle (mf_vegas_refine,
+ *    mf_weight_stats, mf_vjp) work in scratch the caller passes.
  *  - g g -> t t~ g g g (and g g -> t t~ g g with the matrix-core colour
  *    form) evaluates the integrand in stages: kinematics and cuts, then the
  *    partial amplitudes of the events that pass, streamed through a
@@ -191,12 +192,14 @@ mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w
  * sum r, linear inside old bins.
  *   edges: device, [ndim][nbins+1] FP64, in/out, strictly increasing.
  *   hist:  device, [ndim][nbins] FP64 sums of w^2 per bin (>= 0).
+ *   status: device, one int32 of caller-owned scratch (its content on entry
+ *           does not matter; it is cleared by a kernel, not by a memset).
  * A dimension whose histogram is all zero is left unchanged.  MF_ERANGE if
  * the result is not strictly increasing (the input grid is then unchanged
- * for that dimension).  ndim in 1..13, nbins in 1..64.  Takes a 4-byte
- * status word from the stream-ordered allocator and synchronises `stream`
- * before returning. */
-mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins, double alpha, void* stream);
+ * for that dimension).  MF_EINVAL for a NULL buffer.  ndim in 1..13, nbins
+ * in 1..64.  Allocates nothing; synchronises `stream` before returning. */
+mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins, double alpha, int32_t* status,
+                          void* stream);
 
 struct mf_flow;     /* learned proposal, mf_flow.h */
 struct mf_result_s; /* mf_result, below */
@@ -326,8 +329,14 @@ mf_status mf_weights(mf_process* p, struct mf_flow* flow, double flow_mix, uint6
  *        is |mean| sqrt(that / N).
  * The quantile is exact (radix selection on order-preserving bit keys).  The
  * unweighting efficiency of a sample is mean / max (or mean / quantile).
- * MF_EINVAL for a NaN weight or q outside (0,1].  Synchronous. */
-mf_status mf_weight_stats(const double* w, int64_t n, double q, double* out, void* stream);
+ *   work: device scratch owned by the caller, at least
+ *         mf_weight_stats_workspace(n) bytes, 8-byte aligned.
+ * MF_EINVAL for a NaN weight, q outside (0,1], a NULL or too small
+ * workspace.  Allocates nothing.  Synchronous. */
+mf_status mf_weight_stats(const double* w, int64_t n, double q, double* out, void* work, int64_t work_bytes,
+                          void* stream);
+/* Bytes of device scratch mf_weight_stats needs for n weights (n >= 1). */
+int64_t mf_weight_stats_workspace(int64_t n);
 
 /* Vector-Jacobian product of per-event derivatives with an upstream
  * gradient (the backward step of an autograd function over
@@ -335,8 +344,14 @@ mf_status mf_weight_stats(const double* w, int64_t n, double q, double* out, voi
  *   dw:  device [k][n] FP64 (e.g. the dw of mf_integrand_grad, k = 9)
  *   g:   device [n] FP64 upstream gradient of the per-event weights
  *   out: device [k] FP64, out[j] = sum_e dw[j][e] g[e] (ordered, reproducible)
- * k in 1..64, n >= 1.  Takes a small stream-ordered scratch allocation. */
-mf_status mf_vjp(const double* dw, int32_t k, const double* g, int64_t n, double* out, void* stream);
+ *   work: device scratch owned by the caller, at least mf_vjp_workspace(k, n)
+ *         bytes, 8-byte aligned, not read before it is written.
+ * k in 1..64, n >= 1; MF_EINVAL otherwise or for a NULL or too small
+ * workspace.  Allocates nothing; asynchronous on `stream`. */
+mf_status mf_vjp(const double* dw, int32_t k, const double* g, int64_t n, double* out, void* work, int64_t work_bytes,
+                 void* stream);
+/* Bytes of device scratch mf_vjp needs for k rows of n events. */
+int64_t mf_vjp_workspace(int32_t k, int64_t n);
 
 /* Pathwise Monte Carlo estimate of sigma and its parameter derivatives (an
  * extension: the paper integrates sigma only, Sec. 2.1 and 3) with

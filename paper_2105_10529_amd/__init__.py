@@ -149,7 +149,8 @@ EXPORTS = ("mf_process_create", "mf_process_destroy", "mf_process_ndim", "mf_las
            "mf_integrand_grad", "mf_vegas_refine", "mf_integrate", "mf_grad", "mf_weights", "mf_weight_stats",
            "mf_flow_create", "mf_flow_destroy", "mf_flow_ndim", "mf_flow_param_count", "mf_flow_masks",
            "mf_flow_set_params", "mf_flow_get_params", "mf_flow_forward", "mf_flow_inverse", "mf_flow_loss_grad",
-           "mf_flow_adam_step", "mf_flow_train", "mf_flow_train_online", "mf_vjp", "mf_integrand_noalloc")
+           "mf_flow_adam_step", "mf_flow_train", "mf_flow_train_online", "mf_vjp", "mf_integrand_noalloc",
+           "mf_vjp_workspace", "mf_weight_stats_workspace")
 
 _lib = None
 
@@ -176,7 +177,7 @@ def lib():
         L.mf_integrand_noalloc.restype = i32
         L.mf_integrand_grad.argtypes = [P, P, i64, P, P, P]
         L.mf_integrand_grad.restype = i32
-        L.mf_vegas_refine.argtypes = [P, P, ctypes.c_int, ctypes.c_int, d, P]
+        L.mf_vegas_refine.argtypes = [P, P, ctypes.c_int, ctypes.c_int, d, P, P]
         L.mf_vegas_refine.restype = i32
         L.mf_integrate.argtypes = [P, ctypes.POINTER(_IntegrateOpts), ctypes.POINTER(_Result)]
         L.mf_integrate.restype = i32
@@ -184,10 +185,14 @@ def lib():
         L.mf_grad.restype = i32
         L.mf_weights.argtypes = [P, P, d, ctypes.c_uint64, i64, P, P, P]
         L.mf_weights.restype = i32
-        L.mf_weight_stats.argtypes = [P, i64, d, P, P]
+        L.mf_weight_stats.argtypes = [P, i64, d, P, P, i64, P]
         L.mf_weight_stats.restype = i32
-        L.mf_vjp.argtypes = [P, i32, P, i64, P, P]
+        L.mf_weight_stats_workspace.argtypes = [i64]
+        L.mf_weight_stats_workspace.restype = i64
+        L.mf_vjp.argtypes = [P, i32, P, i64, P, P, i64, P]
         L.mf_vjp.restype = i32
+        L.mf_vjp_workspace.argtypes = [i32, i64]
+        L.mf_vjp_workspace.restype = i64
         L.mf_flow_create.argtypes = [ctypes.POINTER(_FlowConfig), ctypes.POINTER(P)]
         L.mf_flow_create.restype = i32
         L.mf_flow_destroy.argtypes = [P]
@@ -465,14 +470,22 @@ def vjp(dw, g, stream=None):
 
     k, n = dw.shape
     out = torch.empty(k, dtype=torch.float64, device=dw.device)
-    _check(lib().mf_vjp(_dev_ptr(dw), k, _dev_ptr(g), n, _dev_ptr(out), _stream_ptr(stream)))
+    nbytes = lib().mf_vjp_workspace(k, n)
+    work = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=dw.device)
+    _check(lib().mf_vjp(_dev_ptr(dw), k, _dev_ptr(g), n, _dev_ptr(out), _dev_ptr(work), 8 * work.numel(),
+                        _stream_ptr(stream)))
     return out
 
 
 def weight_stats(w, q: float = 0.999, stream=None) -> dict:
     """mean, max, q-quantile, non-zero count and relative variance per event of device weights -- mf_weight_stats."""
+    import torch
+
     out = np.zeros(5)
-    _check(lib().mf_weight_stats(_dev_ptr(w), w.numel(), q, out.ctypes.data, _stream_ptr(stream)))
+    nbytes = lib().mf_weight_stats_workspace(w.numel())
+    work = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=w.device)
+    _check(lib().mf_weight_stats(_dev_ptr(w), w.numel(), q, out.ctypes.data, _dev_ptr(work), 8 * work.numel(),
+                                 _stream_ptr(stream)))
     return {"mean": out[0], "max": out[1], "quantile": out[2], "nonzero": int(out[3]), "relvar": out[4]}
 
 
@@ -586,8 +599,12 @@ class Flow:
 
 def vegas_refine(edges, hist, alpha: float = 1.5, stream=None):
     """In-place refinement of a device grid [ndim][nbins+1] from a device histogram -- mf_vegas_refine."""
+    import torch
+
     d, nb1 = edges.shape
-    _check(lib().mf_vegas_refine(_dev_ptr(edges), _dev_ptr(hist), d, nb1 - 1, alpha, _stream_ptr(stream)))
+    status = torch.empty(1, dtype=torch.int32, device=edges.device)
+    _check(lib().mf_vegas_refine(_dev_ptr(edges), _dev_ptr(hist), d, nb1 - 1, alpha, _dev_ptr(status, "int32"),
+                                 _stream_ptr(stream)))
     return edges
 
 

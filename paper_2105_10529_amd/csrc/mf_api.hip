@@ -409,6 +409,8 @@ __device__ bool refine_dim(double* e, const double* h, int nb, double alpha, dou
   return true;
 }
 
+__global__ void k_clear_status(int* status) { status[0] = 0; }
+
 __global__ void k_refine(double* edges, const double* hist, int d, int nb, double alpha, int* status) {
   __shared__ double scratch[3 * MAX_BINS + 1];
   int j = blockIdx.x;
@@ -921,20 +923,19 @@ mf_status mf_integrand_grad(mf_process* p, const double* u, int64_t n, double* w
   return check_stream_launch("k_integrand_grad");
 }
 
-mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins, double alpha, void* stream) {
+mf_status mf_vegas_refine(double* edges, const double* hist, int ndim, int nbins, double alpha, int32_t* status,
+                          void* stream) {
   mf::clear_error();
-  if (!edges || !hist) return fail(MF_EINVAL, "NULL buffer");
+  if (!edges || !hist || !status) return fail(MF_EINVAL, "NULL buffer");
   if (ndim < 1 || ndim > MAXD) return fail(MF_EINVAL, "ndim must be in 1..%d", MAXD);
   if (nbins < 1 || nbins > MAX_BINS) return fail(MF_EINVAL, "nbins must be in 1..%d", MAX_BINS);
   if (!(alpha > 0.0)) return fail(MF_EINVAL, "alpha must be positive");
   hipStream_t s = (hipStream_t)stream;
-  int* st = nullptr;
-  HIP_TRY(hipMallocAsync((void**)&st, sizeof(int), s));
-  HIP_TRY(hipMemsetAsync(st, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_refine, dim3(ndim), dim3(64), 0, s, edges, hist, ndim, nbins, alpha, st);
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, status);
+  hipLaunchKernelGGL(k_refine, dim3(ndim), dim3(64), 0, s, edges, hist, ndim, nbins, alpha, status);
   int hs = 0;
-  HIP_TRY(hipMemcpyAsync(&hs, st, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipFreeAsync(st, s));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (hs) return fail(MF_ERANGE, "refined grid not strictly increasing; dimension left unchanged");
   return MF_OK;

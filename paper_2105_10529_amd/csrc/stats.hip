@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 #include "../../include/mf.h"
@@ -148,36 +149,54 @@ __global__ void k_vjp_final(const double* __restrict__ part, int nb, int k, doub
 
 }  // namespace
 
-extern "C" mf_status mf_vjp(const double* dw, int32_t k, const double* g, int64_t n, double* out, void* stream) {
+// Blocks of the partial-sum kernels for n events.
+static int stat_blocks(int64_t n) { return (int)(n < (int64_t)SMAXB * SB ? (n + SB - 1) / SB : SMAXB); }
+
+extern "C" int64_t mf_vjp_workspace(int32_t k, int64_t n) {
+  if (k < 1 || n < 1) return 0;
+  return (int64_t)sizeof(double) * stat_blocks(n) * k;
+}
+
+extern "C" mf_status mf_vjp(const double* dw, int32_t k, const double* g, int64_t n, double* out, void* work,
+                            int64_t work_bytes, void* stream) {
   mf::clear_error();
-  if (!dw || !g || !out) return mf::set_error(MF_EINVAL, "NULL argument");
+  if (!dw || !g || !out || !work) return mf::set_error(MF_EINVAL, "NULL argument");
   if (k < 1 || k > 64) return mf::set_error(MF_EINVAL, "k must be in 1..64");
   if (n < 1) return mf::set_error(MF_EINVAL, "n must be >= 1");
+  if (work_bytes < mf_vjp_workspace(k, n))
+    return mf::set_error(MF_EINVAL, "workspace of %lld bytes, %lld needed", (long long)work_bytes,
+                         (long long)mf_vjp_workspace(k, n));
+  if (((uintptr_t)work & 7) != 0) return mf::set_error(MF_EINVAL, "workspace not 8-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const int nb = (int)(n < (int64_t)SMAXB * SB ? (n + SB - 1) / SB : SMAXB);
-  double* part = nullptr;
-  if (hipMallocAsync((void**)&part, sizeof(double) * nb * k, s) != hipSuccess)
-    return mf::set_error(MF_ENOMEM, "partial sums");
+  const int nb = stat_blocks(n);
+  double* part = static_cast<double*>(work);
   hipLaunchKernelGGL(k_vjp_partial, dim3(nb), dim3(SB), 0, s, dw, k, g, n, part);
   hipLaunchKernelGGL(k_vjp_final, dim3(1), dim3(64), 0, s, part, nb, k, out);
   const hipError_t e = hipGetLastError();
-  (void)hipFreeAsync(part, s);
   if (e != hipSuccess) return mf::set_error(MF_EDEVICE, "vjp launch: %s", hipGetErrorString(e));
   return MF_OK;
 }
 
-extern "C" mf_status mf_weight_stats(const double* w, int64_t n, double q, double* out, void* stream) {
+extern "C" int64_t mf_weight_stats_workspace(int64_t n) {
+  if (n < 1) return 0;
+  // partial sums (NS per block and NS for the total), then the radix state
+  return (int64_t)sizeof(double) * (NS * stat_blocks(n) + NS) + (int64_t)sizeof(unsigned long long) * (256 + 3);
+}
+
+extern "C" mf_status mf_weight_stats(const double* w, int64_t n, double q, double* out, void* work,
+                                     int64_t work_bytes, void* stream) {
   mf::clear_error();
-  if (!w || !out) return mf::set_error(MF_EINVAL, "NULL argument");
+  if (!w || !out || !work) return mf::set_error(MF_EINVAL, "NULL argument");
   if (n < 1) return mf::set_error(MF_EINVAL, "n must be >= 1");
   if (!(q > 0.0 && q <= 1.0)) return mf::set_error(MF_EINVAL, "q must be in (0,1]");
+  if (work_bytes < mf_weight_stats_workspace(n))
+    return mf::set_error(MF_EINVAL, "workspace of %lld bytes, %lld needed", (long long)work_bytes,
+                         (long long)mf_weight_stats_workspace(n));
+  if (((uintptr_t)work & 7) != 0) return mf::set_error(MF_EINVAL, "workspace not 8-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  const int nb = (int)(n < (int64_t)SMAXB * SB ? (n + SB - 1) / SB : SMAXB);
-  double* part = nullptr;
-  unsigned long long* st = nullptr;
-  if (hipMallocAsync((void**)&part, sizeof(double) * (NS * nb + NS), s) != hipSuccess ||
-      hipMallocAsync((void**)&st, sizeof(unsigned long long) * (256 + 3), s) != hipSuccess)
-    return mf::set_error(MF_ENOMEM, "statistics buffers");
+  const int nb = stat_blocks(n);
+  double* part = static_cast<double*>(work);
+  unsigned long long* st = reinterpret_cast<unsigned long long*>(part + NS * nb + NS);
   hipLaunchKernelGGL(k_wstat_partial, dim3(nb), dim3(SB), 0, s, w, n, part);
   hipLaunchKernelGGL(k_wstat_final, dim3(1), dim3(64), 0, s, part, nb, part + NS * nb);
   // rank of the quantile: ceil(q n) - 1
@@ -200,8 +219,6 @@ extern "C" mf_status mf_weight_stats(const double* w, int64_t n, double q, doubl
                        hipMemcpyAsync(res, st, sizeof(res), hipMemcpyDeviceToHost, s) != hipSuccess ||
                        hipStreamSynchronize(s) != hipSuccess))
     ret = MF_EDEVICE;
-  (void)hipFreeAsync(part, s);
-  (void)hipFreeAsync(st, s);
   (void)hipStreamSynchronize(s);
   if (ret != MF_OK) return mf::set_error(ret, "weight statistics failed on the device");
   if (tot[3] > 0.0) return mf::set_error(MF_EINVAL, "%.0f weights are NaN", tot[3]);

@@ -401,6 +401,51 @@ def test_vjp_is_the_ordered_contraction():
         assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(dw).sum(axis=1).max())
 
 
+def test_handle_free_calls_work_in_caller_scratch():
+    """mf_vjp, mf_weight_stats and mf_vegas_refine allocate nothing: they run
+    in the scratch the caller passes, refuse a workspace smaller than the
+    size they report (or misaligned) with MF_EINVAL before touching the
+    device, and give the same bits with a reused, dirty workspace."""
+    import ctypes
+
+    L = mf.lib()
+    rng = np.random.default_rng(93)
+    k, n = 9, 70001
+    dw = torch.from_numpy(rng.normal(size=(k, n))).cuda()
+    g = torch.from_numpy(rng.normal(size=n)).cuda()
+    need = L.mf_vjp_workspace(k, n)
+    assert need >= 8 * k and L.mf_vjp_workspace(0, n) == 0
+    out = torch.empty(k, dtype=torch.float64, device="cuda")
+    work = torch.full(((need + 7) // 8 + 1,), float("nan"), dtype=torch.float64, device="cuda")
+    assert L.mf_vjp(dw.data_ptr(), k, g.data_ptr(), n, out.data_ptr(), work.data_ptr(), need - 8, None) == mf.MF_EINVAL
+    assert L.mf_vjp(dw.data_ptr(), k, g.data_ptr(), n, out.data_ptr(), work.data_ptr() + 4, need, None) == mf.MF_EINVAL
+    assert L.mf_vjp(dw.data_ptr(), k, g.data_ptr(), n, out.data_ptr(), None, need, None) == mf.MF_EINVAL
+    assert L.mf_vjp(dw.data_ptr(), k, g.data_ptr(), n, out.data_ptr(), work.data_ptr(), need, None) == mf.MF_OK
+    first = out.cpu().numpy().copy()
+    assert L.mf_vjp(dw.data_ptr(), k, g.data_ptr(), n, out.data_ptr(), work.data_ptr(), need, None) == mf.MF_OK
+    assert np.array_equal(out.cpu().numpy(), first)
+    assert np.array_equal(first, mf.vjp(dw, g).cpu().numpy())
+
+    w = torch.from_numpy(np.abs(rng.normal(size=n))).cuda()
+    need = L.mf_weight_stats_workspace(n)
+    res = np.zeros(5)
+    work = torch.full(((need + 7) // 8,), float("nan"), dtype=torch.float64, device="cuda")
+    assert L.mf_weight_stats(w.data_ptr(), n, 0.5, res.ctypes.data, work.data_ptr(), need - 8, None) == mf.MF_EINVAL
+    assert L.mf_weight_stats(w.data_ptr(), n, 0.5, res.ctypes.data, work.data_ptr(), need, None) == mf.MF_OK
+    ref = mf.weight_stats(w, 0.5)
+    assert res[0] == ref["mean"] and res[1] == ref["max"] and res[2] == ref["quantile"]
+    assert res[2] == np.sort(w.cpu().numpy())[int(np.ceil(0.5 * n)) - 1]
+
+    e = torch.from_numpy(si.random_grid(3, 50, seed=94)).cuda()
+    h = torch.from_numpy(rng.random((3, 50)) + 0.1).cuda()
+    st = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    assert L.mf_vegas_refine(e.data_ptr(), h.data_ptr(), 3, 50, 1.5, None, None) == mf.MF_EINVAL
+    e2 = e.clone()
+    assert L.mf_vegas_refine(e2.data_ptr(), h.data_ptr(), 3, 50, 1.5, st.data_ptr(), None) == mf.MF_OK
+    assert int(st.item()) == 0
+    assert np.max(np.abs(e2.cpu().numpy() - oracle.vegas_refine(si.random_grid(3, 50, seed=94), h.cpu().numpy()))) < 1e-10
+
+
 QUARK_PROCS = [("uux>ttxg", "uu~"), ("ddx>ttxg", "dd~"), ("qg>ttxq", "qg")]
 
 
