@@ -645,12 +645,20 @@ struct GemmArgs {
   int colsum;
 };
 
-constexpr int GLD = 40;  // LDS row stride (bf16) of a staged 32-wide k slice
+constexpr int GK = 64;        // k depth of one staged slice
+constexpr int GLD = GK + 8;   // LDS row stride (bf16) of a staged slice
 
+// C = A B over k in [kchunk z, kchunk (z+1)) for the 64 x 64 output tile of
+// the workgroup; four waves of 32 x 32, v_mfma_f32_16x16x32_bf16.  A is
+// staged from k-contiguous rows A[m lda + k]; B from B[n ldb + k] (B_NC = 0)
+// or B[k ldb + n] (B_NC = 1, transposed into LDS).  The k slices are double
+// buffered: the next slice's global loads are issued into registers before
+// the current slice's products, and each slice costs one barrier.
 template <int A_KC, int B_NC, int EPI>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) bf16 As[64 * GLD];
-  __shared__ __attribute__((aligned(16))) bf16 Bs[64 * GLD];
+  static_assert(A_KC == 1, "A is staged from k-contiguous rows");
+  __shared__ __attribute__((aligned(16))) bf16 As[2][64 * GLD];
+  __shared__ __attribute__((aligned(16))) bf16 Bs[2][64 * GLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int row = lane & 15, quad = lane >> 4;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
@@ -667,87 +675,89 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   bf16x8 ones;
 #pragma unroll
   for (int i = 0; i < 8; ++i) ones[i] = (bf16)1.0f;
-  for (int64_t k0 = kb; k0 < ke; k0 += 32) {
-    // stage A: 64 x 32
-    // (16-byte loads where the eight elements are in range; the caller
-    // guarantees 16-byte aligned rows: base and leading dimension multiples
-    // of 8 elements)
-    if (A_KC) {
-      const int m = tid >> 2, k8 = (tid & 3) * 8;
-      const int gm = m0 + m;
-      bf16x8 v;
-      if (gm < g.M && k0 + k8 + 8 <= ke) {
-        v = *reinterpret_cast<const bf16x8*>(g.A + (int64_t)gm * g.lda + k0 + k8);
+  // this thread's share of a slice: rows (or k) r0 and r0 + 32, eight
+  // consecutive elements from c8 (16-byte loads where the eight elements are
+  // in range; the caller guarantees 16-byte aligned rows: base and leading
+  // dimension multiples of 8 elements)
+  const int r0 = tid >> 3, c8 = (tid & 7) * 8;
+  bf16x8 ra[2], rb[2];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int gm = m0 + r0 + 32 * h;
+      if (gm < g.M && k0 + c8 + 8 <= ke) {
+        ra[h] = *reinterpret_cast<const bf16x8*>(g.A + (int64_t)gm * g.lda + k0 + c8);
       } else {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const int64_t gk = k0 + k8 + i;
-          v[i] = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.lda + gk] : (bf16)0.0f;
+          const int64_t gk = k0 + c8 + i;
+          ra[h][i] = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.lda + gk] : (bf16)0.0f;
         }
       }
-      *reinterpret_cast<bf16x8*>(As + m * GLD + k8) = v;
-    } else {
-      const int k = tid >> 3, m8 = (tid & 7) * 8;
-      const int64_t gk = k0 + k;
-      bf16x8 v;
-      if (gk < ke && m0 + m8 + 8 <= g.M) {
-        v = *reinterpret_cast<const bf16x8*>(g.A + gk * g.lda + m0 + m8);
+      if (B_NC) {
+        const int64_t gk = k0 + r0 + 32 * h;
+        if (gk < ke && n0 + c8 + 8 <= g.N) {
+          rb[h] = *reinterpret_cast<const bf16x8*>(g.B + gk * g.ldb + n0 + c8);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int gn = n0 + c8 + i;
+            rb[h][i] = (gn < g.N && gk < ke) ? g.B[gk * g.ldb + gn] : (bf16)0.0f;
+          }
+        }
       } else {
+        const int gn = n0 + r0 + 32 * h;
+        if (gn < g.N && k0 + c8 + 8 <= ke) {
+          rb[h] = *reinterpret_cast<const bf16x8*>(g.B + (int64_t)gn * g.ldb + k0 + c8);
+        } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int gm = m0 + m8 + i;
-          v[i] = (gm < g.M && gk < ke) ? g.A[gk * g.lda + gm] : (bf16)0.0f;
+          for (int i = 0; i < 8; ++i) {
+            const int64_t gk = k0 + c8 + i;
+            rb[h][i] = (gn < g.N && gk < ke) ? g.B[(int64_t)gn * g.ldb + gk] : (bf16)0.0f;
+          }
         }
       }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) As[(m8 + i) * GLD + k] = v[i];
     }
-    // stage B: 32 x 64, stored n-major
-    if (B_NC) {
-      const int k = tid >> 3, n8 = (tid & 7) * 8;
-      const int64_t gk = k0 + k;
-      bf16x8 v;
-      if (gk < ke && n0 + n8 + 8 <= g.N) {
-        v = *reinterpret_cast<const bf16x8*>(g.B + gk * g.ldb + n0 + n8);
+  };
+  // A rows m-major, B rows n-major in LDS, each row GK consecutive k
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      *reinterpret_cast<bf16x8*>(&As[buf][(r0 + 32 * h) * GLD + c8]) = ra[h];
+      if (B_NC) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Bs[buf][(c8 + i) * GLD + r0 + 32 * h] = rb[h][i];
       } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int gn = n0 + n8 + i;
-          v[i] = (gn < g.N && gk < ke) ? g.B[gk * g.ldb + gn] : (bf16)0.0f;
-        }
+        *reinterpret_cast<bf16x8*>(&Bs[buf][(r0 + 32 * h) * GLD + c8]) = rb[h];
       }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[(n8 + i) * GLD + k] = v[i];
-    } else {
-      const int nn = tid >> 2, k8 = (tid & 3) * 8;
-      const int gn = n0 + nn;
-      bf16x8 v;
-      if (gn < g.N && k0 + k8 + 8 <= ke) {
-        v = *reinterpret_cast<const bf16x8*>(g.B + (int64_t)gn * g.ldb + k0 + k8);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int64_t gk = k0 + k8 + i;
-          v[i] = (gn < g.N && gk < ke) ? g.B[(int64_t)gn * g.ldb + gk] : (bf16)0.0f;
-        }
-      }
-      *reinterpret_cast<bf16x8*>(Bs + nn * GLD + k8) = v;
     }
+  };
+  load(kb);
+  int buf = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += GK, buf ^= 1) {
+    // the buffer written here was last read two slices ago, before the
+    // previous slice's barrier
+    store(buf);
     __syncthreads();
-    bf16x8 a[2], b[2];
+    if (k0 + GK < ke) load(k0 + GK);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(As + (wm + 16 * i + row) * GLD + 8 * quad);
+    for (int kk = 0; kk < GK; kk += 32) {
+      bf16x8 a[2], b[2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(Bs + (wn + 16 * j + row) * GLD + 8 * quad);
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][(wm + 16 * i + row) * GLD + kk + 8 * quad]);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn + 16 * j + row) * GLD + kk + 8 * quad]);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
-    if (sums) {
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) accs[j] = mfma16(ones, b[j], accs[j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+      if (sums) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accs[j] = mfma16(ones, b[j], accs[j]);
+      }
     }
-    __syncthreads();
   }
   if (sums && quad == 0) {
 #pragma unroll
@@ -1021,6 +1031,10 @@ namespace {
 
 constexpr int64_t SPLITK_BLOCKS = 512;
 constexpr int64_t SPLITK_MIN = 256;
+// at most this many chunks: the ordered reduction sums them sequentially per
+// output, which for the narrow first-layer gradient (four output tiles) would
+// otherwise take 128 partials
+constexpr int64_t SPLITK_MAX = 32;
 
 mf_status launch_err(const char* what) {
   hipError_t e = hipGetLastError();
@@ -1036,10 +1050,12 @@ void gemm(const GemmArgs& a, int Z, hipStream_t s) {
 
 // Number of event chunks of a weight-gradient product over n events with an
 // M x N output: enough workgroups to fill the chip (about SPLITK_BLOCKS),
-// chunks of at least SPLITK_MIN events.  Non-decreasing in n.
+// chunks of at least SPLITK_MIN events, at most SPLITK_MAX chunks.
+// Non-decreasing in n.
 int64_t splitk(int64_t n, int M, int N) {
   const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
   int64_t z = (SPLITK_BLOCKS + tiles - 1) / tiles;
+  z = z < SPLITK_MAX ? z : SPLITK_MAX;
   const int64_t zmax = (n + SPLITK_MIN - 1) / SPLITK_MIN;
   z = z < zmax ? z : zmax;
   return z < 1 ? 1 : z;
