@@ -1064,11 +1064,13 @@ int64_t splitk(int64_t n, int M, int N) {
 // Weight and bias gradients over the batch: dW[in][out] = X^T G and
 // db[out] = column sums of G, from the event-contiguous BF16 copies
 // XT [M][ldn] and GT [N][ldn], split over events.
-void weight_grad(mf_flow* f, const bf16* XT, int64_t ldn, int M, int m_real, const bf16* GT, int N, int gpad,
+bool weight_grad(mf_flow* f, const bf16* XT, int64_t ldn, int M, int m_real, const bf16* GT, int N, int gpad,
                  int greal, int64_t n, float* out, int ldo, float* bias, hipStream_t s, int fold = 0) {
   const int64_t Z = splitk(n, M, N);
   const int64_t chunk = ((n + Z - 1) / Z + 31) / 32 * 32;
   const int Zl = (int)((n + chunk - 1) / chunk);
+  // the partials of all chunks must fit the buffer sized at creation
+  if ((size_t)Zl * (size_t)(M + 1) * (size_t)N > f->part_cap) return false;
   GemmArgs a{};
   a.A = XT;  // A(m, k) = XT[m ldn + k]
   a.lda = ldn;
@@ -1086,6 +1088,7 @@ void weight_grad(mf_flow* f, const bf16* XT, int64_t ldn, int M, int m_real, con
   const int64_t tot = (int64_t)(m_real + 1) * N;
   hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, f->d_part, Zl, M, N, m_real,
                      gpad, greal, out, ldo, fold, bias);
+  return true;
 }
 
 void run_layers(mf_flow* f, float* y, int64_t n, int64_t ld, float* logq, bool inverse, bool cache, hipStream_t s) {
@@ -1151,7 +1154,8 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     float* gb3 = gW3 + (int64_t)H * nO;
     hipLaunchKernelGGL(k_pq_backward, dim3((unsigned)((n + 255) / 256), L.dB), dim3(256), 0, s, L, C, n, f->d_gy, w,
                        f->d_scal, f->d_go, f->d_goT);
-    weight_grad(f, C.h2, ldn, H, H, f->d_goT, NB, NOP, NO, n, gW3, nO, gb3, s);
+    if (!weight_grad(f, C.h2, ldn, H, H, f->d_goT, NB, NOP, NO, n, gW3, nO, gb3, s))
+      return set_error(MF_EINVAL, "weight-gradient partials exceed the flow's buffer");
     // ga2 = (go W3^T) * leaky'(h2): A = go [n][NB], B(k=o, n=j) = W3t[o][j]
     GemmArgs a{};
     a.A = f->d_go;
@@ -1170,7 +1174,8 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     a.ref_cs = ldn;
     a.ldc = H;
     gemm<1, 1, 1>(a, 1, s);
-    weight_grad(f, C.h1, ldn, H, H, f->d_ga2T, H, 0, 0, n, gW2, H, gb2, s);
+    if (!weight_grad(f, C.h1, ldn, H, H, f->d_ga2T, H, 0, 0, n, gW2, H, gb2, s))
+      return set_error(MF_EINVAL, "weight-gradient partials exceed the flow's buffer");
     // ga1 = (ga2 W2^T) * leaky'(h1): B(k=j2, n=j1) = W2[j1][j2] = W2t[j2][j1]
     a.A = f->d_ga2;
     a.lda = H;
@@ -1182,7 +1187,8 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     a.CbT = f->d_ga1T;
     a.ref = C.h1;
     gemm<1, 1, 1>(a, 1, s);
-    weight_grad(f, C.xa, ldn, KA, L.dA, f->d_ga1T, H, 0, 0, n, gW1, H, gb1, s, KLO);
+    if (!weight_grad(f, C.xa, ldn, KA, L.dA, f->d_ga1T, H, 0, 0, n, gW1, H, gb1, s, KLO))
+      return set_error(MF_EINVAL, "weight-gradient partials exceed the flow's buffer");
     // gx = ga1 W1^T: B(k=j, n=i) = W1[i][j] = W1t[j][i]
     GemmArgs b{};
     b.A = f->d_ga1;
@@ -1275,8 +1281,11 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
   const int64_t capp = (cap + 7) / 8 * 8;
   size_t per_layer = sizeof(bf16) * (size_t)capp * (KA + 2 * H) + sizeof(float) * (size_t)cap * (dBmax * NOP + d);
   per_layer = (per_layer + 255) / 256 * 256;  // every layer's caches start 256-byte aligned
-  f->part_cap = (size_t)std::max({splitk(cap, H, (int)(dBmax * NOP)) * (H + 1) * dBmax * NOP,
-                                   splitk(cap, H, H) * (H + 1) * H, splitk(cap, KA, H) * (KA + 1) * H});
+  // the chunk count depends on the output tiles, so a narrower output could
+  // need more partials than the widest one: the maximum over every width
+  int64_t pc = std::max(splitk(cap, H, H) * (H + 1) * H, splitk(cap, KA, H) * (KA + 1) * H);
+  for (int dB = 1; dB <= dBmax; ++dB) pc = std::max(pc, splitk(cap, H, dB * NOP) * (H + 1) * dB * NOP);
+  f->part_cap = (size_t)pc;
   if (hipMalloc(&f->d_p, sizeof(float) * off) != hipSuccess || hipMalloc(&f->d_g, sizeof(float) * off) != hipSuccess ||
       hipMalloc(&f->d_m1, sizeof(float) * off) != hipSuccess || hipMalloc(&f->d_m2, sizeof(float) * off) != hipSuccess ||
       hipMalloc(&f->d_w16, sizeof(bf16) * w16) != hipSuccess || hipMalloc(&f->d_b3p, sizeof(float) * b3) != hipSuccess ||
