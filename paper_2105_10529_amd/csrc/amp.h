@@ -94,10 +94,13 @@ template <class R> __device__ __forceinline__ void opaque4(V4<R>& p) {
 // Colour-ordered three-gluon vertex contracted with two currents X, Y of
 // outgoing momenta PX, PY (coupling and the off-shell propagator excluded):
 //   X (2PX+PY).Y + (X.Y)(PY-PX) - Y (PX+2PY).X
+// X and Y are always complete Berends-Giele currents (or polarisation
+// vectors) of on-shell transverse gluons, which are conserved, PX.X =
+// PY.Y = 0, so the coefficients are formed as 2 PX.Y and 2 PY.X.
 template <class R>
 __device__ __forceinline__ V4<R> v3(const V4<R>& X, const V4<R>& Y, const V4<R>& PX, const V4<R>& PY) {
-  R a = R(2.0) * mdot(PX, Y) + mdot(PY, Y);
-  R d = mdot(PX, X) + R(2.0) * mdot(PY, X);
+  R a = R(2.0) * mdot(PX, Y);
+  R d = R(2.0) * mdot(PY, X);
   R c = mdot(X, Y);
   return V4<R>{a * X.t + c * (PY.t - PX.t) - d * Y.t, a * X.x + c * (PY.x - PX.x) - d * Y.x,
                a * X.y + c * (PY.y - PX.y) - d * Y.y, a * X.z + c * (PY.z - PX.z) - d * Y.z};
@@ -107,8 +110,8 @@ __device__ __forceinline__ V4<R> v3(const V4<R>& X, const V4<R>& Y, const V4<R>&
 // this way instead of adding separately rounded vertices).
 template <class R>
 __device__ __forceinline__ V4<R> v3_acc(const V4<R>& X, const V4<R>& Y, const V4<R>& PX, const V4<R>& PY, V4<R> o) {
-  R a = R(2.0) * mdot(PX, Y) + mdot(PY, Y);
-  R d = mdot(PX, X) + R(2.0) * mdot(PY, X);
+  R a = R(2.0) * mdot(PX, Y);
+  R d = R(2.0) * mdot(PY, X);
   R c = mdot(X, Y);
   o.t = ((o.t + a * X.t) + c * (PY.t - PX.t)) - d * Y.t;
   o.x = ((o.x + a * X.x) + c * (PY.x - PX.x)) - d * Y.x;

@@ -235,13 +235,14 @@ def _colour_lines(w, ind, groups, name):
 
 
 # Real-flop cost of each device routine in amp.h (a fused multiply-add counts
-# as two flops): Minkowski product 7; v3 63; w4 42; scaling a four-vector 4;
+# as two flops): Minkowski product 7; v3 47 (three Minkowski products, the
+# conserved currents' PX.X and PY.Y being zero); w4 42; scaling a four-vector 4;
 # adding four-vectors 4; slash(real J, spinor) 42; prop 63 (five coefficient
 # products, two sums, then 8 x (one product + three fused multiply-adds));
 # adding spinors 8; ubar_dot 30; cabs2 and cre_dot 3.  The accumulating forms
 # (v3_acc, w4_sub, slash_acc, cabs2_acc, cre_dot_acc) cost exactly the plain
 # routine plus the addition they absorb.
-COST = {"v3": 63, "w4": 42, "vscale": 4, "vadd": 4, "slash": 42, "prop": 63, "sadd": 8, "ubar": 30,
+COST = {"v3": 47, "w4": 42, "vscale": 4, "vadd": 4, "slash": 42, "prop": 63, "sadd": 8, "ubar": 30,
         "abs2": 3, "redot": 3, "mdot": 7}
 
 

@@ -82,7 +82,7 @@ def test_flop_counts_are_consistent():
     # positions 2..4: J(2,3), J(3,4), J(2,4) and the spinor currents from 4, 3, 2
     shared = (2 * (c["v3"] + c["vscale"]) + (2 * c["v3"] + c["w4"] + 2 * c["vadd"] + c["vscale"])
               + sum(L * c["slash"] + (L - 1) * c["sadd"] + c["prop"] for L in range(1, 4)))
-    assert shared == 779
+    assert shared == 715
     assert fc["amplitudes_single_state"] == 120 * per_ordering - 60 * shared
     # the summed mode builds the gluon currents once for both antitop helicities
     gluon = (4 * (c["v3"] + c["vscale"]) + 3 * (2 * c["v3"] + c["w4"] + 2 * c["vadd"] + c["vscale"])
@@ -99,7 +99,7 @@ def test_shared_antitop_counts():
     """g g -> t t~ g and g g -> t t~ g g build each ordering's gluon currents
     once per gluon polarisation state for both antitop helicities: the count
     drops by one set of gluon currents per gluon polarisation state."""
-    for m, before in ((3, 54186), (4, 713978)):
+    for m, before in ((3, 51882), (4, 680186)):
         fc = gen_me.flop_count(m)
         assert fc["total"] == before - (fc["states"] // 2) * fc["gluon_currents_per_polarisation"]
 
