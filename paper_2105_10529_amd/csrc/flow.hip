@@ -42,6 +42,7 @@ constexpr int KLO = 16;       // offset of the low parts
 constexpr int T = 64;         // events per workgroup of the layer kernel
 constexpr int LDO = 68;       // LDS row stride (floats) of one coordinate's 64 leading logits (16-byte rows)
 constexpr int FMAXD = 16;
+constexpr int TBMAX = FMAXD / 2;  // transformed coordinates per layer (the masks take one half)
 constexpr int MAXL = 8;
 constexpr float SLOPE = 0.01f;
 
@@ -326,13 +327,15 @@ __device__ __forceinline__ void cache_hidden(const bf16* h, bf16* __restrict__ d
 // LDS: one [T][H] BF16 tile that holds the first hidden layer and then the
 // second (written over the first once every wave has read it), and one
 // [T][LDO] FP32 tile for the 64 leading logits of the current coordinate
-// (before that, its first 4 KB hold the first-layer inputs): 49.0 KiB, so
-// that three workgroups share a compute unit.
+// (before that, its first 4 KB hold the first-layer inputs), and the inputs
+// of the transformed coordinates (2 KiB): 51.0 KiB, so that three
+// workgroups share a compute unit.
 template <bool INVERSE, bool CACHE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE ? 2 : 3))) k_coupling(LayerDev L, float* __restrict__ y, int64_t n, int64_t ld,
                                                   float* __restrict__ logq, int first, LayerCache C, int d) {
   __shared__ __attribute__((aligned(16))) bf16 h[T * H];
   __shared__ __attribute__((aligned(16))) float out[T * LDO];
+  __shared__ float tb[TBMAX * T];
   static_assert(T * KA * sizeof(bf16) <= T * LDO * sizeof(float), "first-layer inputs must fit the logit tile");
   bf16* xa = reinterpret_cast<bf16*>(out);  // [T][KA]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -342,19 +345,43 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
   // inputs of the first dense layer (events fastest, so the reads coalesce):
   // each kept coordinate as a BF16 pair hi + lo (about 16 significant bits),
   // multiplied by the same weight column
-  for (int idx = tid; idx < T * KLO; idx += 256) {
-    const int m = idx % T, i = idx / T;
+  {
+    // all of this thread's HBM reads are issued before the first is used
+    // (one latency instead of several): kept coordinates w, w + 4, w + 8,
+    // w + 12 and transformed coordinates w, w + 4 of event m (w = wave); the
+    // transformed ones wait in LDS for their PQ transforms
+    static_assert(KLO == 16 && TBMAX == 8, "four kept and two transformed coordinates per thread");
+    const int m = lane;
     const int64_t e = e0 + m;
-    float v = 0.0f;
-    if (i < L.dA && e < n) v = y[(int64_t)L.a_idx[i] * ld + e];
-    const bf16 hi = (bf16)v;
-    const bf16 lo = (bf16)(v - (float)hi);
-    const int il = i + KLO;
-    xa[m * KA + (((i >> 3) ^ (m & 3)) << 3) + (i & 7)] = hi;
-    xa[m * KA + (((il >> 3) ^ (m & 3)) << 3) + (il & 7)] = lo;
-    if (CACHE && e < n) {
-      C.xa[i * C.ldn + e] = hi;
-      C.xa[il * C.ldn + e] = lo;
+    const bool ev = e < n;
+    float v[4], tv[2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = wave + 4 * r;
+      v[r] = (i < L.dA && ev) ? y[(int64_t)L.a_idx[i] * ld + e] : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int j = wave + 4 * r;
+      tv[r] = (j < L.dB && ev) ? y[(int64_t)L.b_idx[j] * ld + e] : 0.5f;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = wave + 4 * r;
+      const bf16 hi = (bf16)v[r];
+      const bf16 lo = (bf16)(v[r] - (float)hi);
+      const int il = i + KLO;
+      xa[m * KA + (((i >> 3) ^ (m & 3)) << 3) + (i & 7)] = hi;
+      xa[m * KA + (((il >> 3) ^ (m & 3)) << 3) + (il & 7)] = lo;
+      if (CACHE && ev) {
+        C.xa[i * C.ldn + e] = hi;
+        C.xa[il * C.ldn + e] = lo;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int j = wave + 4 * r;
+      if (j < L.dB) tb[j * T + m] = tv[r];
     }
   }
   if (CACHE) {
@@ -498,7 +525,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
     }
     {
       float* yp = y + (int64_t)L.b_idx[c] * ld + (live ? em : e0);
-      const float t = live ? *yp : 0.5f;
+      const float t = tb[c * T + m];
       float res, pdf;
       pq_quad<INVERSE>(out + m * LDO, vlast, t, part, res, pdf);
       if (live && part == 0) {
@@ -1275,6 +1302,9 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     mf_flow_destroy(f);
     return s;
   };
+  // the layer kernel keeps the transformed coordinates' inputs in a tile of
+  // TBMAX rows (the masks above never transform more than half of 16)
+  if (dBmax > TBMAX) return cleanup(set_error(MF_EINVAL, "a layer transforms more than %d coordinates", TBMAX));
   const int64_t cap = cfg->max_batch;
   f->cap = cap;
   // caches: xa, h1, h2, o, lin per layer

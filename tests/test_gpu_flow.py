@@ -120,15 +120,21 @@ def test_forward_and_inverse_match_oracle(d, n):
         assert np.array_equal(lqm.cpu().numpy(), lq[:m].astype(np.float32))
     # GPU round trip: inverse(forward(y)) = y with the same BF16 layers, to
     # FP32 accuracy.  One FP32 rounding of a CDF value (6e-8) moves the
-    # inverse by 6e-8 / pdf, and a moved kept coordinate changes the next
-    # layers' inputs; an FP32 replay of this arithmetic on the CPU gives, for
-    # these parameters, median |dy| 1e-8, 99th percentile 2e-7, maximum 3e-4,
-    # and |d log q| median 2e-6, 99th percentile 7e-5, maximum 1e-2.
+    # inverse by 6e-8 / pdf; where such a moved coordinate is a kept input of
+    # an inner layer and the move changes a bit of its BF16 low part, that
+    # layer's logits change and the point moves by ~1e-5.  Measured for these
+    # parameters at d = 13 on 7000 events: |dy| 95th percentile 6e-8 with
+    # 0.4 % of the coordinates above 1e-5, |d log q| 95th percentile 1e-5
+    # with 0.7 % of the events above 1e-3 (up to 1 % in blocks of 700).
+    # The 99th percentile sits on the edge of that tail, so the checks are a
+    # quantile below it and the tail's size.
     yr, lqr = f.inverse(_dev32(z))
     dy = np.abs(yr.cpu().numpy().T - y)
     dl = np.abs(lqr.cpu().numpy() - lq)
-    assert np.median(dy) < 1e-7 and np.quantile(dy, 0.99) < 2e-6 and dy.max() < 2e-3, np.quantile(dy, [0.5, 0.99, 1])
-    assert np.median(dl) < 2e-5 and np.quantile(dl, 0.99) < 1e-3 and dl.max() < 5e-2, np.quantile(dl, [0.5, 0.99, 1])
+    assert np.median(dy) < 1e-7 and np.quantile(dy, 0.95) < 1e-6 and np.mean(dy > 1e-5) < 0.02 and dy.max() < 2e-3, \
+        (np.quantile(dy, [0.5, 0.95, 1]), np.mean(dy > 1e-5))
+    assert np.median(dl) < 2e-5 and np.quantile(dl, 0.95) < 1e-4 and np.mean(dl > 1e-3) < 0.03 and dl.max() < 5e-2, \
+        (np.quantile(dl, [0.5, 0.95, 1]), np.mean(dl > 1e-3))
 
 
 def _set(f, params):
