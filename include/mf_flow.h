@@ -33,6 +33,11 @@
  * mf_last_error(); "device" pointers are HIP device pointers owned by the
  * caller; points are [ndim][n] FP32 structure-of-arrays; `stream` is a
  * hipStream_t or NULL; calls are asynchronous unless stated otherwise.
+ * A flow owns one more stream of its own (default priority, created with
+ * the flow): mf_flow_loss_grad runs its weight-gradient products there,
+ * ordered against `stream` by events, and leaves `stream` waiting for them,
+ * so the gradient is complete in `stream` order when the call returns.
+ * Calls on one flow must not overlap.
  *
  * Parameter layout (FP32, host): layer after layer, each as
  *   W1 [d_A][256], b1 [256], W2 [256][256], b2 [256],

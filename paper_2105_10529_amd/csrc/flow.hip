@@ -1052,6 +1052,11 @@ struct mf_flow {
   size_t part_cap = 0;
   float* d_scal = nullptr;  // wsum, loss
   std::vector<float*> d_losses;
+  // the backward pass runs the weight-gradient products on a second stream
+  // (default priority) beside the activation-gradient chain; events order
+  // the two
+  hipStream_t side = nullptr;
+  hipEvent_t ev[6] = {};
 };
 
 namespace {
@@ -1169,20 +1174,35 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     hipLaunchKernelGGL(k_loss, dim3(1), dim3(RB), 0, s, w, f->d_lq, n, f->d_scal, loss_dev);
   e = hipMemsetAsync(f->d_gy, 0, sizeof(float) * d * n, s);
   if (e != hipSuccess) return set_error(MF_EDEVICE, "gradient clear: %s", hipGetErrorString(e));
+  // Per layer the activation-gradient chain (PQ backward, ga2, ga1, gx) runs
+  // on s and the three weight-gradient products on the side stream, each
+  // started once its input exists on s; before a layer's kernels overwrite
+  // go/goT, ga2/ga2T or ga1/ga1T, s waits until the previous layer's product
+  // that reads them has run.  All split-K partials are on the side stream.
+  hipStream_t s2 = f->side;
+  enum { E_PQ, E_GA2, E_GA1, E_W3, E_W2, E_W1 };
+  bool ok = true;
+  auto rec = [&](int k, hipStream_t from) { ok = ok && hipEventRecord(f->ev[k], from) == hipSuccess; };
+  auto wait = [&](int k, hipStream_t on) { ok = ok && hipStreamWaitEvent(on, f->ev[k], 0) == hipSuccess; };
   for (int l = f->nl - 1; l >= 0; --l) {
     const LayerDev& L = f->L[l];
     const LayerCache& C = f->cache[l];
     const int NB = L.dB * NOP, nO = L.dB * NO;
+    const bool later = l < f->nl - 1;  // a previous layer's products exist
     float* gW1 = f->d_g + f->loff[l];
     float* gb1 = gW1 + (int64_t)L.dA * H;
     float* gW2 = gb1 + H;
     float* gb2 = gW2 + (int64_t)H * H;
     float* gW3 = gb2 + H;
     float* gb3 = gW3 + (int64_t)H * nO;
+    if (later) wait(E_W3, s);
     hipLaunchKernelGGL(k_pq_backward, dim3((unsigned)((n + 255) / 256), L.dB), dim3(256), 0, s, L, C, n, f->d_gy, w,
                        f->d_scal, f->d_go, f->d_goT);
-    if (!weight_grad(f, C.h2, ldn, H, H, f->d_goT, NB, NOP, NO, n, gW3, nO, gb3, s))
+    rec(E_PQ, s);
+    wait(E_PQ, s2);
+    if (!weight_grad(f, C.h2, ldn, H, H, f->d_goT, NB, NOP, NO, n, gW3, nO, gb3, s2))
       return set_error(MF_EINVAL, "weight-gradient partials exceed the flow's buffer");
+    rec(E_W3, s2);
     // ga2 = (go W3^T) * leaky'(h2): A = go [n][NB], B(k=o, n=j) = W3t[o][j]
     GemmArgs a{};
     a.A = f->d_go;
@@ -1200,9 +1220,13 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     a.ref_rs = 1;
     a.ref_cs = ldn;
     a.ldc = H;
+    if (later) wait(E_W2, s);
     gemm<1, 1, 1>(a, 1, s);
-    if (!weight_grad(f, C.h1, ldn, H, H, f->d_ga2T, H, 0, 0, n, gW2, H, gb2, s))
+    rec(E_GA2, s);
+    wait(E_GA2, s2);
+    if (!weight_grad(f, C.h1, ldn, H, H, f->d_ga2T, H, 0, 0, n, gW2, H, gb2, s2))
       return set_error(MF_EINVAL, "weight-gradient partials exceed the flow's buffer");
+    rec(E_W2, s2);
     // ga1 = (ga2 W2^T) * leaky'(h1): B(k=j2, n=j1) = W2[j1][j2] = W2t[j2][j1]
     a.A = f->d_ga2;
     a.lda = H;
@@ -1213,9 +1237,13 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     a.Cb = f->d_ga1;
     a.CbT = f->d_ga1T;
     a.ref = C.h1;
+    if (later) wait(E_W1, s);
     gemm<1, 1, 1>(a, 1, s);
-    if (!weight_grad(f, C.xa, ldn, KA, L.dA, f->d_ga1T, H, 0, 0, n, gW1, H, gb1, s, KLO))
+    rec(E_GA1, s);
+    wait(E_GA1, s2);
+    if (!weight_grad(f, C.xa, ldn, KA, L.dA, f->d_ga1T, H, 0, 0, n, gW1, H, gb1, s2, KLO))
       return set_error(MF_EINVAL, "weight-gradient partials exceed the flow's buffer");
+    rec(E_W1, s2);
     // gx = ga1 W1^T: B(k=j, n=i) = W1[i][j] = W1t[j][i]
     GemmArgs b{};
     b.A = f->d_ga1;
@@ -1234,6 +1262,9 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     if (ta > 0)
       hipLaunchKernelGGL(k_add_gx, dim3((unsigned)((ta + 255) / 256)), dim3(256), 0, s, L, f->d_gx, n, f->d_gy);
   }
+  // the gradient is complete on s once the side stream's last product is
+  wait(E_W1, s);
+  if (!ok) return set_error(MF_EDEVICE, "backward stream ordering failed");
   return launch_err("flow backward");
 }
 
@@ -1342,6 +1373,17 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
       hipMemset(f->d_w16, 0, sizeof(bf16) * w16) != hipSuccess ||
       hipMemset(f->d_b3p, 0, sizeof(float) * b3) != hipSuccess)
     return cleanup(set_error(MF_EDEVICE, "flow initialisation failed"));
+  if (hipStreamCreateWithFlags(&f->side, hipStreamNonBlocking) != hipSuccess) {
+    f->side = nullptr;
+    hipGetLastError();
+    return cleanup(set_error(MF_EDEVICE, "flow stream creation failed"));
+  }
+  for (hipEvent_t& e : f->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      hipGetLastError();
+      return cleanup(set_error(MF_EDEVICE, "flow event creation failed"));
+    }
   bf16* wp = f->d_w16;
   float* bp = f->d_b3p;
   char* cm = (char*)f->d_cachemem;
@@ -1405,6 +1447,9 @@ void mf_flow_destroy(mf_flow* f) {
   hipFree(f->d_part);
   hipFree(f->d_scal);
   for (float* p : f->d_losses) hipFree(p);
+  for (hipEvent_t e : f->ev)
+    if (e) hipEventDestroy(e);
+  if (f->side) hipStreamDestroy(f->side);
   delete f;
 }
 
