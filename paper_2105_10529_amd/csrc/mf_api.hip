@@ -602,6 +602,21 @@ int blocks_for(int64_t n) {
   return (int)b;
 }
 
+// Blocks of a VEGAS iteration: once there are more than 256 chunks of
+// events, at least 16 chunks per block, in whole rounds of 256 blocks (the
+// fused kernel runs one block per compute unit at a time), so that a
+// block's kept events fill several passes of its waves and no round is
+// mostly idle; one chunk per block up to 256 chunks.
+int iter_blocks(int64_t n) {
+  const int64_t chunks = (n + BLOCK - 1) / BLOCK;
+  if (chunks <= 256) return blocks_for(n);
+  int64_t b = (chunks + 15) / 16;
+  b = (b + 255) / 256 * 256;
+  if (b < 256) b = 256;
+  if (b > MAX_BLOCKS) b = MAX_BLOCKS;
+  return (int)b;
+}
+
 size_t vegas_lds_bytes(int d, int nb) {
   return sizeof(double) * (size_t)(d * (nb + 1) + 4 * NXK + WAVES * (d + 1) * nb + WAVES * 4 + 2 * BLOCK +
                                   d * BLOCK) +
@@ -648,10 +663,10 @@ void noalloc_scratch_init(int dev) {
   else (void)hipGetLastError();
 }
 
-// Grow the per-block selection lists to the chunks of an n-event iteration.
-mf_status ensure_select(mf_process* p, int64_t n, hipStream_t s) {
+// Grow the per-block selection lists to the chunks of an n-event pass over
+// nblk blocks.
+mf_status ensure_select(mf_process* p, int64_t n, int nblk, hipStream_t s) {
   if (n > (int64_t)INT32_MAX) return fail(MF_EINVAL, "n_events must be below 2^31 for fused iterations");
-  const int nblk = blocks_for(n);
   const int64_t cap = (n + (int64_t)nblk * BLOCK - 1) / ((int64_t)nblk * BLOCK) * BLOCK;
   if (p->d_selcnt && p->sel_cap >= cap) return MF_OK;
   HIP_TRY(hipStreamSynchronize(s));
@@ -675,7 +690,7 @@ mf_status run_integrand(mf_process* p, const double* x, int64_t n, double* w, hi
     if (e != hipSuccess) return fail(MF_EDEVICE, "integrand: %s", hipGetErrorString(e));
     return MF_OK;
   }
-  mf_status st = ensure_select(p, n, s);
+  mf_status st = ensure_select(p, n, blocks_for(n), s);
   if (st != MF_OK) return st;
   p->L.integrand(p->dc, x, n, w, blocks_for(n), p->d_sel, p->d_selcnt, p->sel_cap, s);
   return check_stream_launch("k_integrand");
@@ -953,7 +968,7 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
   const int d = p->ndim, nb = p->nb;
   if (o->edges_in) HIP_TRY(hipMemcpyAsync(p->d_edges, o->edges_in, sizeof(double) * d * (nb + 1),
                                           hipMemcpyDeviceToDevice, s));
-  const int nblk = blocks_for(o->n_events);
+  const int nblk = iter_blocks(o->n_events);
   const size_t lds = vegas_lds_bytes(d, nb);
   if (o->flow) {
     if (o->adapt) return fail(MF_EINVAL, "the grid is frozen under a flow proposal (adapt must be 0)");
@@ -968,7 +983,7 @@ mf_status mf_integrate(mf_process* p, const mf_integrate_opts* o, mf_result* r) 
     if (st != MF_OK) return st;
   }
   if (p->L.fused && (!o->flow || can_fallback)) {
-    mf_status st = ensure_select(p, o->n_events, s);
+    mf_status st = ensure_select(p, o->n_events, nblk, s);
     if (st != MF_OK) return st;
   }
   // the proposal of the current iteration: the flow until a fallback
@@ -1343,7 +1358,7 @@ mf_status mf_grad(mf_process* p, const mf_integrate_opts* o, double* out, double
   const size_t lds = sizeof(double) * (d * (nb + 1) + WAVES * GV * 4);
   if (!p->L.grad_vegas) return fail(MF_ENOTSUP, "derivatives are not built for this process");
   if (p->dc.dyn_scale) return fail(MF_ENOTSUP, "derivatives are not built with the dynamic scale");
-  mf_status sst = ensure_select(p, o->n_events, s);
+  mf_status sst = ensure_select(p, o->n_events, nblk, s);
   if (sst != MF_OK) return sst;
   p->L.grad_vegas(p->dc, p->d_edges, o->iter_offset, o->n_events, p->cfg.seed, p->d_part, nblk, lds, p->d_sel,
                   p->d_selcnt, p->sel_cap, s);

@@ -150,10 +150,11 @@ def _oracle_iteration(ng, n, grid_seed, iteration, seed):
                                                  (2, 600_000, "fp32", 2), (2, 600_000, "fp64", 1),
                                                  (2, 600_000, "fp64", 2)])
 def test_vegas_iteration_full_geometry_matches_oracle(ng, n, precision, form):
-    """One iteration in the launch geometry of the full-size runs: 2048 blocks
-    of 256 threads, each block looping over two or three 256-event chunks
-    (2048 x 256 = 524288 events per pass, so 600000 and 1100000 events leave
-    a ragged last pass).  That carried path -- per-wave LDS accumulators and
+    """One iteration in the looping geometry of the full-size runs: blocks of
+    256 threads, each looping over several 256-event chunks (an iteration has
+    at least 16 chunks per block once it has more than 256 chunks: 600000
+    events run on 256 blocks of 9 or 10 chunks, 1100000 on 512 blocks of 8 or
+    9, the last pass ragged).  That carried path -- per-wave LDS accumulators and
     histograms and the per-block lists of kept events persisting across
     chunks -- must give the oracle's iteration: FP64 to rounding (1e-12 on the
     estimate, 1e-10 on the refined edges, the same count of non-zero events),
