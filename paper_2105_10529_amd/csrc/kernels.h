@@ -62,31 +62,24 @@ __global__ void __launch_bounds__(BLOCK) k_select_points(DevCfg c, const double*
   if (tid == 0) cnt[blockIdx.x] = qn;
 }
 
-// pairs = 1 (g g channel only): two neighbouring lanes share an event, each
-// summing every other gluon polarisation state, and the pair adds its two
-// weights; for batches too small to give every SIMD a wave of its own.
 template <int NG, int CH, class RA>
 __global__ void __launch_bounds__(BLOCK) k_integrand(DevCfg c, const double* __restrict__ u, int64_t n,
                                                      double* __restrict__ w, const int* __restrict__ list,
-                                                     const int* __restrict__ cnt, int64_t cap, int pairs) {
+                                                     const int* __restrict__ cnt, int64_t cap) {
   const int* mine_list = list + (int64_t)blockIdx.x * cap;
   const int nsel = __builtin_amdgcn_readfirstlane(cnt[blockIdx.x]);
-  const int pr = CH == 0 ? __builtin_amdgcn_readfirstlane(pairs) : 0;
-  const int per = BLOCK >> pr;  // events per pass
-  const int64_t nchunk = (nsel + per - 1) / per;
+  const int64_t nchunk = (nsel + BLOCK - 1) / BLOCK;
   for (int64_t it = 0; it < nchunk; ++it) {
-    const int64_t j0 = it * per + (threadIdx.x >> pr);
+    const int64_t j0 = it * BLOCK + threadIdx.x;
     const bool live = j0 < nsel;
     const int64_t e = mine_list[live ? j0 : 0];  // idle lanes recompute the block's first point
     double x[MAXD];
 #pragma unroll
     for (int j = 0; j < MAXD; ++j)
       if (j < c.ndim) x[j] = u[(int64_t)j * n + e];
-    EventOut<double> r = event_weight<NG, CH, RA, double>(c, x, c.mt, c.pdfc, pr ? (int)(threadIdx.x & 1) : 0, 1 + pr);
-    double v = r.w;
-    if (pr) v += __shfl_xor(v, 1);
-    v = isfinite(v) ? v : 0.0;
-    if (live && (pr == 0 || (threadIdx.x & 1) == 0)) w[e] = v;
+    EventOut<double> r = event_weight<NG, CH, RA, double>(c, x, c.mt, c.pdfc);
+    const double v = isfinite(r.w) ? r.w : 0.0;
+    if (live) w[e] = v;
   }
 }
 
@@ -520,8 +513,7 @@ Launchers make_launchers() {
   L.integrand = [](const DevCfg& c, const double* u, int64_t n, double* w, int nblk, int* list, int* cnt,
                    int64_t cap, hipStream_t s) {
     hipLaunchKernelGGL((k_select_points<NG>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w, list, cnt, cap);
-    const int pairs = CH == 0 && n <= PAIR_MAX_POINTS ? 1 : 0;
-    hipLaunchKernelGGL((k_integrand<NG, CH, RA>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w, list, cnt, cap, pairs);
+    hipLaunchKernelGGL((k_integrand<NG, CH, RA>), dim3(nblk), dim3(BLOCK), 0, s, c, u, n, w, list, cnt, cap);
   };
   L.vegas = [](const DevCfg& c, const double* edges, uint64_t iter, int64_t N, uint64_t seed, double* part,
                int pstride, int nblk, size_t lds, int* list, int* cnt, int64_t cap, double* wk, hipStream_t s) {

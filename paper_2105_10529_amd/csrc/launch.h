@@ -10,10 +10,6 @@
 namespace mf {
 
 constexpr int BLOCK = 256;
-// mf_integrand batches of at most this many points (the g g channel) give
-// each event two lanes, each summing half of the gluon polarisation states:
-// such a batch keeps too few events per block to give every SIMD a wave
-constexpr int64_t PAIR_MAX_POINTS = 131072;
 constexpr int WAVES = BLOCK / 64;
 constexpr int MAX_BLOCKS = 2048;
 constexpr int PART_HEAD = 8;  // S1 hi, S1 lo, S2 hi, S2 lo, nonzero, nonfinite, pad, pad

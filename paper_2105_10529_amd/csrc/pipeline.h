@@ -292,11 +292,9 @@ __device__ __forceinline__ Dual<float> to_amp_s(Dual<double> x, Dual<float>*) { 
 // Colour- and polarisation-summed |M|^2 (g = 1) for g g -> t t~ + NG g.
 // E: beam energy; gluons in emission order; top/atop from the phase space.
 // Momenta and per-event invariants stay in the kinematic type RK; the
-// helicity loops run in the amplitude type RA.  hg0, hgs: only the gluon
-// polarisation states hg0, hg0 + hgs, ... are summed.
+// helicity loops run in the amplitude type RA.
 template <int NG, class RA, class RK>
-__device__ __forceinline__ RA me_gg(double E, const V4<double>* gl, const V4<RK>& top, const V4<RK>& atop, RK mt,
-                                    int hg0 = 0, int hgs = 1) {
+__device__ __forceinline__ RA me_gg(double E, const V4<double>* gl, const V4<RK>& top, const V4<RK>& atop, RK mt) {
   constexpr int m = NG + 2;
   V4<RK> K[m];
   V4<RA> Ep[m][2];
@@ -316,11 +314,10 @@ __device__ __forceinline__ RA me_gg(double E, const V4<double>* gl, const V4<RK>
   V4<RA> t = cvt4<RA>(top), tb = cvt4<RA>(atop);
   Sp<RA> UB[2] = {ubar_spinor(t, m_a, -1), ubar_spinor(t, m_a, 1)};
   Sp<RA> VS[2] = {v_spinor(tb, m_a, -1), v_spinor(tb, m_a, 1)};
-  if constexpr (m == 2) return me_gg_m2<RA, RK>(K, Ep, UB, VS, atop, mt, hg0, hgs);
-  else if constexpr (m == 3) return me_gg_m3<RA, RK>(K, Ep, UB, VS, atop, mt, hg0, hgs);
-  else if constexpr (std::is_same<RA, float>::value)
-    return me_gg_m4_grouped<RA, RK>(K, Ep, UB, VS, atop, mt, hg0, hgs);
-  else return me_gg_m4<RA, RK>(K, Ep, UB, VS, atop, mt, hg0, hgs);
+  if constexpr (m == 2) return me_gg_m2<RA, RK>(K, Ep, UB, VS, atop, mt);
+  else if constexpr (m == 3) return me_gg_m3<RA, RK>(K, Ep, UB, VS, atop, mt);
+  else if constexpr (std::is_same<RA, float>::value) return me_gg_m4_grouped<RA, RK>(K, Ep, UB, VS, atop, mt);
+  else return me_gg_m4<RA, RK>(K, Ep, UB, VS, atop, mt);
 }
 
 // Row spinor psibar gamma^mu chi contracted: returns the four components
@@ -413,11 +410,9 @@ __device__ __forceinline__ bool event_passes(const DevCfg& c, const double* x) {
 // The integrand at x (unit hypercube, after the VEGAS map).  Branch-free:
 // an event below threshold or outside the cuts is evaluated on safe
 // kinematics and its weight is selected to zero, so the amplitude code never
-// runs under a partial execution mask.  For the g g channel hg0, hgs select
-// the gluon polarisation states summed (the weight is linear in the sum).
+// runs under a partial execution mask.
 template <int NG, int CH, class RA, class RK>
-__device__ __forceinline__ EventOut<RK> event_weight(const DevCfg& c, const double* x, RK mt, const double* pdf,
-                                                     int hg0 = 0, int hgs = 1) {
+__device__ __forceinline__ EventOut<RK> event_weight(const DevCfg& c, const double* x, RK mt, const double* pdf) {
   EventOut<RK> out;
   double x1 = x[0], x2 = x[1];
   double shat = x1 * x2 * c.s;
@@ -437,7 +432,7 @@ __device__ __forceinline__ EventOut<RK> event_weight(const DevCfg& c, const doub
   const RK zero = RK(0.0);
   const double tq = c.dyn_scale ? q_position(half_ht<NG>(val(mt), top, atop, gl)) : 0.0;
   if constexpr (CH == 0) {
-    RK me = to_k(me_gg<NG, RA, RK>(E, gl, top, atop, mt, hg0, hgs), (RK*)nullptr);
+    RK me = to_k(me_gg<NG, RA, RK>(E, gl, top, atop, mt), (RK*)nullptr);
     RK r1 = pre * me;
     RK w = r1 * RK(pdf_at(c, pdf, 0, out.t1, tq) * pdf_at(c, pdf, 0, out.t2, tq));
     out.r1 = ok ? r1 : zero;

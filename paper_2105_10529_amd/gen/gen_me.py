@@ -276,12 +276,9 @@ def emit_me(m: int, with_cost: bool = False):
     w("//   Per-event invariants and propagator factors are formed in the kinematic")
     w("//   type RK (FP64) and only then converted to the amplitude type R, so that")
     w("//   denominators such as (p_t + k)^2 - m^2 = 2 p_t.k + k^2 never cancel in R.")
-    w("//   Only the gluon polarisation states hg0, hg0 + hgs, ... are summed (all")
-    w("//   of them by default), so that several lanes can share one event.")
     w("template <class R, class RK>")
     w(f"__device__ __forceinline__ R me_gg_m{m}(const V4<RK>* K, const V4<R> (*E)[2], const Sp<R>* UB,")
-    w("                                         const Sp<R>* VS, const V4<RK>& PTB, RK MTK, int hg0 = 0,")
-    w("                                         int hgs = 1) {")
+    w("                                         const Sp<R>* VS, const V4<RK>& PTB, RK MTK) {")
     w("  const R MT = cvt<R>(MTK);")
     subsets = [s for s in range(1, 1 << m)]
     for s_ in subsets:
@@ -309,7 +306,7 @@ def emit_me(m: int, with_cost: bool = False):
     w("  for (int ht = 0; ht < 2; ++ht) {")
     w("    const Sp<R> S_ = VS[ht];")
     w("#pragma unroll 1")
-    w(f"    for (int hg = hg0; hg < {1 << m}; hg += hgs) {{")
+    w(f"    for (int hg = 0; hg < {1 << m}; ++hg) {{")
     ind = "      "
     for i in range(m):
         w(f"{ind}const V4<R> J{i} = ((hg >> {m - 1 - i}) & 1) ? E[{i}][1] : E[{i}][0];")
@@ -432,8 +429,7 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings=Fal
     w("// the shared-current schedule).")
     w("template <class R, class RK>")
     w(f"__device__ __forceinline__ R me_gg_m{m}{suffix}(const V4<RK>* K, const V4<R> (*E)[2], const Sp<R>* UB,")
-    w("                                         const Sp<R>* VS, const V4<RK>& PTB, RK MTK, int hg0 = 0,")
-    w("                                         int hgs = 1) {")
+    w("                                         const Sp<R>* VS, const V4<RK>& PTB, RK MTK) {")
     w("  const R MT = cvt<R>(MTK);")
     subsets = list(range(1, 1 << m))
     full = (1 << m) - 1
@@ -462,7 +458,7 @@ def emit_me_per_ordering(m: int, share_antitop: bool = False, pair_orderings=Fal
     else:
         w("  {")
     w("#pragma unroll 1")
-    w(f"    for (int hg = hg0; hg < {1 << m}; hg += hgs) {{")
+    w(f"    for (int hg = 0; hg < {1 << m}; ++hg) {{")
     ind = "      "
     for i in range(m):
         w(f"{ind}const V4<R> E{i} = ((hg >> {m - 1 - i}) & 1) ? E[{i}][1] : E[{i}][0];")

@@ -70,23 +70,6 @@ def test_integrand_fp32_amplitudes_within_1e5(ng, n):
     assert_close(got, ref, 1e-5)
 
 
-@pytest.mark.parametrize("ng,precision,tol", [(1, "fp64", 1e-13), (2, "fp32", 4e-6), (2, "fp64", 1e-13)])
-def test_small_batches_share_events_between_lane_pairs(ng, precision, tol):
-    """mf_integrand batches of at most 131072 points give each g g event two
-    lanes, each summing every other gluon polarisation state; inside a larger
-    batch the same points are evaluated one lane per event.  The two agree up
-    to the order of the state sum (a sum of non-negative terms)."""
-    d = si.ndim(ng)
-    big = si.points_above_threshold(140_000, d, SQRT_S, MT, seed=400 + ng)
-    p = _proc(ng, precision)
-    full = p.integrand(to_dev_soa(big)).cpu().numpy()
-    assert np.count_nonzero(full) > 0.3 * len(full)
-    for a, b in ((0, 1), (0, 4097), (70_000, 70_000 + 65_536)):
-        part = p.integrand(to_dev_soa(big[a:b])).cpu().numpy()
-        assert_close(part, full[a:b], tol)
-        assert np.array_equal(part != 0, full[a:b] != 0)
-
-
 def test_empty_ragged_and_single_inputs():
     p = _proc(1)
     u = torch.empty((7, 0), dtype=torch.float64, device="cuda")
