@@ -128,9 +128,9 @@ def _load_kernels(process: str, precisions, helicity: int = 0) -> None:
 
 
 def learned_vs_vegas(process: str = "gg>ttxgg", precisions=("fp64", "fp32"), seeds=SEEDS,
-                     vegas_events: int = 10_000_000, flow_iter_events: int = 4_000_000, steps: int = 30,
+                     vegas_events: int = 10_000_000, flow_iter_events: int = 4_000_000, steps: int = 15,
                      batch: int = 65536, lr: float = 5e-3, helicity: int = 0, eval_events: int = 10_000_000,
-                     long_steps: int = 0) -> dict:
+                     long_steps: int = 60) -> dict:
     """Wall time from process creation to a combined relative error of 1e-3,
     per seed, for plain VEGAS in each precision (iterations of vegas_events,
     the grid adapting after each) and for FP32 amplitudes with the learned
