@@ -130,11 +130,11 @@ def _load_kernels(process: str, precisions, helicity: int = 0) -> None:
 def learned_vs_vegas(process: str = "gg>ttxgg", precisions=("fp64", "fp32"), seeds=SEEDS,
                      vegas_events: int = 10_000_000, flow_iter_events: int = 4_000_000, steps: int = 15,
                      batch: int = 65536, lr: float = 5e-3, helicity: int = 0, eval_events: int = 10_000_000,
-                     long_steps: int = 60) -> dict:
+                     long_steps: int = 60, warm_iters: int = 5, warm_events: int = 1_000_000) -> dict:
     """Wall time from process creation to a combined relative error of 1e-3,
     per seed, for plain VEGAS in each precision (iterations of vegas_events,
     the grid adapting after each) and for FP32 amplitudes with the learned
-    proposal: VEGAS warm-up 5 x 1e6, `steps` on-policy variance-training
+    proposal: VEGAS warm-up warm_iters x warm_events, `steps` on-policy variance-training
     steps of the flow (batch points per step from the flow mixed with 20%
     uniform points on the frozen grid; the batches are themselves unbiased
     estimates, pooled per 50 steps), then iterations of flow_iter_events
@@ -182,12 +182,12 @@ def learned_vs_vegas(process: str = "gg>ttxgg", precisions=("fp64", "fp32"), see
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         p = mf.Process(cfg("fp32", seed))
-        warm = p.integrate(5, 1_000_000, adapt=True)
+        warm = p.integrate(warm_iters, warm_events, adapt=True)
         torch.cuda.synchronize()
         t_warm = time.perf_counter() - t0
         # the VEGAS proposal's per-event relative variance on the frozen grid,
         # from the last warm-up iteration: (N - 1) sigma^2 / I^2
-        rv_vegas = (1_000_000 - 1) * warm.iter_error[-1] ** 2 / warm.iter_integral[-1] ** 2
+        rv_vegas = (warm_events - 1) * warm.iter_error[-1] ** 2 / warm.iter_integral[-1] ** 2
         f = mf.Flow(p.ndim, max_batch=batch, seed=seed)
         mix, group = 0.2, 50
         rel, est = p.train_flow_online(f, steps, batch=batch, lr=lr, loss="variance", flow_mix=mix,
