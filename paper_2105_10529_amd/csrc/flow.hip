@@ -61,6 +61,14 @@ struct LayerDev {
   const float* b2;   // [H]
   const bf16* W3t;   // [dB*NOP][H]  (W3 transposed, zero-padded outputs)
   const float* b3p;  // [dB*NOP]
+  // The coupling kernel's A fragments of the second layer and of the 64
+  // leading logits of the third, packed so that one wave's fragment load is
+  // 1 KB of consecutive bytes (64 lanes x 16 B) instead of 16 rows x 64 B:
+  //   W2p[((w * 8 + ks) * 4 + jt) * 64 + lane][8]:  W2t row 64 w + 16 jt + (lane & 15),
+  //                                                 k = 32 ks + 8 (lane >> 4) + e
+  //   W3p[((c * 4 + w) * 8 + ks) * 64 + lane][8]:  W3t row c NOP + 16 w + (lane & 15), same k
+  const bf16* W2p;   // [H][H]
+  const bf16* W3p;   // [dB][64][H]
 };
 
 // Training caches of one layer.  The activations are kept event-contiguous
@@ -427,12 +435,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = bias;
     }
-    const bf16* W2 = L.W2t + (64 * wave + row) * H + 8 * quad;
+    // this wave's fragments in packed order: step ks, fragment jt at
+    // ((wave 8 + ks) 4 + jt) KB
+    const bf16* W2 = L.W2p + (int64_t)wave * 8 * 4 * 512 + lane * 8;
 #pragma unroll
     for (int ks = 0; ks < H / 32; ++ks) {
       bf16x8 a[4], b[4];
 #pragma unroll
-      for (int jt = 0; jt < 4; ++jt) a[jt] = *reinterpret_cast<const bf16x8*>(W2 + 16 * jt * H + 32 * ks);
+      for (int jt = 0; jt < 4; ++jt) a[jt] = *reinterpret_cast<const bf16x8*>(W2 + (ks * 4 + jt) * 512);
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
         b[mt] = *reinterpret_cast<const bf16x8*>(h + hs(16 * mt + row, 32 * ks + 8 * quad));
@@ -476,9 +486,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
   // L2 latency overlaps it
   bf16x8 bw[H / 32];
   {
-    const bf16* W3 = L.W3t + ((int64_t)(16 * wave + row)) * H + 8 * quad;
+    const bf16* W3 = L.W3p + (int64_t)wave * 8 * 512 + lane * 8;
 #pragma unroll
-    for (int ks = 0; ks < H / 32; ++ks) bw[ks] = *reinterpret_cast<const bf16x8*>(W3 + 32 * ks);
+    for (int ks = 0; ks < H / 32; ++ks) bw[ks] = *reinterpret_cast<const bf16x8*>(W3 + ks * 512);
   }
   // the PQ transform's event (16 per wave, four lanes each) and part
   const int m = tid >> 2, part = tid & 3;
@@ -500,9 +510,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
         }
       }
       if (c + 1 < L.dB) {
-        const bf16* W3 = L.W3t + ((int64_t)(c + 1) * NOP + 16 * wave + row) * H + 8 * quad;
+        const bf16* W3 = L.W3p + (((int64_t)(c + 1) * 4 + wave) * 8) * 512 + lane * 8;
 #pragma unroll
-        for (int ks = 0; ks < H / 32; ++ks) bw[ks] = *reinterpret_cast<const bf16x8*>(W3 + 32 * ks);
+        for (int ks = 0; ks < H / 32; ++ks) bw[ks] = *reinterpret_cast<const bf16x8*>(W3 + ks * 512);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -939,6 +949,8 @@ struct SegLayer {
   bf16* W2t;
   bf16* W3t;
   float* b3p;
+  bf16* W2p;
+  bf16* W3p;
 };
 struct SegTable {
   int nl;
@@ -977,6 +989,9 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, floa
   if (r < nW2) {
     const int a = (int)(r / H), j = (int)(r % H);
     s.W2t[(int64_t)j * H + a] = (bf16)v;
+    // wave j >> 6, fragment (j >> 4) & 3, row j & 15
+    s.W2p[(((int64_t)(j >> 6) * 8 + (a >> 5)) * 4 + ((j >> 4) & 3)) * 512 + ((j & 15) + 16 * ((a >> 3) & 3)) * 8 +
+          (a & 7)] = (bf16)v;
     return;
   }
   r -= nW2 + H;
@@ -984,6 +999,11 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, floa
   if (r < H * nO) {
     const int a = (int)(r / nO), o = (int)(r % nO);
     s.W3t[((int64_t)(o / NO) * NOP + o % NO) * H + a] = (bf16)v;
+    const int c = o / NO, col = o % NO;
+    // coordinate c, wave col >> 4, row col & 15 (the 65th logit is read from W3t)
+    if (col < 64)
+      s.W3p[(((int64_t)c * 4 + (col >> 4)) * 8 + (a >> 5)) * 512 + ((col & 15) + 16 * ((a >> 3) & 3)) * 8 + (a & 7)] =
+          (bf16)v;
     return;
   }
   r -= H * nO;
@@ -1324,7 +1344,7 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     f->seg.l[l].dA = L.dA;
     f->seg.l[l].dB = L.dB;
     off += (int64_t)L.dA * H + H + (int64_t)H * H + H + (int64_t)H * L.dB * NO + L.dB * NO;
-    w16 += (int64_t)H * KA + (int64_t)H * H + (int64_t)L.dB * NOP * H;
+    w16 += (int64_t)H * KA + (int64_t)H * H + (int64_t)L.dB * NOP * H + (int64_t)H * H + (int64_t)L.dB * 64 * H;
     b3 += (int64_t)L.dB * NOP;
     if (L.dB > dBmax) dBmax = L.dB;
   }
@@ -1398,6 +1418,12 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     L.W3t = wp;
     f->seg.l[l].W3t = wp;
     wp += (int64_t)L.dB * NOP * H;
+    L.W2p = wp;
+    f->seg.l[l].W2p = wp;
+    wp += (int64_t)H * H;
+    L.W3p = wp;
+    f->seg.l[l].W3p = wp;
+    wp += (int64_t)L.dB * 64 * H;
     L.b3p = bp;
     f->seg.l[l].b3p = bp;
     bp += (int64_t)L.dB * NOP;
