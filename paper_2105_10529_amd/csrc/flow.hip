@@ -67,8 +67,12 @@ struct LayerDev {
   //   W2p[((w * 8 + ks) * 4 + jt) * 64 + lane][8]:  W2t row 64 w + 16 jt + (lane & 15),
   //                                                 k = 32 ks + 8 (lane >> 4) + e
   //   W3p[((c * 4 + w) * 8 + ks) * 64 + lane][8]:  W3t row c NOP + 16 w + (lane & 15), same k
+  //   W3L[ks * 64 + lane][8]:                    W3t row (lane & 15) NOP + 2K (the 65th
+  //                                                 logit of coordinate lane & 15; zero
+  //                                                 past d_B), same k
   const bf16* W2p;   // [H][H]
   const bf16* W3p;   // [dB][64][H]
+  const bf16* W3L;   // [16][H]
 };
 
 // Training caches of one layer.  The activations are kept event-contiguous
@@ -436,20 +440,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
       for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = bias;
     }
     // this wave's fragments in packed order: step ks, fragment jt at
-    // ((wave 8 + ks) 4 + jt) KB
+    // ((wave 8 + ks) 4 + jt) KB; a step's fragments are requested two steps
+    // ahead (a ring of three) and kept in their step by a scheduling barrier
     const bf16* W2 = L.W2p + (int64_t)wave * 8 * 4 * 512 + lane * 8;
+    bf16x8 a[3][4];
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) a[st][jt] = *reinterpret_cast<const bf16x8*>(W2 + (st * 4 + jt) * 512);
 #pragma unroll
     for (int ks = 0; ks < H / 32; ++ks) {
-      bf16x8 a[4], b[4];
+      if (ks + 2 < H / 32) {
 #pragma unroll
-      for (int jt = 0; jt < 4; ++jt) a[jt] = *reinterpret_cast<const bf16x8*>(W2 + (ks * 4 + jt) * 512);
+        for (int jt = 0; jt < 4; ++jt)
+          a[(ks + 2) % 3][jt] = *reinterpret_cast<const bf16x8*>(W2 + ((ks + 2) * 4 + jt) * 512);
+      }
+      bf16x8 b[4];
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
         b[mt] = *reinterpret_cast<const bf16x8*>(h + hs(16 * mt + row, 32 * ks + 8 * quad));
 #pragma unroll
       for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = mfma16(a[jt], b[mt], acc[jt][mt]);
+        for (int mt = 0; mt < 4; ++mt) acc[jt][mt] = mfma16(a[ks % 3][jt], b[mt], acc[jt][mt]);
+      __builtin_amdgcn_sched_barrier(0);
     }
     // every wave has read the first layer (and the cache copy is done)
     // before the second overwrites it
@@ -461,16 +475,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
 
   // The 65th logit of every transformed coordinate at once: one more MFMA
   // tile per wave, D[coordinate][event] for the wave's 16 events, with the
-  // weight rows of the coordinates' last outputs as A fragments (rows past
-  // d_B repeat coordinate 0 and are never read).  Lane l keeps coordinates
+  // weight rows of the coordinates' last outputs as A fragments (packed;
+  // rows past d_B are zero and never read).  Lane l keeps coordinates
   // 4 (l >> 4) + i of event 16 wave + (l & 15) in registers until their PQ
   // transforms.
   f32x4 lastv = {0.0f, 0.0f, 0.0f, 0.0f};
   {
-    const bf16* wl = L.W3t + ((int64_t)(row < L.dB ? row : 0) * NOP + 2 * KB) * H + 8 * quad;
+    const bf16* wl = L.W3L + lane * 8;
 #pragma unroll
     for (int ks = 0; ks < H / 32; ++ks) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(wl + 32 * ks);
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(wl + ks * 512);
       const bf16x8 b = *reinterpret_cast<const bf16x8*>(h + hs(16 * wave + row, 32 * ks + 8 * quad));
       lastv = mfma16(a, b, lastv);
     }
@@ -951,6 +965,7 @@ struct SegLayer {
   float* b3p;
   bf16* W2p;
   bf16* W3p;
+  bf16* W3L;
 };
 struct SegTable {
   int nl;
@@ -1000,10 +1015,12 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, floa
     const int a = (int)(r / nO), o = (int)(r % nO);
     s.W3t[((int64_t)(o / NO) * NOP + o % NO) * H + a] = (bf16)v;
     const int c = o / NO, col = o % NO;
-    // coordinate c, wave col >> 4, row col & 15 (the 65th logit is read from W3t)
+    // coordinate c, wave col >> 4, row col & 15; the 65th logit in row c of W3L
     if (col < 64)
       s.W3p[(((int64_t)c * 4 + (col >> 4)) * 8 + (a >> 5)) * 512 + ((col & 15) + 16 * ((a >> 3) & 3)) * 8 + (a & 7)] =
           (bf16)v;
+    else if (col == 2 * KB)
+      s.W3L[((a >> 5) * 64 + c + 16 * ((a >> 3) & 3)) * 8 + (a & 7)] = (bf16)v;
     return;
   }
   r -= H * nO;
@@ -1344,7 +1361,8 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     f->seg.l[l].dA = L.dA;
     f->seg.l[l].dB = L.dB;
     off += (int64_t)L.dA * H + H + (int64_t)H * H + H + (int64_t)H * L.dB * NO + L.dB * NO;
-    w16 += (int64_t)H * KA + (int64_t)H * H + (int64_t)L.dB * NOP * H + (int64_t)H * H + (int64_t)L.dB * 64 * H;
+    w16 += (int64_t)H * KA + (int64_t)H * H + (int64_t)L.dB * NOP * H + (int64_t)H * H + (int64_t)L.dB * 64 * H +
+           (int64_t)16 * H;
     b3 += (int64_t)L.dB * NOP;
     if (L.dB > dBmax) dBmax = L.dB;
   }
@@ -1424,6 +1442,9 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     L.W3p = wp;
     f->seg.l[l].W3p = wp;
     wp += (int64_t)L.dB * 64 * H;
+    L.W3L = wp;
+    f->seg.l[l].W3L = wp;
+    wp += (int64_t)16 * H;
     L.b3p = bp;
     f->seg.l[l].b3p = bp;
     bp += (int64_t)L.dB * NOP;
