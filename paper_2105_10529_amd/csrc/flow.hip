@@ -103,13 +103,19 @@ __device__ __forceinline__ float leaky(float v) { return __builtin_amdgcn_fmed3f
 
 // Exchanges inside an aligned group of four lanes through DPP quad
 // permutations (no LDS round trip): lane ^ 1, lane ^ 2, and the group's lane
-// 0, 1 or 2 broadcast to all four.
+// 0, 1 or 2 broadcast to all four.  A quad permutation reads a lane of the
+// same group for every lane, so no old value is needed.
 constexpr int QX1 = 0xB1, QX2 = 0x4E, QB0 = 0x00, QB1 = 0x55, QB2 = 0xAA;
 template <int CTRL> __device__ __forceinline__ float qdpp(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL> __device__ __forceinline__ int qdpp(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
+}
+// max(a, b) of finite values as the median of (a, b, FLT_MAX), without the
+// canonicalising instructions fmaxf adds in IEEE mode
+__device__ __forceinline__ float max_nc(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, 3.40282347e38f);
 }
 
 // ------------------------------------------------------------ PQ transform
@@ -219,29 +225,29 @@ __device__ __forceinline__ void pq_quad(const float* o, float vlast, float t, in
   float mw = w[0];
 #pragma unroll
   for (int k = 1; k < KP; ++k) mw = fmaxf(mw, w[k]);
-  mw = fmaxf(mw, qdpp<QX1>(mw));
-  mw = fmaxf(mw, qdpp<QX2>(mw));
+  mw = max_nc(mw, qdpp<QX1>(mw));
+  mw = max_nc(mw, qdpp<QX2>(mw));
   const float mwl = mw * L2E;
+  // the widths stay unnormalised (sum sw); the part's sum is its offset
   float sw = 0.0f;
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     w[k] = __builtin_amdgcn_exp2f(fmaf(w[k], L2E, -mwl));
     sw += w[k];
   }
+  const float part_w = sw;
   sw += qdpp<QX1>(sw);
   sw += qdpp<QX2>(sw);
-  const float isw = __builtin_amdgcn_rcpf(sw);
-#pragma unroll
-  for (int k = 0; k < KP; ++k) w[k] *= isw;
   float mv = v[0];
 #pragma unroll
   for (int k = 1; k <= KP; ++k) mv = fmaxf(mv, v[k]);
-  mv = fmaxf(mv, qdpp<QX1>(mv));
-  mv = fmaxf(mv, qdpp<QX2>(mv));
+  mv = max_nc(mv, qdpp<QX1>(mv));
+  mv = max_nc(mv, qdpp<QX2>(mv));
   const float mvl = mv * L2E;
 #pragma unroll
   for (int k = 0; k <= KP; ++k) v[k] = __builtin_amdgcn_exp2f(fmaf(v[k], L2E, -mvl));
-  // bin areas with the unnormalised heights, twice over: ar_k = (v_k + v_k+1) w_k
+  // bin areas with the unnormalised widths and heights, twice over:
+  // ar_k = (v_k + v_k+1) w_k, total nl
   float ar[KP];
   float nl = 0.0f;
 #pragma unroll
@@ -249,42 +255,45 @@ __device__ __forceinline__ void pq_quad(const float* o, float vlast, float t, in
     ar[k] = (v[k] + v[k + 1]) * w[k];
     nl += ar[k];
   }
-  const float part_area = nl;
+  const float part_a = nl;
   nl += qdpp<QX1>(nl);
   nl += qdpp<QX2>(nl);
-  // the heights are divided by the total area sum ar / 2; a bin's area is
-  // then ar_k / sum ar
+  // normalised: width w_k / sw, area ar_k / nl, height v_k 2 sw / nl (unit
+  // total area); the running edges are compared in unnormalised units
+  const float isw = __builtin_amdgcn_rcpf(sw);
   const float iar = __builtin_amdgcn_rcpf(nl);
-  const float inl = 2.0f * iar;
+  const float tt = t * (INVERSE ? nl : sw);
   // exclusive offsets of the running width and area at the part's first bin
-  float sp = 0.0f;
-#pragma unroll
-  for (int k = 0; k < KP; ++k) sp += w[k];
-  const float ap = part_area * iar;
-  const float s0 = qdpp<QB0>(sp), s1 = qdpp<QB1>(sp), s2 = qdpp<QB2>(sp);
-  const float a0 = qdpp<QB0>(ap), a1 = qdpp<QB1>(ap), a2 = qdpp<QB2>(ap);
+  const float s0 = qdpp<QB0>(part_w), s1 = qdpp<QB1>(part_w), s2 = qdpp<QB2>(part_w);
+  const float a0 = qdpp<QB0>(part_a), a1 = qdpp<QB1>(part_a), a2 = qdpp<QB2>(part_a);
   float S = (p > 0 ? s0 : 0.0f) + (p > 1 ? s1 : 0.0f) + (p > 2 ? s2 : 0.0f);
   float A = (p > 0 ? a0 : 0.0f) + (p > 1 ? a1 : 0.0f) + (p > 2 ? a2 : 0.0f);
-  int bl = -1;
-  float Sb = 0.0f, Ab = 0.0f, Wb = w[0], Vb = v[0], Vb1 = v[1];
+  // the edges grow with the bin index, so bin b is owned by the last lane
+  // of the group whose first bin is taken
+  const bool first = p == 0 || (INVERSE ? A : S) <= tt;
+  int owner = first ? p : -1;
+  float Sb = S, Ab = A, Wb = w[0], Vb = v[0], Vb1 = v[1];
+  S += w[0];
+  A += ar[0];
 #pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int kg = KP * p + k;
-    const bool take = kg == 0 || (INVERSE ? A : S) <= t;
-    bl = take ? kg : bl;
+  for (int k = 1; k < KP; ++k) {
+    const bool take = (INVERSE ? A : S) <= tt;
     Sb = take ? S : Sb;
     Ab = take ? A : Ab;
     Wb = take ? w[k] : Wb;
     Vb = take ? v[k] : Vb;
     Vb1 = take ? v[k + 1] : Vb1;
     S += w[k];
-    A += ar[k] * iar;
+    A += ar[k];
   }
-  Vb *= inl;
-  Vb1 *= inl;
-  int b = bl;
-  b = max(b, qdpp<QX1>(b));
-  b = max(b, qdpp<QX2>(b));
+  owner = max(owner, qdpp<QX1>(owner));
+  owner = max(owner, qdpp<QX2>(owner));
+  Sb *= isw;
+  Ab *= iar;
+  Wb *= isw;
+  const float hn = 2.0f * sw * iar;
+  Vb *= hn;
+  Vb1 *= hn;
   const float dV = Vb1 - Vb;
   const float iW = __builtin_amdgcn_rcpf(Wb);
   float r, q;
@@ -295,14 +304,15 @@ __device__ __forceinline__ void pq_quad(const float* o, float vlast, float t, in
   } else {
     const float cc = (t - Ab) * iW;
     const float disc = fmaxf(Vb * Vb + 2.0f * dV * cc, 0.0f);
-    float al = 2.0f * cc * __builtin_amdgcn_rcpf(Vb + sqrtf(disc));
+    // hardware square root (1 ulp)
+    float al = 2.0f * cc * __builtin_amdgcn_rcpf(Vb + __builtin_amdgcn_sqrtf(disc));
     al = fminf(fmaxf(al, 0.0f), 1.0f);
     r = Sb + al * Wb;
     q = Vb + al * dV;
   }
   // only the owner of bin b holds the right values: a sum over the group
   // with the other three lanes contributing exact zeros
-  const bool own = b / KP == p;
+  const bool own = owner == p;
   float rr = own ? r : 0.0f, qq = own ? q : 0.0f;
   rr += qdpp<QX1>(rr);
   qq += qdpp<QX1>(qq);
