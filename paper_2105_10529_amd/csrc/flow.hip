@@ -360,7 +360,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CACHE 
   __shared__ float tb[TBMAX * T];
   static_assert(T * KA * sizeof(bf16) <= T * LDO * sizeof(float), "first-layer inputs must fit the logit tile");
   bf16* xa = reinterpret_cast<bf16*>(out);  // [T][KA]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform across the wave: held in a scalar register, the
+  // per-wave weight and index addresses are scalar arithmetic
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t e0 = (int64_t)blockIdx.x * T;
   const int row = lane & 15, quad = lane >> 4;
 
