@@ -724,8 +724,23 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) bf16 Bs[2][64 * GLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int row = lane & 15, quad = lane >> 4;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
+  // XCD-aware tile order: workgroup b runs on XCD b mod 8, so the tiles are
+  // numbered XCD by XCD; consecutive tiles (the column tiles of one row
+  // tile, the tiles of one event chunk) then share an XCD and its L2, and
+  // their common operand rows are read from HBM once
+  int tx, ty, tz;
+  {
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int G = gx * gy * gridDim.z;
+    const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int xcd = b & 7, slot = b >> 3, per = G >> 3, rem = G & 7;
+    const int t = xcd * per + (xcd < rem ? xcd : rem) + slot;
+    tx = t % gx;
+    ty = (t / gx) % gy;
+    tz = t / (gx * gy);
+  }
+  const int m0 = ty * 64, n0 = tx * 64;
+  const int64_t kb = (int64_t)tz * g.kchunk;
   const int64_t ke = kb + g.kchunk < g.K ? kb + g.kchunk : g.K;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   f32x4 acc[2][2];
@@ -734,7 +749,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   f32x4 accs[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
-  const bool sums = EPI == 0 && g.colsum && blockIdx.y == 0 && wm == 0;
+  const bool sums = EPI == 0 && g.colsum && ty == 0 && wm == 0;
   bf16x8 ones;
 #pragma unroll
   for (int i = 0; i < 8; ++i) ones[i] = (bf16)1.0f;
@@ -826,7 +841,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int gn = n0 + wn + 16 * j + row;
-      if (gn < g.N) g.Cf[(int64_t)blockIdx.z * g.zs + (int64_t)g.M * g.ldc + gn] = accs[j][0];
+      if (gn < g.N) g.Cf[(int64_t)tz * g.zs + (int64_t)g.M * g.ldc + gn] = accs[j][0];
     }
   }
 #pragma unroll
@@ -840,7 +855,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       if (EPI == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (gm0 + r < g.M) g.Cf[(int64_t)blockIdx.z * g.zs + (int64_t)(gm0 + r) * g.ldc + gn] = acc[i][j][r];
+          if (gm0 + r < g.M) g.Cf[(int64_t)tz * g.zs + (int64_t)(gm0 + r) * g.ldc + gn] = acc[i][j][r];
       } else {
         // the four sign references of rows gm0..gm0+3 (event-contiguous when
         // ref_rs == 1: one 8-byte load)
