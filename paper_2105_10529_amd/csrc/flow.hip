@@ -718,7 +718,7 @@ constexpr int GLD = GK + 8;   // LDS row stride (bf16) of a staged slice
 // buffered: the next slice's global loads are issued into registers before
 // the current slice's products, and each slice costs one barrier.
 template <int A_KC, int B_NC, int EPI>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gemm(GemmArgs g) {
   static_assert(A_KC == 1, "A is staged from k-contiguous rows");
   __shared__ __attribute__((aligned(16))) bf16 As[2][64 * GLD];
   __shared__ __attribute__((aligned(16))) bf16 Bs[2][64 * GLD];
@@ -754,53 +754,51 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) ones[i] = (bf16)1.0f;
   // this thread's share of a slice: rows (or k) r0 and r0 + 32, eight
-  // consecutive elements from c8 (16-byte loads where the eight elements are
-  // in range; the caller guarantees 16-byte aligned rows: base and leading
-  // dimension multiples of 8 elements)
+  // consecutive elements from c8, one 16-byte load each.  The loads have no
+  // branches (so that the waits for a slice do not wait for the next one):
+  // rows and chunks outside the operand read an in-range chunk instead, and
+  // the number of valid elements of each chunk (0-8) zeroes the rest when
+  // the slice is stored.  The caller guarantees 16-byte aligned rows: base
+  // and leading dimension multiples of 8 elements, so a chunk that starts
+  // inside a row ends inside it.
   const int r0 = tid >> 3, c8 = (tid & 7) * 8;
-  bf16x8 ra[2], rb[2];
-  auto load = [&](int64_t k0) {
+  // two register stages: the slices k + 1 and k + 2 are in flight while
+  // slice k is multiplied
+  bf16x8 ra0[2], rb0[2], ra1[2], rb1[2];
+  // valid elements of this thread's A and B chunks h of the slice at k0
+  auto nvalid = [](int64_t lim, int64_t j) -> int {
+    const int64_t r = lim - j;
+    return r <= 0 ? 0 : (r >= 8 ? 8 : (int)r);
+  };
+  auto va = [&](int64_t k0, int h) -> int { return m0 + r0 + 32 * h < g.M ? nvalid(ke, k0 + c8) : 0; };
+  auto vb = [&](int64_t k0, int h) -> int {
+    if (B_NC) return k0 + r0 + 32 * h < ke ? nvalid(g.N, n0 + c8) : 0;
+    return n0 + r0 + 32 * h < g.N ? nvalid(ke, k0 + c8) : 0;
+  };
+  auto load = [&](int64_t k0, bf16x8 (&ra)[2], bf16x8 (&rb)[2]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int gm = m0 + r0 + 32 * h;
-      if (gm < g.M && k0 + c8 + 8 <= ke) {
-        ra[h] = *reinterpret_cast<const bf16x8*>(g.A + (int64_t)gm * g.lda + k0 + c8);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int64_t gk = k0 + c8 + i;
-          ra[h][i] = (gm < g.M && gk < ke) ? g.A[(int64_t)gm * g.lda + gk] : (bf16)0.0f;
-        }
-      }
+      ra[h] = *reinterpret_cast<const bf16x8*>(g.A + (int64_t)(gm < g.M ? gm : 0) * g.lda + (va(k0, h) > 0 ? k0 + c8 : kb));
       if (B_NC) {
         const int64_t gk = k0 + r0 + 32 * h;
-        if (gk < ke && n0 + c8 + 8 <= g.N) {
-          rb[h] = *reinterpret_cast<const bf16x8*>(g.B + gk * g.ldb + n0 + c8);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int gn = n0 + c8 + i;
-            rb[h][i] = (gn < g.N && gk < ke) ? g.B[gk * g.ldb + gn] : (bf16)0.0f;
-          }
-        }
+        rb[h] = *reinterpret_cast<const bf16x8*>(g.B + (gk < ke ? gk : kb) * g.ldb + (vb(k0, h) > 0 ? n0 + c8 : 0));
       } else {
         const int gn = n0 + r0 + 32 * h;
-        if (gn < g.N && k0 + c8 + 8 <= ke) {
-          rb[h] = *reinterpret_cast<const bf16x8*>(g.B + (int64_t)gn * g.ldb + k0 + c8);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int64_t gk = k0 + c8 + i;
-            rb[h][i] = (gn < g.N && gk < ke) ? g.B[(int64_t)gn * g.ldb + gk] : (bf16)0.0f;
-          }
-        }
+        rb[h] = *reinterpret_cast<const bf16x8*>(g.B + (int64_t)(gn < g.N ? gn : 0) * g.ldb + (vb(k0, h) > 0 ? k0 + c8 : kb));
       }
     }
   };
   // A rows m-major, B rows n-major in LDS, each row GK consecutive k
-  auto store = [&](int buf) {
+  auto store = [&](int buf, bf16x8 (&ra)[2], bf16x8 (&rb)[2], int64_t k0) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+      const int na = va(k0, h), nb = vb(k0, h);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        ra[h][i] = i < na ? ra[h][i] : (bf16)0.0f;
+        rb[h][i] = i < nb ? rb[h][i] : (bf16)0.0f;
+      }
       *reinterpret_cast<bf16x8*>(&As[buf][(r0 + 32 * h) * GLD + c8]) = ra[h];
       if (B_NC) {
 #pragma unroll
@@ -810,14 +808,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       }
     }
   };
-  load(kb);
-  int buf = 0;
-  for (int64_t k0 = kb; k0 < ke; k0 += GK, buf ^= 1) {
-    // the buffer written here was last read two slices ago, before the
-    // previous slice's barrier
-    store(buf);
-    __syncthreads();
-    if (k0 + GK < ke) load(k0 + GK);
+  auto products = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 32) {
       bf16x8 a[2], b[2];
@@ -836,6 +827,30 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         for (int j = 0; j < 2; ++j) accs[j] = mfma16(ones, b[j], accs[j]);
       }
     }
+  };
+  // slices alternate between the register stages and the LDS buffers; the
+  // buffer written for a slice was last read two slices before, ahead of the
+  // previous slice's barrier.  Each iteration takes two slices and issues the
+  // loads of the two after them (empty past the chunk, reading its first
+  // columns), so that every iteration has the same loads in flight; an odd
+  // last slice follows the loop.
+  load(kb, ra0, rb0);
+  load(kb + GK, ra1, rb1);
+  int64_t k0 = kb;
+  for (; k0 + GK < ke; k0 += 2 * GK) {
+    store(0, ra0, rb0, k0);
+    __syncthreads();
+    load(k0 + 2 * GK, ra0, rb0);
+    products(0);
+    store(1, ra1, rb1, k0 + GK);
+    __syncthreads();
+    load(k0 + 3 * GK, ra1, rb1);
+    products(1);
+  }
+  if (k0 < ke) {
+    store(0, ra0, rb0, k0);
+    __syncthreads();
+    products(0);
   }
   if (sums && quad == 0) {
 #pragma unroll
