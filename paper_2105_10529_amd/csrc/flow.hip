@@ -57,22 +57,26 @@ struct LayerDev {
   int b_idx[FMAXD];
   const bf16* W1t;   // [H][KA]      (W1 transposed, at k = i and k = KLO + i)
   const float* b1;   // [H]
-  const bf16* W2t;   // [H][H]       (W2 transposed)
   const float* b2;   // [H]
-  const bf16* W3t;   // [dB*NOP][H]  (W3 transposed, zero-padded outputs)
   const float* b3p;  // [dB*NOP]
   // The coupling kernel's A fragments of the second layer and of the 64
   // leading logits of the third, packed so that one wave's fragment load is
-  // 1 KB of consecutive bytes (64 lanes x 16 B) instead of 16 rows x 64 B:
-  //   W2p[((w * 8 + ks) * 4 + jt) * 64 + lane][8]:  W2t row 64 w + 16 jt + (lane & 15),
+  // 1 KB of consecutive bytes (64 lanes x 16 B) instead of 16 rows x 64 B;
+  // element (k, j) is W[k][j] (input k, output j; the outputs of W3 padded
+  // to NOP per coordinate):
+  //   W2p[((w * 8 + ks) * 4 + jt) * 64 + lane][8]:  output j = 64 w + 16 jt + (lane & 15),
   //                                                 k = 32 ks + 8 (lane >> 4) + e
-  //   W3p[((c * 4 + w) * 8 + ks) * 64 + lane][8]:  W3t row c NOP + 16 w + (lane & 15), same k
-  //   W3L[ks * 64 + lane][8]:                    W3t row (lane & 15) NOP + 2K (the 65th
+  //   W3p[((c * 4 + w) * 8 + ks) * 64 + lane][8]:  output c NOP + 16 w + (lane & 15), same k
+  //   W3L[ks * 64 + lane][8]:                    output (lane & 15) NOP + 2K (the 65th
   //                                                 logit of coordinate lane & 15; zero
   //                                                 past d_B), same k
   const bf16* W2p;   // [H][H]
   const bf16* W3p;   // [dB][64][H]
   const bf16* W3L;   // [16][H]
+  // The backward products' B operands with k contiguous: W2 [in][out] and
+  // W3 [in][dB*NOP] in their own orientation (zero-padded outputs)
+  const bf16* W2n;   // [H][H]
+  const bf16* W3n;   // [H][dB*NOP]
 };
 
 // Training caches of one layer.  The activations are kept event-contiguous
@@ -1002,12 +1006,12 @@ struct SegLayer {
   int64_t off;  // start of the layer in the master array
   int dA, dB;
   bf16* W1t;
-  bf16* W2t;
-  bf16* W3t;
   float* b3p;
   bf16* W2p;
   bf16* W3p;
   bf16* W3L;
+  bf16* W2n;
+  bf16* W3n;
 };
 struct SegTable {
   int nl;
@@ -1045,7 +1049,7 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, floa
   if (r < 0) return;
   if (r < nW2) {
     const int a = (int)(r / H), j = (int)(r % H);
-    s.W2t[(int64_t)j * H + a] = (bf16)v;
+    s.W2n[r] = (bf16)v;
     // wave j >> 6, fragment (j >> 4) & 3, row j & 15
     s.W2p[(((int64_t)(j >> 6) * 8 + (a >> 5)) * 4 + ((j >> 4) & 3)) * 512 + ((j & 15) + 16 * ((a >> 3) & 3)) * 8 +
           (a & 7)] = (bf16)v;
@@ -1055,7 +1059,7 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, floa
   if (r < 0) return;
   if (r < H * nO) {
     const int a = (int)(r / nO), o = (int)(r % nO);
-    s.W3t[((int64_t)(o / NO) * NOP + o % NO) * H + a] = (bf16)v;
+    s.W3n[(int64_t)a * s.dB * NOP + (o / NO) * NOP + o % NO] = (bf16)v;
     const int c = o / NO, col = o % NO;
     // coordinate c, wave col >> 4, row col & 15; the 65th logit in row c of W3L
     if (col < 64)
@@ -1282,12 +1286,12 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     if (!weight_grad(f, C.h2, ldn, H, H, f->d_goT, NB, NOP, NO, n, gW3, nO, gb3, s2))
       return set_error(MF_EINVAL, "weight-gradient partials exceed the flow's buffer");
     rec(E_W3, s2);
-    // ga2 = (go W3^T) * leaky'(h2): A = go [n][NB], B(k=o, n=j) = W3t[o][j]
+    // ga2 = (go W3^T) * leaky'(h2): A = go [n][NB], B(k=o, n=j) = W3n[j][o]
     GemmArgs a{};
     a.A = f->d_go;
     a.lda = NB;
-    a.B = L.W3t;
-    a.ldb = H;
+    a.B = L.W3n;
+    a.ldb = NB;
     a.M = (int)n;
     a.N = H;
     a.K = NB;
@@ -1300,16 +1304,16 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     a.ref_cs = ldn;
     a.ldc = H;
     if (later) wait(E_W2, s);
-    gemm<1, 1, 1>(a, 1, s);
+    gemm<1, 0, 1>(a, 1, s);
     rec(E_GA2, s);
     wait(E_GA2, s2);
     if (!weight_grad(f, C.h1, ldn, H, H, f->d_ga2T, H, 0, 0, n, gW2, H, gb2, s2))
       return set_error(MF_EINVAL, "weight-gradient partials exceed the flow's buffer");
     rec(E_W2, s2);
-    // ga1 = (ga2 W2^T) * leaky'(h1): B(k=j2, n=j1) = W2[j1][j2] = W2t[j2][j1]
+    // ga1 = (ga2 W2^T) * leaky'(h1): B(k=j2, n=j1) = W2[j1][j2] = W2n[j1][j2]
     a.A = f->d_ga2;
     a.lda = H;
-    a.B = L.W2t;
+    a.B = L.W2n;
     a.ldb = H;
     a.K = H;
     a.kchunk = H;
@@ -1317,7 +1321,7 @@ mf_status loss_grad_impl(mf_flow* f, const float* y, int64_t ldy, const float* w
     a.CbT = f->d_ga1T;
     a.ref = C.h1;
     if (later) wait(E_W1, s);
-    gemm<1, 1, 1>(a, 1, s);
+    gemm<1, 0, 1>(a, 1, s);
     rec(E_GA1, s);
     wait(E_GA1, s2);
     if (!weight_grad(f, C.xa, ldn, KA, L.dA, f->d_ga1T, H, 0, 0, n, gW1, H, gb1, s2, KLO))
@@ -1403,8 +1407,8 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     f->seg.l[l].dA = L.dA;
     f->seg.l[l].dB = L.dB;
     off += (int64_t)L.dA * H + H + (int64_t)H * H + H + (int64_t)H * L.dB * NO + L.dB * NO;
-    w16 += (int64_t)H * KA + (int64_t)H * H + (int64_t)L.dB * NOP * H + (int64_t)H * H + (int64_t)L.dB * 64 * H +
-           (int64_t)16 * H;
+    w16 += (int64_t)H * KA + (int64_t)H * H + (int64_t)L.dB * 64 * H + (int64_t)16 * H + (int64_t)H * H +
+           (int64_t)H * L.dB * NOP;
     b3 += (int64_t)L.dB * NOP;
     if (L.dB > dBmax) dBmax = L.dB;
   }
@@ -1472,12 +1476,6 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     L.W1t = wp;
     f->seg.l[l].W1t = wp;
     wp += (int64_t)H * KA;
-    L.W2t = wp;
-    f->seg.l[l].W2t = wp;
-    wp += (int64_t)H * H;
-    L.W3t = wp;
-    f->seg.l[l].W3t = wp;
-    wp += (int64_t)L.dB * NOP * H;
     L.W2p = wp;
     f->seg.l[l].W2p = wp;
     wp += (int64_t)H * H;
@@ -1487,6 +1485,12 @@ mf_status mf_flow_create(const mf_flow_config* cfg, mf_flow** out) {
     L.W3L = wp;
     f->seg.l[l].W3L = wp;
     wp += (int64_t)16 * H;
+    L.W2n = wp;
+    f->seg.l[l].W2n = wp;
+    wp += (int64_t)H * H;
+    L.W3n = wp;
+    f->seg.l[l].W3n = wp;
+    wp += (int64_t)H * L.dB * NOP;
     L.b3p = bp;
     f->seg.l[l].b3p = bp;
     bp += (int64_t)L.dB * NOP;
