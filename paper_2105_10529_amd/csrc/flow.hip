@@ -693,8 +693,10 @@ __global__ void __launch_bounds__(256) k_pq_backward(LayerDev L, LayerCache C, i
 //          colsum set, row M of the partial receives the column sums of B
 //          over the chunk (one more MFMA per k-step with an all-ones A
 //          fragment in the first row of blocks)
-//   EPI 1: BF16 store to Cb[m ldc + n] of acc * (ref[m ref_rs + n ref_cs] > 0 ? 1 : slope),
-//          and of the same values to CbT[n ldt + m] (event-contiguous copy)
+//   EPI 1: BF16 store to Cb[m ldc + n] of acc * (ref[m + n ref_cs] > 0 ? 1 : slope),
+//          and of the same values to CbT[n ldt + m] (event-contiguous copy);
+//          the references are event-contiguous (ref_rs = 1), and Cb, CbT and
+//          ref rows are 16-byte aligned
 struct GemmArgs {
   const bf16* A;
   int64_t lda;
@@ -724,8 +726,11 @@ constexpr int GLD = GK + 8;   // LDS row stride (bf16) of a staged slice
 template <int A_KC, int B_NC, int EPI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gemm(GemmArgs g) {
   static_assert(A_KC == 1, "A is staged from k-contiguous rows");
-  __shared__ __attribute__((aligned(16))) bf16 As[2][64 * GLD];
-  __shared__ __attribute__((aligned(16))) bf16 Bs[2][64 * GLD];
+  // the two double-buffered slices; after the k loop the same memory holds
+  // the FP32 output tile of the BF16 epilogue
+  __shared__ __attribute__((aligned(16))) bf16 smem[4 * 64 * GLD];
+  bf16(*As)[64 * GLD] = reinterpret_cast<bf16(*)[64 * GLD]>(smem);
+  bf16(*Bs)[64 * GLD] = reinterpret_cast<bf16(*)[64 * GLD]>(smem + 2 * 64 * GLD);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int row = lane & 15, quad = lane >> 4;
   // XCD-aware tile order: workgroup b runs on XCD b mod 8, so the tiles are
@@ -863,45 +868,80 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       if (gn < g.N) g.Cf[(int64_t)tz * g.zs + (int64_t)g.M * g.ldc + gn] = accs[j][0];
     }
   }
+  if (EPI == 0) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int gn = n0 + wn + 16 * j + row;
-      if (gn >= g.N) continue;
-      const int gm0 = m0 + wm + 16 * i + 4 * quad;
-      if (gm0 >= g.M) continue;
-      if (EPI == 0) {
+      for (int j = 0; j < 2; ++j) {
+        const int gn = n0 + wn + 16 * j + row;
+        if (gn >= g.N) continue;
+        const int gm0 = m0 + wm + 16 * i + 4 * quad;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           if (gm0 + r < g.M) g.Cf[(int64_t)tz * g.zs + (int64_t)(gm0 + r) * g.ldc + gn] = acc[i][j][r];
+      }
+  } else {
+    // The tile goes through LDS (FP32, row stride LDT: the fragment stores
+    // at most two-way bank conflicts, the column reads none), so that the
+    // sign references are read and both BF16 copies written with 16-byte
+    // accesses: first eight consecutive events of one feature per thread
+    // (references, scaling, the event-contiguous copy; the rounded values go
+    // back to the tile), then eight consecutive features of one event (the
+    // row-major copy).  The references are event-contiguous (ref_rs = 1).
+    constexpr int LDT = 73;
+    static_assert(64 * LDT * sizeof(float) <= sizeof(smem), "the output tile must fit the slice buffers");
+    float* Ts = reinterpret_cast<float*>(smem);
+    __syncthreads();  // every wave is done with the slices
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Ts[(wm + 16 * i + 4 * quad + r) * LDT + wn + 16 * j + row] = acc[i][j][r];
+    __syncthreads();
+    for (int q = tid; q < 64 * 8; q += 256) {
+      const int c = q & 7, nn = q >> 3;
+      const int gm = m0 + 8 * c, gn = n0 + nn;
+      if (gm >= g.M || gn >= g.N) continue;
+      const bool full = gm + 8 <= g.M;
+      const bf16* rp = g.ref + (int64_t)gn * g.ref_cs + gm;
+      bf16x8 rv;
+      if (full) {
+        rv = *reinterpret_cast<const bf16x8*>(rp);
       } else {
-        // the four sign references of rows gm0..gm0+3 (event-contiguous when
-        // ref_rs == 1: one 8-byte load)
-        bf16x4 rv;
-        if (g.ref_rs == 1 && gm0 + 4 <= g.M) {
-          rv = *reinterpret_cast<const bf16x4*>(g.ref + (int64_t)gn * g.ref_cs + gm0);
-        } else {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int gm = gm0 + r < g.M ? gm0 + r : gm0;
-            rv[r] = g.ref[(int64_t)gm * g.ref_rs + (int64_t)gn * g.ref_cs];
-          }
-        }
-        bf16x4 t;
+        for (int e = 0; e < 8; ++e) rv[e] = gm + e < g.M ? rp[e] : (bf16)0.0f;
+      }
+      bf16x8 t;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float s = (float)rv[r] > 0.0f ? 1.0f : SLOPE;
-          t[r] = (bf16)(acc[i][j][r] * s);
-          if (gm0 + r < g.M) g.Cb[(int64_t)(gm0 + r) * g.ldc + gn] = t[r];
-        }
-        if (gm0 + 4 <= g.M) {
-          *reinterpret_cast<bf16x4*>(g.CbT + (int64_t)gn * g.ldt + gm0) = t;
-        } else {
-          for (int r = 0; gm0 + r < g.M; ++r) g.CbT[(int64_t)gn * g.ldt + gm0 + r] = t[r];
-        }
+      for (int e = 0; e < 8; ++e) {
+        float* tp = Ts + (8 * c + e) * LDT + nn;
+        t[e] = (bf16)(*tp * ((float)rv[e] > 0.0f ? 1.0f : SLOPE));
+        *tp = (float)t[e];
+      }
+      bf16* dp = g.CbT + (int64_t)gn * g.ldt + gm;
+      if (full) {
+        *reinterpret_cast<bf16x8*>(dp) = t;
+      } else {
+        for (int e = 0; gm + e < g.M; ++e) dp[e] = t[e];
       }
     }
+    __syncthreads();
+    for (int q = tid; q < 64 * 8; q += 256) {
+      const int k = q & 7, mm = q >> 3;
+      const int gm = m0 + mm, gn = n0 + 8 * k;
+      if (gm >= g.M || gn >= g.N) continue;
+      bf16x8 t;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) t[e] = (bf16)Ts[mm * LDT + 8 * k + e];
+      bf16* dp = g.Cb + (int64_t)gm * g.ldc + gn;
+      if (gn + 8 <= g.N) {
+        *reinterpret_cast<bf16x8*>(dp) = t;
+      } else {
+        for (int e = 0; gn + e < g.N; ++e) dp[e] = t[e];
+      }
+    }
+  }
 }
 
 // out[m ldo + map(n)] = sum_z part[z][m][n] (+ part[z][m + fold][n] when
