@@ -165,23 +165,34 @@ __device__ __forceinline__ V4<R> boost_from_rest(const V4<R>& p, const V4<R>& Q,
   return V4<R>{e, p.x + c * Q.x, p.y + c * Q.y, p.z + c * Q.z};
 }
 
+// v^k for a small non-negative integer k, by multiplication (the exponents
+// here are at most the number of final-state bodies)
+__device__ __forceinline__ double ipow(double v, int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= v;
+  return r;
+}
+
 // Solve (N-1) v^(N-2) - (N-2) v^(N-1) = r on [0,1] (the distribution of
 // v = M_i^2/M_{i-1}^2 for N massless bodies): closed form for N = 3,
-// otherwise bisection to 2^-40 then safeguarded Newton steps.
+// otherwise bisection to 2^-40 then safeguarded Newton steps.  The
+// polynomial is evaluated as v^(N-3) (v ((N-1) - (N-2) v)) with integer
+// powers.
 __device__ __forceinline__ double solve_mass_ratio(int N, double r) {
   if (N == 3) return r / (1.0 + sqrt(1.0 - r));
   double lo = 0.0, hi = 1.0;
   const double a = N - 1, b = N - 2;
   for (int it = 0; it < 40; ++it) {
-    double mid = 0.5 * (lo + hi);
-    double F = a * pow(mid, N - 2) - b * pow(mid, N - 1);
+    const double mid = 0.5 * (lo + hi);
+    const double F = ipow(mid, N - 2) * (a - b * mid);
     if (F < r) lo = mid; else hi = mid;
   }
   double v = 0.5 * (lo + hi);
   for (int it = 0; it < 4; ++it) {
-    double F = a * pow(v, N - 2) - b * pow(v, N - 1) - r;
-    double dF = a * b * pow(v, N - 3) * (1.0 - v);
-    double nv = dF > 0.0 ? v - F / dF : v;
+    const double p3 = ipow(v, N - 3);
+    const double F = p3 * v * (a - b * v) - r;
+    const double dF = a * b * p3 * (1.0 - v);
+    const double nv = dF > 0.0 ? v - F / dF : v;
     v = (nv > lo && nv < hi) ? nv : v;
   }
   return v;
@@ -233,7 +244,7 @@ __device__ __forceinline__ R phase_space(int ng, const double* x, double shat, R
   top = boost_from_rest(t, QR, Mtt);
   atop = boost_from_rest(tb, QR, Mtt);
   // massless volume V_n(s) = (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!)
-  double vol = pow(2.0 * M_PI, 4.0 - 3.0 * n) * pow(0.5 * M_PI, n - 1.0) * pow(shat, n - 2.0);
+  double vol = pow(2.0 * M_PI, 4.0 - 3.0 * n) * pow(0.5 * M_PI, n - 1.0) * ipow(shat, n - 2);
   double fact = 1.0;
   for (int k = 2; k <= n - 1; ++k) fact *= k;
   double fact2 = 1.0;
