@@ -47,10 +47,10 @@ TARGET = 1e-3
 # calibration (profiles/traffic_k_vegas_gg_ttgg_fp32_1e8.md); the same in
 # every iteration measured, so the traffic of a launch is this times its kept
 # events.
-TTGG_TRAFFIC_BYTES_PER_KEPT_EVENT = 1398.0
+TTGG_TRAFFIC_BYTES_PER_KEPT_EVENT = 1071.0
 # the same for k_select<1> + k_vegas<1,0,double> at 1e7 events
 # (profiles/traffic_k_vegas_gg_ttg_fp64_1e7.md)
-TTG_TRAFFIC_BYTES = 83.1e6
+TTG_TRAFFIC_BYTES = 52.7e6
 
 
 def flops_per_event(m: int) -> int:
@@ -739,8 +739,8 @@ def main() -> int:
             "peak_unpacked": FP32_UNPACKED_PEAK / 1e12,
             "frac_unpacked": achieved / FP32_UNPACKED_PEAK,
             "traffic": TTGG_TRAFFIC_BYTES_PER_KEPT_EVENT * passing if args.events == HEADLINE_EVENTS else None,
-            "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE (copy-calibrated), 1398 B per kept "
-                            "event: mostly the fused kernel's register spill; 0.12 TB/s, not the bound",
+            "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE (copy-calibrated), 1071 B per kept "
+                            "event: mostly the fused kernel's register spill; 0.1 TB/s, not the bound",
             "kernel": "k_select<2> + k_vegas<2,0,float> (cut selection, then the fused weight of the kept events)",
             "flops_per_event": fpe,
             "flops_per": "event that passes the cuts (the matrix element is evaluated for those only)",
